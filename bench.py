@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the separated SU(2) Fourier transform on one MI355X.
+
+Workload: bandlimit B = 64 (128^3 Euler grid), batch of 32 signals, inputs from
+seeded complex Gaussian bandlimited coefficients with variance (2l+1)^-2
+(the samples are synthesised from them once, before timing).  One step runs
+the whole transform chain on the batch: forward (ring FFT + beta contraction),
+inverse (beta synthesis + inverse ring FFT) and adjoint (the same two kernels
+with the quadrature weights), i.e. 3 x 32 single-signal transforms.
+
+Printed: one JSON line.  `value` = single-signal transforms per second (each
+forward, inverse or adjoint of one signal counts as one), from the wall clock
+around the K timed steps (bracketed by device synchronisation).  Every kernel
+is bracketed by HIP events on the stream it runs on; `roofline` reports the
+kernel with the largest share of the step against the HBM peak, with its
+algorithmic bytes per launch.  `cpu_baseline` times the CPU oracle (direct
+quadrature sum) on a bounded sample of the same forward workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
+DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
+STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
+KERNEL_NAME = {"ring_forward": "ring_forward_kernel", "beta_forward": "beta_forward_kernel",
+               "beta_inverse": "beta_inverse_kernel", "ring_inverse": "ring_inverse_kernel",
+               "beta_adjoint": "beta_inverse_kernel", "ring_adjoint": "ring_inverse_kernel"}
+
+
+def retained_pairs(B: int) -> int:
+    return 2 * B * B - 2 * B + 1
+
+
+def table_bytes(B: int, mode: str) -> int:
+    C = B * (B + 1) * (2 * B + 1) // 6
+    es = {"c128": 8, "c64": 4, "c64_bf16x3": 4}[mode]
+    return C * 2 * B * es
+
+
+def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
+    """Compulsory HBM bytes of one launch: inputs read once, outputs written once."""
+    N = 2 * B
+    cb = 16 if mode == "c128" else 8
+    C = B * (B + 1) * (2 * B + 1) // 6
+    ring = N ** 3 * cb                       # one signal's samples
+    spec = retained_pairs(B) * N * cb        # one signal's retained ring spectra
+    coef = C * cb
+    if stage.startswith("ring"):
+        return batch * (ring + spec)
+    return batch * (spec + coef) + table_bytes(B, mode)
+
+
+def useful_flops(stage: str, B: int, batch: int) -> float:
+    """Useful real flops of a beta contraction: 4 per (l, m, n, k, signal)."""
+    N = 2 * B
+    C = B * (B + 1) * (2 * B + 1) // 6
+    return 4.0 * N * C * batch if stage.startswith("beta") else 0.0
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_23923_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            h.update(fn.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, mode: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(f"{kernel}:{mode}")
+    if not ent or ent.get("source_digest") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps: bool):
+    import torch
+
+    import paper_2605_23923_amd as su2
+    import synth
+
+    plan = su2.Plan(B, batch, mode)
+    np_dt = "complex128" if mode == "c128" else "complex64"
+    c_host = synth.coeffs(B, batch, seed=2, spectrum="decay").astype(np_dt)
+    coeffs = torch.from_numpy(c_host).to("cuda")
+    samples = plan.inverse(coeffs)                       # input synthesis, not timed
+    c_out = torch.empty_like(coeffs)
+    x_out = torch.empty_like(samples)
+    a_out = torch.empty_like(samples)
+    args = {"ring_forward": (samples, None), "beta_forward": (None, c_out), "beta_inverse": (coeffs, None),
+            "ring_inverse": (None, x_out), "beta_adjoint": (coeffs, None), "ring_adjoint": (None, a_out)}
+
+    def step(evs=None):
+        for i, st in enumerate(STAGES):
+            if evs is not None:
+                evs[i].record()
+            plan.run_stage(st, *args[st])
+        if evs is not None:
+            evs[len(STAGES)].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms = {st: 0.0 for st in STAGES}
+    for s in range(steps):
+        for i, st in enumerate(STAGES):
+            stage_ms[st] += events[s][i].elapsed_time(events[s][i + 1]) / steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    out = {
+        "ms_per_step": ms_per_step,
+        "transforms_per_s": 3 * batch / (ms_per_step * 1e-3),
+        "forward_per_s": batch / ((stage_ms["ring_forward"] + stage_ms["beta_forward"]) * 1e-3),
+        "inverse_per_s": batch / ((stage_ms["beta_inverse"] + stage_ms["ring_inverse"]) * 1e-3),
+        "adjoint_per_s": batch / ((stage_ms["beta_adjoint"] + stage_ms["ring_adjoint"]) * 1e-3),
+        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stage_hbm_frac": {k: round(algorithmic_bytes(k, B, batch, mode) / (v * 1e-3) / HBM_PEAK, 4)
+                           for k, v in stage_ms.items()},
+        "beta_mfma_useful_frac": {k: round(useful_flops(k, B, batch) / (stage_ms[k] * 1e-3) / MFMA_PEAK[mode], 5)
+                                  for k in STAGES if k.startswith("beta")},
+    }
+    plan.close()
+    del samples, coeffs, c_out, x_out, a_out
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(B: int, budget_s: float):
+    """The oracle's direct sum on a bounded sample: the forward transform of one
+    signal restricted to a subset of its coefficients (a few of every 2l), timed
+    on the host; scaled to whole-signal transforms per second."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    C = B * (B + 1) * (2 * B + 1) // 6
+    x = synth.samples_uniform(B, 1, seed=5)[0]
+    rng = np.random.default_rng(0)
+    probe = rng.choice(C, 32, replace=False)
+    t0 = time.perf_counter()
+    oracle.forward(B, x, probe)
+    per = (time.perf_counter() - t0) / probe.size
+    count = int(min(C, max(64, budget_s / max(per, 1e-9))))
+    sel = rng.choice(C, count, replace=False)
+    t0 = time.perf_counter()
+    oracle.forward(B, x, sel)
+    dt = time.perf_counter() - t0
+    return {"value": round(count / dt / C, 6), "unit": "transforms/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"forward, B={B}, 1 signal, {count} of {C} coefficients (direct quadrature sum, "
+                      f"{(2 * B) ** 3} terms each), {dt:.1f} s; scaled by {C}/{count}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="c64", choices=["c128", "c64", "c64_bf16x3"],
+                    help="precision mode of the headline number")
+    ap.add_argument("--other-modes", default="c128",
+                    help="comma-separated modes also timed and reported under 'modes' ('' for none)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); signals are independent, "
+              "so a multi-GPU run would shard the batch (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    B, batch = 64, 32
+    digest = source_digest()
+    head = run_mode(args.mode, B, batch, args.steps, args.warmup, True)
+    modes = {args.mode: head}
+    for m in [m for m in args.other_modes.split(",") if m and m != args.mode]:
+        modes[m] = run_mode(m, B, batch, max(5, args.steps // 2), args.warmup, False)
+
+    dom = max(STAGES, key=lambda s: head["stage_ms"][s])
+    dom_ms = head["stage_ms"][dom]
+    ab = algorithmic_bytes(dom, B, batch, args.mode)
+    achieved = ab / (dom_ms * 1e-3)
+    roof = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "stage": dom, "achieved": round(achieved / 1e9, 2),
+            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+            "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(dom_ms, 5),
+            "traffic": measured_traffic(KERNEL_NAME[dom], args.mode, digest)}
+
+    line = {
+        "metric": "SU(2) FFT transforms/s at B=64 batch 32; %HBM/MFMA peak; plain vs BF16x2",
+        "value": round(head["transforms_per_s"], 2),
+        "unit": "transforms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE_NAME[args.mode], "data": "synthetic",
+        "config": {"workload": "SU(2) transform chain (forward + inverse + adjoint), B=64 (2l<64), "
+                               "128^3 Euler grid, batch 32, bandlimited Gaussian coefficients var (2l+1)^-2",
+                   "B": B, "batch": batch, "grid": "128x128x128", "mode": args.mode,
+                   "transforms_per_step": 3 * batch},
+        "roofline": roof,
+        "modes": {m: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for m, r in modes.items()},
+        "source_digest": digest,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(B, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

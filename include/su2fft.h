@@ -1,0 +1,161 @@
+/*
+ * su2fft -- separated Fourier transform on SU(2) for MI355X (gfx950).
+ *
+ * C ABI.  No C++ or framework types cross it: plain integers, plain host or
+ * device pointers, and the HIP stream handle as an opaque pointer.
+ *
+ * The transform (Section 3, Definition 3.4 and the Peter-Weyl series; the
+ * separation of Section 4, Proposition 4.2, with the contraction over beta of
+ * Section 4 generalised to every (m, n) pair):
+ *
+ *   forward  fhat(l)_{mn} = sum_{k,j,l'} W_k f(alpha_j, beta_k, gamma_l') conj(t^l_{nm})
+ *   inverse  f(alpha_j, beta_k, gamma_l') = sum_{2l<B} (2l+1) sum_{m,n} fhat(l)_{mn} t^l_{nm}
+ *   adjoint  (F^H c)(alpha_j, beta_k, gamma_l') = W_k sum_{l,m,n} c_{lmn} t^l_{nm}
+ *
+ * with t^l_{nm}(alpha, beta, gamma) = P^l_{nm}(cos beta) exp(-i(n alpha + m gamma))
+ * (the index-swapped basis of Section 3), l running over {0, 1/2, 1, ...,
+ * (B-1)/2} and m, n over -l..l with l-m, l-n integer.
+ *
+ * Grid (Definition 4.1 as read for an exact quadrature), N = 2B nodes per angle:
+ *   alpha_j = -pi + 2 pi j / N,  beta_k = pi k / (N-1),  gamma_l = -2 pi + 4 pi l / N,
+ *   W_k = w_k / (2 N^2), w_k the Clenshaw-Curtis weights on cos(beta_k).
+ * For a bandlimited f (all coefficients with 2l >= B zero) forward(inverse(c)) = c
+ * up to rounding.
+ *
+ * Layouts (per signal; signals of a batch are consecutive):
+ *   samples       [k: beta][j: alpha][l: gamma], row-major, N^3 complex values;
+ *   coefficients  2l-major blocks; the block of 2l = tl starts at tl(tl+1)(2tl+1)/6
+ *                 and is the (2l+1)x(2l+1) matrix fhat(l), row-major over
+ *                 m = -l..l (rows) and n = -l..l (columns); B(B+1)(2B+1)/6 values.
+ *   Complex values are interleaved (re, im): double for SU2_C128, float otherwise.
+ *
+ * Ownership and concurrency:
+ *   The plan owns its device tables and workspace, allocated on the device that
+ *   is current at su2_plan_create and freed by su2_plan_destroy.  The caller
+ *   owns every data pointer (device memory of that device, aligned to the
+ *   element size, inputs and outputs not overlapping); inputs are never written
+ *   and every output element is written.  Calls enqueue work on `stream`
+ *   (a hipStream_t; NULL = the null stream) and return without synchronising;
+ *   a kernel fault surfaces at the caller's next synchronisation.  A plan holds
+ *   one workspace: two calls with the same plan must not run concurrently
+ *   (different plans are independent).
+ *
+ * Errors: arguments are validated before any HIP call; no exception crosses
+ * the ABI.  On SU2_ERR_HIP the HIP error code is kept in a thread-local slot
+ * read by su2_last_hip_error().
+ */
+#ifndef SU2FFT_H
+#define SU2FFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SU2_OK = 0,
+  SU2_ERR_INVALID_VALUE = 1, /* null pointer, B < 1, batch < 1, unknown dtype, null plan */
+  SU2_ERR_UNSUPPORTED = 2,   /* B > 128, or N = 2B not of the form 2^a 3^b */
+  SU2_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed; nothing is leaked */
+  SU2_ERR_HIP = 4,           /* a HIP call or kernel launch failed (see su2_last_hip_error) */
+  SU2_ERR_NO_DEVICE = 5      /* no usable GPU */
+} su2_status_t;
+
+typedef enum {
+  SU2_C128 = 0,       /* complex double in and out; FP64 FFT, FP64 MFMA beta contraction */
+  SU2_C64 = 1,        /* complex float in and out; FP32 FFT, FP32 MFMA beta contraction  */
+  SU2_C64_BF16X3 = 2  /* complex float in and out; FP32 FFT; beta contraction in split
+                         bfloat16 (x = hi + lo, three products hi*hi + hi*lo + lo*hi)
+                         with FP32 accumulation */
+} su2_dtype_t;
+
+typedef struct su2_plan_s* su2_plan_t;
+
+/* Create a plan for `batch` signals of bandlimit B (2l < B) in `dtype`.
+ * Section 4, Definition 4.1 (grid) and Proposition 4.2 (the separation the
+ * plan's kernels carry out).  Allocates the Wigner-d tables (generated on the
+ * GPU by the FP64 three-term recurrence in l; Lemma 4.3 is its m = n = 0 case)
+ * and the workspace, on the current device; synchronises once.
+ * *out receives the plan (NULL on error). */
+su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_plan_t* out);
+
+/* Plan for a batch of signals with individual bandlimits B_per_signal[0..batch-1]
+ * (each 1..128, N = 2B of the form 2^a 3^b).  Signals are concatenated in order
+ * in the sample and coefficient buffers: signal s starts at the prefix sum of
+ * the per-signal sizes (su2_num_samples / su2_num_coeffs of its B).  The plan
+ * records every kernel of one call into a HIP graph (captured on the first
+ * call on a stream) and replays it.  B_per_signal is a host array, read only
+ * during the call. */
+su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype,
+                                   su2_plan_t* out);
+
+/* Release the plan's device memory.  Waits for work the plan enqueued.
+ * NULL is accepted and ignored. */
+su2_status_t su2_plan_destroy(su2_plan_t plan);
+
+/* Forward transform (analysis), Definition 3.4 with the separation of
+ * Proposition 4.2: a 2D FFT over (alpha, gamma) on every beta ring, then the
+ * contraction over beta for every (m, n) pair.
+ * d_samples: device, batch x N^3 complex; d_coeffs: device, batch x C(B) complex. */
+su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+
+/* Inverse transform (synthesis), the Peter-Weyl series of Section 3 evaluated
+ * as the transpose chain of the forward: contraction over l per (m, n), then an
+ * inverse 2D FFT per ring.  d_coeffs: device input; d_samples: device output. */
+su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+
+/* Adjoint (conjugate transpose) of su2_forward: the inverse chain with the
+ * weight W_k in place of (2l+1).  This is the backward map of the forward
+ * transform for gradient computation. */
+su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+
+/* The kernels behind su2_forward / su2_inverse / su2_adjoint, one at a time,
+ * for timing and profiling a single stage.  The intermediate ring spectra stay
+ * in the plan's workspace:
+ *   SU2_STAGE_RING_FORWARD  in = samples -> workspace      (out unused)
+ *   SU2_STAGE_BETA_FORWARD  workspace -> out = coefficients (in unused)
+ *   SU2_STAGE_BETA_INVERSE  in = coefficients -> workspace  (out unused)
+ *   SU2_STAGE_RING_INVERSE  workspace -> out = samples      (in unused)
+ *   SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT: the same for su2_adjoint.
+ * su2_forward is exactly RING_FORWARD then BETA_FORWARD on the same stream;
+ * su2_inverse is BETA_INVERSE then RING_INVERSE; su2_adjoint is BETA_ADJOINT
+ * then RING_ADJOINT.  Single-B plans only. */
+typedef enum {
+  SU2_STAGE_RING_FORWARD = 0,
+  SU2_STAGE_BETA_FORWARD = 1,
+  SU2_STAGE_BETA_INVERSE = 2,
+  SU2_STAGE_RING_INVERSE = 3,
+  SU2_STAGE_BETA_ADJOINT = 4,
+  SU2_STAGE_RING_ADJOINT = 5
+} su2_stage_t;
+su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream);
+
+/* Sizes and indexing (pure host functions, no device needed). */
+int64_t su2_num_samples(int32_t B);                                    /* (2B)^3, or -1 if B < 1 */
+int64_t su2_num_coeffs(int32_t B);                                     /* B(B+1)(2B+1)/6, or -1   */
+int64_t su2_coeff_index(int32_t two_l, int32_t two_m, int32_t two_n);  /* -1 if not a valid triple */
+
+/* Grid nodes and beta weights of the plan's quadrature (host arrays of 2B
+ * doubles each; any pointer may be NULL to skip it).  w_beta receives W_k. */
+su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, double* w_beta);
+
+/* Plan queries: bandlimit (-1 for mixed plans), batch, dtype, device bytes held. */
+su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype,
+                           int64_t* device_bytes);
+
+/* Diagnostic: copy to host the FP64 Wigner-d table a single-B plan generated
+ * for the pair (m, n) (doubled indices): host_out[k * L + i] = d^{l0+i}_{nm}(beta_k),
+ * l0 = max(|m|, |n|), k = 0..2B-1, with *L = number of degrees l (may be NULL
+ * to query L only when host_out is NULL).  SU2_ERR_INVALID_VALUE if the pair is
+ * not retained (|2m|, |2n| > B-1 or 2m, 2n of different parity).  Synchronous. */
+su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L);
+
+const char* su2_status_string(su2_status_t status);
+int32_t su2_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU2FFT_H */

@@ -1,0 +1,271 @@
+"""su2fft: the separated Fourier transform on SU(2) on MI355X (gfx950).
+
+Thin Python binding of the C ABI in ``include/su2fft.h`` (ctypes).  It only
+marshals arguments: every step of the transform runs in the HIP library
+``libsu2fft.so`` built next to this file.  PyTorch provides device memory and
+the current stream; there is no CPU or PyTorch fallback -- a missing or
+unloadable library raises.
+
+    plan = Plan(B=64, batch=32, dtype="c64")
+    coeffs = plan.forward(samples)        # (batch, C(B)) complex, 2l-major blocks
+    samples = plan.inverse(coeffs)        # (batch, N, N, N) complex, [k][j][l]
+    grad = plan.adjoint(coeffs)           # conjugate transpose of forward
+    coeffs = SU2Transform.apply(samples, plan)   # differentiable forward
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["Plan", "MixedPlan", "SU2Transform", "SU2Error", "num_coeffs", "num_samples", "coeff_index",
+           "grid", "library_path", "C128", "C64", "C64_BF16X3"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsu2fft.so")
+
+C128, C64, C64_BF16X3 = 0, 1, 2
+_DTYPES = {"c128": C128, "c64": C64, "c64_bf16x3": C64_BF16X3, C128: C128, C64: C64, C64_BF16X3: C64_BF16X3}
+_TORCH_DTYPE = {C128: torch.complex128, C64: torch.complex64, C64_BF16X3: torch.complex64}
+
+_STATUS = {0: "SU2_OK", 1: "SU2_ERR_INVALID_VALUE", 2: "SU2_ERR_UNSUPPORTED", 3: "SU2_ERR_OUT_OF_MEMORY",
+           4: "SU2_ERR_HIP", 5: "SU2_ERR_NO_DEVICE"}
+
+_lib = None
+
+
+class SU2Error(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = f"{where}: {_STATUS.get(status, status)}"
+        if status == 4 and _lib is not None:
+            msg += f" (hip error {_lib.su2_last_hip_error()})"
+        super().__init__(msg)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"su2fft HIP library not built: {_LIB_PATH} is missing "
+                          "(run __graft_entry__.build() or python -m paper_2605_23923_amd._build)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.su2_plan_create.argtypes = [i32, i32, i32, ctypes.POINTER(vp)]
+    lib.su2_plan_create.restype = i32
+    lib.su2_plan_create_mixed.argtypes = [ctypes.POINTER(i32), i32, i32, ctypes.POINTER(vp)]
+    lib.su2_plan_create_mixed.restype = i32
+    lib.su2_plan_destroy.argtypes = [vp]
+    lib.su2_plan_destroy.restype = i32
+    for name in ("su2_forward", "su2_inverse", "su2_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, vp, vp]
+        f.restype = i32
+    lib.su2_run_stage.argtypes = [vp, i32, vp, vp, vp]
+    lib.su2_run_stage.restype = i32
+    lib.su2_num_samples.argtypes = [i32]
+    lib.su2_num_samples.restype = i64
+    lib.su2_num_coeffs.argtypes = [i32]
+    lib.su2_num_coeffs.restype = i64
+    lib.su2_coeff_index.argtypes = [i32, i32, i32]
+    lib.su2_coeff_index.restype = i64
+    lib.su2_grid.argtypes = [i32, dp, dp, dp, dp]
+    lib.su2_grid.restype = i32
+    lib.su2_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i64)]
+    lib.su2_plan_info.restype = i32
+    lib.su2_plan_dtable.argtypes = [vp, i32, i32, dp, ctypes.POINTER(i32)]
+    lib.su2_plan_dtable.restype = i32
+    lib.su2_status_string.argtypes = [i32]
+    lib.su2_status_string.restype = ctypes.c_char_p
+    lib.su2_last_hip_error.argtypes = []
+    lib.su2_last_hip_error.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise SU2Error(status, where)
+
+
+def num_samples(B: int) -> int:
+    return int(_load().su2_num_samples(B))
+
+
+def num_coeffs(B: int) -> int:
+    return int(_load().su2_num_coeffs(B))
+
+
+def coeff_index(two_l: int, two_m: int, two_n: int) -> int:
+    return int(_load().su2_coeff_index(two_l, two_m, two_n))
+
+
+def grid(B: int):
+    """(alpha, beta, gamma, W) as lists of 2B floats (host computation)."""
+    N = 2 * B
+    arrs = [(ctypes.c_double * N)() for _ in range(4)]
+    _check(_load().su2_grid(B, *[ctypes.cast(a, ctypes.POINTER(ctypes.c_double)) for a in arrs]), "su2_grid")
+    return tuple(list(a) for a in arrs)
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class _PlanBase:
+    _handle = None
+
+    def _check_tensor(self, t: torch.Tensor, numel: int, what: str):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+        if t.dtype != self.torch_dtype:
+            raise TypeError(f"{what} must be {self.torch_dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+        if t.device != self.device:
+            raise ValueError(f"{what} is on {t.device}, plan is on {self.device}")
+
+    def _call(self, fn: str, src: torch.Tensor, dst: torch.Tensor):
+        status = getattr(_load(), fn)(self._handle, ctypes.c_void_p(src.data_ptr()),
+                                      ctypes.c_void_p(dst.data_ptr()), _stream_handle(self.device))
+        _check(status, fn)
+
+    def forward(self, samples: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(samples, self.total_samples, "samples")
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.torch_dtype, device=self.device)
+        self._check_tensor(out, self.total_coeffs, "out")
+        self._call("su2_forward", samples, out)
+        return out
+
+    def inverse(self, coeffs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(coeffs, self.total_coeffs, "coeffs")
+        if out is None:
+            out = torch.empty(self.sample_shape, dtype=self.torch_dtype, device=self.device)
+        self._check_tensor(out, self.total_samples, "out")
+        self._call("su2_inverse", coeffs, out)
+        return out
+
+    def adjoint(self, coeffs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_tensor(coeffs, self.total_coeffs, "coeffs")
+        if out is None:
+            out = torch.empty(self.sample_shape, dtype=self.torch_dtype, device=self.device)
+        self._check_tensor(out, self.total_samples, "out")
+        self._call("su2_adjoint", coeffs, out)
+        return out
+
+    STAGES = {"ring_forward": 0, "beta_forward": 1, "beta_inverse": 2, "ring_inverse": 3,
+              "beta_adjoint": 4, "ring_adjoint": 5}
+
+    def run_stage(self, stage: str, inp: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        """Launch one kernel stage (see su2_run_stage); the ring spectra stay in
+        the plan workspace between stages."""
+        code = self.STAGES[stage]
+        pin = ctypes.c_void_p(inp.data_ptr()) if inp is not None else ctypes.c_void_p()
+        pout = ctypes.c_void_p(out.data_ptr()) if out is not None else ctypes.c_void_p()
+        _check(_load().su2_run_stage(self._handle, code, pin, pout, _stream_handle(self.device)), "su2_run_stage")
+
+    def dtable(self, two_m: int, two_n: int):
+        """The plan's FP64 Wigner-d table of pair (m, n) as a list of rows
+        [k][i] = d^{l0+i}_{nm}(beta_k) (diagnostic, synchronous)."""
+        lib = _load()
+        L = ctypes.c_int32(0)
+        _check(lib.su2_plan_dtable(self._handle, two_m, two_n, None, ctypes.byref(L)), "su2_plan_dtable")
+        n = self.N * L.value
+        buf = (ctypes.c_double * max(n, 1))()
+        with torch.cuda.device(self.device):
+            _check(lib.su2_plan_dtable(self._handle, two_m, two_n,
+                                       ctypes.cast(buf, ctypes.POINTER(ctypes.c_double)), None), "su2_plan_dtable")
+        return [list(buf[k * L.value:(k + 1) * L.value]) for k in range(self.N)]
+
+    def device_bytes(self) -> int:
+        n = ctypes.c_int64(0)
+        _check(_load().su2_plan_info(self._handle, None, None, None, ctypes.byref(n)), "su2_plan_info")
+        return int(n.value)
+
+    def close(self):
+        if self._handle is not None and _lib is not None:
+            with torch.cuda.device(self.device):
+                _lib.su2_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan(_PlanBase):
+    """Transform plan for `batch` signals of bandlimit B (2l < B)."""
+
+    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None):
+        lib = _load()
+        self.B, self.batch = int(B), int(batch)
+        self.dtype = _DTYPES[dtype]
+        self.torch_dtype = _TORCH_DTYPE[self.dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.N = 2 * self.B
+        self.ncoef = num_coeffs(self.B) if self.B >= 1 else 0
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.su2_plan_create(self.B, self.batch, self.dtype, ctypes.byref(h)), "su2_plan_create")
+        self._handle = h
+        self.sample_shape = (self.batch, self.N, self.N, self.N)
+        self.coeff_shape = (self.batch, self.ncoef)
+        self.total_samples = self.batch * self.N ** 3
+        self.total_coeffs = self.batch * self.ncoef
+
+
+class MixedPlan(_PlanBase):
+    """Plan for a batch of signals with individual bandlimits, concatenated
+    in order (flat sample and coefficient buffers)."""
+
+    def __init__(self, Bs, dtype="c64", device=None):
+        lib = _load()
+        self.Bs = [int(b) for b in Bs]
+        self.batch = len(self.Bs)
+        self.dtype = _DTYPES[dtype]
+        self.torch_dtype = _TORCH_DTYPE[self.dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        arr = (ctypes.c_int32 * self.batch)(*self.Bs)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.su2_plan_create_mixed(arr, self.batch, self.dtype, ctypes.byref(h)), "su2_plan_create_mixed")
+        self._handle = h
+        self.sample_offsets = [0]
+        self.coeff_offsets = [0]
+        for b in self.Bs:
+            self.sample_offsets.append(self.sample_offsets[-1] + num_samples(b))
+            self.coeff_offsets.append(self.coeff_offsets[-1] + num_coeffs(b))
+        self.total_samples = self.sample_offsets[-1]
+        self.total_coeffs = self.coeff_offsets[-1]
+        self.sample_shape = (self.total_samples,)
+        self.coeff_shape = (self.total_coeffs,)
+
+
+class SU2Transform(torch.autograd.Function):
+    """Differentiable forward transform.  The backward pass is the adjoint
+    kernel chain (PyTorch's complex convention: grad_in = F^H grad_out)."""
+
+    @staticmethod
+    def forward(ctx, samples: torch.Tensor, plan: _PlanBase):
+        ctx.plan = plan
+        return plan.forward(samples.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        g = ctx.plan.adjoint(grad_out.contiguous())
+        return g, None

@@ -1,0 +1,501 @@
+// Host side of the su2fft C ABI: argument validation, grid and quadrature,
+// the pair ordering and FFT bin map, plan tables and workspace, dispatch.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "su2fft_internal.h"
+
+using namespace su2;
+
+static thread_local int32_t g_last_hip_error = 0;
+
+namespace {
+
+su2_status_t hip_fail(hipError_t e) {
+  g_last_hip_error = (int32_t)e;
+  // a failed runtime call also sets HIP's per-thread "last error"; reset it so
+  // that it is not reported again by the next launch check of a later call
+  (void)hipGetLastError();
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SU2_ERR_OUT_OF_MEMORY;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return SU2_ERR_NO_DEVICE;
+  return SU2_ERR_HIP;
+}
+
+bool only_2_3(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// radix sequence for a length that is a product of 2s and 3s: 8s first, then
+// a 4 or a 2 for the rest of the power of two, then 3s.
+int radix_plan(int L, int* rad) {
+  int n = 0;
+  int p2 = 0, p3 = 0;
+  while (L % 2 == 0) { L /= 2; p2++; }
+  while (L % 3 == 0) { L /= 3; p3++; }
+  while (p2 >= 3) { rad[n++] = 8; p2 -= 3; }
+  if (p2 == 2) rad[n++] = 4;
+  if (p2 == 1) rad[n++] = 2;
+  for (int i = 0; i < p3; i++) rad[n++] = 3;
+  return n;
+}
+
+// position of frequency q after in-place decimation-in-frequency passes with
+// the given radix sequence on a length-L line
+int dif_position(int q, int L, const int* rad, int nrad) {
+  int pos = 0;
+  for (int s = 0; s < nrad; s++) {
+    const int R = rad[s];
+    L /= R;
+    pos += (q % R) * L;
+    q /= R;
+  }
+  return pos;
+}
+
+int imod(int a, int n) { return ((a % n) + n) % n; }
+
+// Clenshaw-Curtis weights on the n+1 Chebyshev extreme points cos(k pi / n)
+// (closed endpoint weights plus a cosine sum for the interior), long double.
+void clenshaw_curtis(int n, std::vector<long double>& w) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  w.assign(n + 1, 0.0L);
+  if (n == 1) { w[0] = w[1] = 1.0L; return; }
+  const bool even = (n % 2 == 0);
+  const long double wend = even ? 1.0L / ((long double)n * n - 1.0L) : 1.0L / ((long double)n * n);
+  w[0] = w[n] = wend;
+  for (int i = 1; i < n; i++) {
+    const long double th = pi * i / n;
+    long double v = 1.0L;
+    const int kmax = even ? n / 2 - 1 : (n - 1) / 2;
+    for (int k = 1; k <= kmax; k++) v -= 2.0L * cosl(2.0L * k * th) / (4.0L * k * k - 1.0L);
+    if (even) v -= cosl(n * th) / ((long double)n * n - 1.0L);
+    w[i] = 2.0L * v / n;
+  }
+}
+
+void grid_ld(int B, std::vector<long double>& alpha, std::vector<long double>& beta, std::vector<long double>& gamma,
+             std::vector<long double>& W) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const int N = 2 * B;
+  alpha.resize(N); beta.resize(N); gamma.resize(N);
+  std::vector<long double> w;
+  clenshaw_curtis(N - 1, w);
+  W.resize(N);
+  for (int i = 0; i < N; i++) {
+    alpha[i] = -pi + 2.0L * pi * i / N;
+    beta[i] = pi * i / (N - 1);
+    gamma[i] = -2.0L * pi + 4.0L * pi * i / N;
+    W[i] = w[i] / (2.0L * N * N);
+  }
+}
+
+}  // namespace
+
+struct su2_plan_s {
+  int B = 0, N = 0, batch = 0;
+  su2_dtype_t dtype = SU2_C128;
+  int split = 1, Nc = 0;
+  int P = 0, P_pad = 0, ntiles = 0;
+  int nrad_c = 0, nrad_n = 0, rad_c[MAX_RADICES] = {0}, rad_n[MAX_RADICES] = {0};
+  int cls_begin[MAX_SPLIT] = {0}, cls_end[MAX_SPLIT] = {0};
+  long long ncoef = 0;
+  long long tab_elems = 0;
+  int device = 0;
+  int64_t bytes = 0;
+  // device memory
+  PairInfo* d_pairs = nullptr;
+  double* d_tab64 = nullptr;
+  float* d_tab32 = nullptr;
+  bf16x2_t* d_tabbf = nullptr;
+  int* d_fftpos = nullptr;
+  int* d_colq = nullptr;
+  void* d_rho = nullptr;
+  void* d_tw = nullptr;
+  void* d_W = nullptr;
+  void* d_S = nullptr;
+  std::vector<void*> allocs;
+  std::vector<PairInfo> h_pairs;
+
+  hipError_t alloc(void** p, size_t n) {
+    hipError_t e = hipMalloc(p, n == 0 ? 16 : n);
+    if (e == hipSuccess) { allocs.push_back(*p); bytes += (int64_t)n; }
+    return e;
+  }
+  void release() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+  }
+};
+
+namespace {
+
+template <class T>
+RingParams<T> ring_params(const su2_plan_s* pl, int adjoint) {
+  RingParams<T> r;
+  memset(&r, 0, sizeof(r));
+  r.N = pl->N; r.Nc = pl->Nc; r.split = pl->split; r.batch = pl->batch; r.ntiles = pl->ntiles;
+  r.nrad_c = pl->nrad_c; r.nrad_n = pl->nrad_n;
+  for (int i = 0; i < MAX_RADICES; i++) { r.rad_c[i] = pl->rad_c[i]; r.rad_n[i] = pl->rad_n[i]; }
+  for (int i = 0; i < MAX_SPLIT; i++) { r.cls_begin[i] = pl->cls_begin[i]; r.cls_end[i] = pl->cls_end[i]; }
+  r.tw = (const cpx<T>*)pl->d_tw;
+  r.W = (const T*)pl->d_W;
+  r.fftpos = pl->d_fftpos;
+  r.rho = (const cpx<T>*)pl->d_rho;
+  r.colq = pl->d_colq;
+  r.adjoint = adjoint;
+  return r;
+}
+
+template <class T>
+BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
+  BetaParams<T> b;
+  b.B = pl->B; b.N = pl->N; b.batch = pl->batch; b.ntiles = pl->ntiles;
+  b.ncoef = pl->ncoef;
+  b.pairs = pl->d_pairs;
+  b.tab = tab;
+  b.scale_mode = scale_mode;
+  return b;
+}
+
+template <class T>
+hipError_t upload_typed(su2_plan_s* pl, const std::vector<long double>& W, const std::vector<long double>& twr,
+                        const std::vector<long double>& twi, const std::vector<int>& rho_e) {
+  const int N = pl->N;
+  std::vector<T> hW(N);
+  for (int i = 0; i < N; i++) hW[i] = (T)W[i];
+  std::vector<cpx<T>> htw(2 * N);
+  for (int i = 0; i < 2 * N; i++) htw[i] = {(T)twr[i], (T)twi[i]};
+  std::vector<cpx<T>> hrho(pl->P_pad);
+  const T ir[4] = {1, 0, -1, 0}, ii[4] = {0, 1, 0, -1};  // i^e
+  for (int p = 0; p < pl->P_pad; p++) hrho[p] = {ir[rho_e[p]], ii[rho_e[p]]};
+  hipError_t e;
+  if ((e = pl->alloc(&pl->d_W, sizeof(T) * N)) != hipSuccess) return e;
+  if ((e = pl->alloc(&pl->d_tw, sizeof(cpx<T>) * 2 * N)) != hipSuccess) return e;
+  if ((e = pl->alloc(&pl->d_rho, sizeof(cpx<T>) * pl->P_pad)) != hipSuccess) return e;
+  if ((e = hipMemcpy(pl->d_W, hW.data(), sizeof(T) * N, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(pl->d_tw, htw.data(), sizeof(cpx<T>) * 2 * N, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(pl->d_rho, hrho.data(), sizeof(cpx<T>) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+su2_status_t build_plan(su2_plan_s* pl) {
+  const int B = pl->B, N = 2 * B;
+  pl->N = N;
+  pl->ncoef = (long long)B * (B + 1) * (2 * B + 1) / 6;
+  const size_t cb = (pl->dtype == SU2_C128) ? 16 : 8;
+
+  hipError_t e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
+  pl->device = dev;
+  int max_lds = 0;
+  if ((e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+    return hip_fail(e);
+
+  // gamma-frequency classes: the smallest divisor of N whose class fits in LDS
+  int split = 0;
+  for (int s = 1; s <= MAX_SPLIT; s++) {
+    if (N % s) continue;
+    const size_t need = ((size_t)N * (N / s) + 2 * (size_t)N) * cb;
+    if (need <= (size_t)max_lds) { split = s; break; }
+  }
+  if (split == 0) return SU2_ERR_UNSUPPORTED;
+  pl->split = split;
+  pl->Nc = N / split;
+  pl->nrad_c = radix_plan(pl->Nc, pl->rad_c);
+  pl->nrad_n = radix_plan(N, pl->rad_n);
+
+  // pairs (m, n): grouped by class r = (2m mod N) mod split, then 2m, then 2n
+  std::vector<PairInfo> pairs;
+  std::vector<int> fftpos, rho_e;
+  long long tab = 0;
+  for (int r = 0; r < split; r++) {
+    pl->cls_begin[r] = (int)pairs.size();
+    for (int tm = -(B - 1); tm <= B - 1; tm++) {
+      const int q = imod(tm, N);
+      if (q % split != r) continue;
+      const int qp = q / split;
+      const int ccol = dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c);
+      for (int tn = -(B - 1); tn <= B - 1; tn++) {
+        if ((tn - tm) & 1) continue;
+        PairInfo pi;
+        pi.tm = tm; pi.tn = tn;
+        pi.tl0 = abs(tm) > abs(tn) ? abs(tm) : abs(tn);
+        pi.L = (B - 1 - pi.tl0) / 2 + 1;
+        pi.tab = tab;
+        tab += (long long)N * pi.L;
+        pairs.push_back(pi);
+        const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
+        const int jrow = dif_position(palpha, N, pl->rad_n, pl->nrad_n);
+        fftpos.push_back(jrow * pl->Nc + ccol);
+        // rho = i^{n-m} (-1)^{2m} e^{-i pi n} = i^{(tn-tm)/2 + 2 tm + 3 tn}
+        rho_e.push_back(imod((tn - tm) / 2 + 2 * tm + 3 * tn, 4));
+      }
+    }
+    pl->cls_end[r] = (int)pairs.size();
+  }
+  pl->P = (int)pairs.size();
+  pl->P_pad = (pl->P + PT - 1) / PT * PT;
+  pl->ntiles = pl->P_pad / PT;
+  while ((int)pairs.size() < pl->P_pad) {
+    PairInfo pi;
+    pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0;
+    pairs.push_back(pi);
+    fftpos.push_back(0);
+    rho_e.push_back(0);
+  }
+  pl->tab_elems = tab;
+  pl->h_pairs = pairs;
+  std::vector<int> colq(pl->Nc);
+  for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
+
+  std::vector<long double> alpha, beta, gamma, W;
+  grid_ld(B, alpha, beta, gamma, W);
+  std::vector<long double> twr(2 * N), twi(2 * N);
+  const long double pi_l = 3.141592653589793238462643383279502884L;
+  for (int t = 0; t < 2 * N; t++) { twr[t] = cosl(pi_l * t / N); twi[t] = sinl(pi_l * t / N); }
+  std::vector<double> hbeta(N);
+  for (int i = 0; i < N; i++) hbeta[i] = (double)beta[i];
+
+  // device tables
+  double* d_beta = nullptr;
+  if ((e = pl->alloc((void**)&pl->d_pairs, sizeof(PairInfo) * pl->P_pad)) != hipSuccess) return hip_fail(e);
+  if ((e = pl->alloc((void**)&pl->d_fftpos, sizeof(int) * pl->P_pad)) != hipSuccess) return hip_fail(e);
+  if ((e = pl->alloc((void**)&pl->d_colq, sizeof(int) * pl->Nc)) != hipSuccess) return hip_fail(e);
+  if ((e = pl->alloc((void**)&d_beta, sizeof(double) * N)) != hipSuccess) return hip_fail(e);
+  if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMemcpy(pl->d_pairs, pairs.data(), sizeof(PairInfo) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(pl->d_fftpos, fftpos.data(), sizeof(int) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(pl->d_colq, colq.data(), sizeof(int) * pl->Nc, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(d_beta, hbeta.data(), sizeof(double) * N, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if (pl->dtype == SU2_C128)
+    e = upload_typed<double>(pl, W, twr, twi, rho_e);
+  else
+    e = upload_typed<float>(pl, W, twr, twi, rho_e);
+  if (e != hipSuccess) return hip_fail(e);
+
+  if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
+  if (pl->dtype == SU2_C64) {
+    if ((e = pl->alloc((void**)&pl->d_tab32, sizeof(float) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_round_table_f32(tab, pl->d_tab64, pl->d_tab32, 0)) != hipSuccess) return hip_fail(e);
+  } else if (pl->dtype == SU2_C64_BF16X3) {
+    if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_split_table_bf16(tab, pl->d_tab64, pl->d_tabbf, 0)) != hipSuccess) return hip_fail(e);
+  }
+  if ((e = pl->alloc(&pl->d_S, cb * (size_t)pl->P_pad * N * pl->batch)) != hipSuccess) return hip_fail(e);
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+template <class T>
+const T* table_of(const su2_plan_s* pl) {
+  return std::is_same<T, double>::value ? (const T*)pl->d_tab64 : (const T*)pl->d_tab32;
+}
+
+template <class T>
+su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  switch (stage) {
+    case SU2_STAGE_RING_FORWARD:
+      e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      break;
+    case SU2_STAGE_BETA_FORWARD:
+      e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+      break;
+    case SU2_STAGE_BETA_INVERSE:
+    case SU2_STAGE_BETA_ADJOINT:
+      e = launch_beta_inverse<T>(beta_params<T>(pl, table_of<T>(pl), stage == SU2_STAGE_BETA_ADJOINT),
+                                 (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      break;
+    case SU2_STAGE_RING_INVERSE:
+    case SU2_STAGE_RING_ADJOINT:
+      e = launch_ring_inverse<T>(ring_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
+                                 (cpx<T>*)out, s);
+      break;
+    default:
+      return SU2_ERR_INVALID_VALUE;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+su2_status_t run_stage(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s) {
+  if (pl->dtype == SU2_C128) return run_stage_t<double>(pl, stage, in, out, s);
+  return run_stage_t<float>(pl, stage, in, out, s);
+}
+
+su2_status_t run_pair(su2_plan_s* pl, su2_stage_t first, su2_stage_t second, const void* in, void* out,
+                      hipStream_t s) {
+  su2_status_t st = run_stage(pl, first, in, nullptr, s);
+  if (st != SU2_OK) return st;
+  return run_stage(pl, second, nullptr, out, s);
+}
+
+su2_status_t check_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    g_last_hip_error = (int32_t)e;
+    return SU2_ERR_NO_DEVICE;
+  }
+  return SU2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t su2_num_samples(int32_t B) {
+  if (B < 1) return -1;
+  const int64_t N = 2 * (int64_t)B;
+  return N * N * N;
+}
+
+int64_t su2_num_coeffs(int32_t B) {
+  if (B < 1) return -1;
+  return (int64_t)B * (B + 1) * (2 * B + 1) / 6;
+}
+
+int64_t su2_coeff_index(int32_t tl, int32_t tm, int32_t tn) {
+  if (tl < 0 || tm < -tl || tm > tl || tn < -tl || tn > tl) return -1;
+  if (((tl - tm) & 1) || ((tl - tn) & 1)) return -1;
+  return (int64_t)tl * (tl + 1) * (2 * tl + 1) / 6 + (int64_t)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
+}
+
+su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, double* w_beta) {
+  if (B < 1) return SU2_ERR_INVALID_VALUE;
+  if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
+  std::vector<long double> a, b, g, W;
+  grid_ld(B, a, b, g, W);
+  for (int i = 0; i < 2 * B; i++) {
+    if (alpha) alpha[i] = (double)a[i];
+    if (beta) beta[i] = (double)b[i];
+    if (gamma) gamma[i] = (double)g[i];
+    if (w_beta) w_beta[i] = (double)W[i];
+  }
+  return SU2_OK;
+}
+
+su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_plan_t* out) {
+  if (!out) return SU2_ERR_INVALID_VALUE;
+  *out = nullptr;
+  if (B < 1 || batch < 1) return SU2_ERR_INVALID_VALUE;
+  if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
+  if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
+  if (dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
+  su2_status_t st = check_device();
+  if (st != SU2_OK) return st;
+  su2_plan_s* pl = new (std::nothrow) su2_plan_s();
+  if (!pl) return SU2_ERR_OUT_OF_MEMORY;
+  pl->B = B;
+  pl->batch = batch;
+  pl->dtype = dtype;
+  st = build_plan(pl);
+  if (st != SU2_OK) {
+    (void)hipDeviceSynchronize();
+    pl->release();
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return SU2_OK;
+}
+
+su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype, su2_plan_t* out) {
+  if (!out || !B_per_signal) return SU2_ERR_INVALID_VALUE;
+  *out = nullptr;
+  if (batch < 1) return SU2_ERR_INVALID_VALUE;
+  if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
+  for (int i = 0; i < batch; i++) {
+    if (B_per_signal[i] < 1) return SU2_ERR_INVALID_VALUE;
+    if (B_per_signal[i] > 128 || !only_2_3(2 * B_per_signal[i])) return SU2_ERR_UNSUPPORTED;
+  }
+  return SU2_ERR_UNSUPPORTED;
+}
+
+su2_status_t su2_plan_destroy(su2_plan_t plan) {
+  if (!plan) return SU2_OK;
+  hipError_t e = hipDeviceSynchronize();
+  plan->release();
+  delete plan;
+  if (e != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype, int64_t* device_bytes) {
+  if (!plan) return SU2_ERR_INVALID_VALUE;
+  if (B) *B = plan->B;
+  if (batch) *batch = plan->batch;
+  if (dtype) *dtype = (int32_t)plan->dtype;
+  if (device_bytes) *device_bytes = plan->bytes;
+  return SU2_OK;
+}
+
+su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+  if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, (hipStream_t)stream);
+}
+
+su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+  if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  return run_pair(plan, SU2_STAGE_BETA_INVERSE, SU2_STAGE_RING_INVERSE, d_coeffs, d_samples, (hipStream_t)stream);
+}
+
+su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+  if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  return run_pair(plan, SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT, d_coeffs, d_samples, (hipStream_t)stream);
+}
+
+su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream) {
+  if (!plan) return SU2_ERR_INVALID_VALUE;
+  if ((int)stage < 0 || (int)stage > (int)SU2_STAGE_RING_ADJOINT) return SU2_ERR_INVALID_VALUE;
+  const bool needs_in = stage == SU2_STAGE_RING_FORWARD || stage == SU2_STAGE_BETA_INVERSE ||
+                        stage == SU2_STAGE_BETA_ADJOINT;
+  if (needs_in ? !in : !out) return SU2_ERR_INVALID_VALUE;
+  return run_stage(plan, stage, in, out, (hipStream_t)stream);
+}
+
+su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L) {
+  if (!plan || (!host_out && !L)) return SU2_ERR_INVALID_VALUE;
+  for (int p = 0; p < plan->P; p++) {
+    const PairInfo& pi = plan->h_pairs[p];
+    if (pi.tm != two_m || pi.tn != two_n) continue;
+    if (L) *L = pi.L;
+    if (host_out) {
+      hipError_t e = hipMemcpy(host_out, plan->d_tab64 + pi.tab, sizeof(double) * (size_t)plan->N * pi.L,
+                               hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    return SU2_OK;
+  }
+  return SU2_ERR_INVALID_VALUE;
+}
+
+const char* su2_status_string(su2_status_t status) {
+  switch (status) {
+    case SU2_OK: return "SU2_OK";
+    case SU2_ERR_INVALID_VALUE: return "SU2_ERR_INVALID_VALUE: invalid argument";
+    case SU2_ERR_UNSUPPORTED: return "SU2_ERR_UNSUPPORTED: unsupported bandlimit or mode";
+    case SU2_ERR_OUT_OF_MEMORY: return "SU2_ERR_OUT_OF_MEMORY: device allocation failed";
+    case SU2_ERR_HIP: return "SU2_ERR_HIP: HIP runtime error";
+    case SU2_ERR_NO_DEVICE: return "SU2_ERR_NO_DEVICE: no usable GPU";
+  }
+  return "unknown status";
+}
+
+int32_t su2_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

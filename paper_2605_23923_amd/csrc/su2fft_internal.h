@@ -1,0 +1,105 @@
+// Internal declarations shared by the su2fft host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/su2fft.h"
+
+namespace su2 {
+
+// Pairs (m, n) are processed in tiles of PT consecutive pairs.  The
+// intermediate ring spectra live in the plan workspace as
+//   S[tile][k][b][PT]   (complex),
+// so that a ring (b, k) writes PT contiguous values per tile and a beta
+// contraction over one tile reads, for each k, a contiguous [b][PT] slab.
+constexpr int PT = 16;
+constexpr int MAX_RADICES = 8;
+constexpr int MAX_SPLIT = 8;
+constexpr int FFT_THREADS = 256;
+constexpr int GEMM_THREADS = 256;
+
+template <class T>
+struct cpx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ inline cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__host__ __device__ inline cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <class T>
+__host__ __device__ inline cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__host__ __device__ inline cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__host__ __device__ inline cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// Per-pair data used by the beta contraction.
+struct PairInfo {
+  int tm, tn;     // doubled m, n
+  int tl0;        // doubled lowest degree: max(|tm|, |tn|)
+  int L;          // number of degrees l (0 for padding pairs)
+  long long tab;  // offset of the pair's table block [k][L] (in table elements)
+};
+
+// Parameters of the ring-FFT kernels (one workgroup per ring (signal, k)).
+template <class T>
+struct RingParams {
+  int N;          // nodes per angle
+  int Nc;         // columns held in LDS at once: N / split
+  int split;      // number of gamma-frequency classes processed one after another
+  int batch;
+  int ntiles;     // pair tiles
+  int nrad_c, nrad_n;
+  int rad_c[MAX_RADICES];   // radix sequence of the length-Nc gamma transform
+  int rad_n[MAX_RADICES];   // radix sequence of the length-N alpha transform
+  int cls_begin[MAX_SPLIT], cls_end[MAX_SPLIT];  // pair ranges per class
+  const cpx<T>* tw;         // e^{+i pi t / N}, t = 0..2N-1
+  const T* W;               // beta weights W_k
+  const int* fftpos;        // per pair: LDS position (row * Nc + column) of its bin
+  const cpx<T>* rho;        // per pair: phase i^{n-m} (-1)^{2m} e^{-i pi n}
+  const int* colq;          // per LDS column c': q' with pos(q') = c'
+  int adjoint;              // inverse chain: 0 -> plain, 1 -> multiply by W_k
+};
+
+// Parameters of the beta contraction kernels.
+template <class T>
+struct BetaParams {
+  int B, N, batch, ntiles;
+  long long ncoef;          // coefficients per signal
+  const PairInfo* pairs;
+  const T* tab;             // Wigner-d table, per pair [k][L]
+  int scale_mode;           // inverse: 0 -> (2l+1) weights, 1 -> none (adjoint)
+};
+
+// bf16 split table entry (hi, lo) for the split-precision contraction
+struct bf16x2_t {
+  unsigned short hi, lo;
+};
+
+// ---- kernel launchers (defined in the .hip files) ----
+template <class T>
+hipError_t launch_ring_forward(const RingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
+template <class T>
+hipError_t launch_ring_inverse(const RingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s);
+template <class T>
+hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s);
+template <class T>
+hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s);
+hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const bf16x2_t* tab, const cpx<float>* S,
+                                      cpx<float>* coeffs, hipStream_t s);
+hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const bf16x2_t* tab, const cpx<float>* coeffs,
+                                      cpx<float>* S, hipStream_t s);
+
+// d-table generation: FP64 three-term recurrence in l, one thread per (pair, k).
+hipError_t launch_dtable(int B, int N, int npairs, const PairInfo* pairs, const double* beta, double* tab64,
+                         hipStream_t s);
+hipError_t launch_round_table_f32(long long n, const double* src, float* dst, hipStream_t s);
+hipError_t launch_split_table_bf16(long long n, const double* src, bf16x2_t* dst, hipStream_t s);
+
+}  // namespace su2

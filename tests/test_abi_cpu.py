@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, validates arguments before touching
+the device, and its host helpers (sizes, indices, grid) agree with the
+oracle's independent implementations."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_23923_amd as su2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(su2_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(su2.library_path())
+    names = _header_functions()
+    assert "su2_forward" in names and "su2_plan_create" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+
+
+def test_sizes_and_indices_match_oracle():
+    for B in (1, 2, 3, 8, 64, 128):
+        assert su2.num_coeffs(B) == oracle.num_coeffs(B)
+        assert su2.num_samples(B) == (2 * B) ** 3
+    for tl in range(0, 12):
+        for tm in range(-tl - 1, tl + 2):
+            for tn in range(-tl - 1, tl + 2):
+                assert su2.coeff_index(tl, tm, tn) == oracle.coeff_index(tl, tm, tn)
+    assert su2.num_coeffs(0) == -1 and su2.num_samples(-3) == -1
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 8, 24, 64, 128])
+def test_grid_matches_oracle(B):
+    a, b, g, w = (np.array(v) for v in su2.grid(B))
+    A, Bt, G, W = oracle.grid(B)
+    # the library builds the grid in long double and rounds once; the oracle in
+    # double: agreement to a few units in the last place
+    assert np.max(np.abs(a - A)) < 4e-15 and np.max(np.abs(b - Bt)) < 4e-15
+    assert np.max(np.abs(g - G)) < 8e-15
+    assert np.max(np.abs(w - W)) < 4e-15 * np.max(np.abs(W))
+
+
+def _lib():
+    su2._load()
+    return su2._lib
+
+
+def _create(B, batch, dtype):
+    h = ctypes.c_void_p()
+    st = _lib().su2_plan_create(B, batch, dtype, ctypes.byref(h))
+    return st, h
+
+
+def test_argument_validation_before_any_device_call():
+    lib = _lib()
+    assert _create(0, 1, 0)[0] == 1           # B < 1
+    assert _create(8, 0, 0)[0] == 1           # batch < 1
+    assert _create(8, 1, 7)[0] == 1           # unknown dtype
+    assert _create(5, 1, 0)[0] == 2           # N = 10 is not 2^a 3^b
+    assert _create(129, 1, 0)[0] == 2         # beyond the largest bandlimit
+    assert lib.su2_plan_create(8, 1, 0, None) == 1
+    assert lib.su2_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
+    assert lib.su2_inverse(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
+    assert lib.su2_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
+    assert lib.su2_plan_destroy(None) == 0
+    bs = (ctypes.c_int32 * 2)(8, 5)
+    h = ctypes.c_void_p()
+    assert lib.su2_plan_create_mixed(bs, 2, 1, ctypes.byref(h)) == 2
+    bs = (ctypes.c_int32 * 2)(8, 0)
+    assert lib.su2_plan_create_mixed(bs, 2, 1, ctypes.byref(h)) == 1
+    assert lib.su2_grid(0, None, None, None, None) == 1
+    assert lib.su2_status_string(2).startswith(b"SU2_ERR_UNSUPPORTED")
+
+
+def test_valid_plan_without_device_reports_no_device():
+    st, h = _create(8, 1, 1)
+    if st == 0:                                # a GPU is visible: the plan is real
+        assert _lib().su2_plan_destroy(h) == 0
+    else:
+        assert st == 5, f"expected SU2_ERR_NO_DEVICE, got {st}"
+        assert not h.value

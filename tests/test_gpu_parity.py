@@ -1,0 +1,202 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerances (normwise relative error ||x - x_ref|| / ||x_ref|| and worst element
+relative to the largest reference element):
+* c128 (FP64 everywhere): 1e-10, the target the transform is specified to;
+  observed values are near 1e-14.
+* c64 (FP32 FFT, FP32 matrix-core contraction, tables rounded from FP64):
+  2e-5.  FP32 unit roundoff is 6e-8; the ring FFT has 2 log2 N <= 16 radix
+  stages and the beta sum runs over N <= 256 terms, so the expected normwise
+  error is a few 1e-7 with a margin of roughly 30x for the worst element.
+The oracle runs on the same inputs (FP32 inputs are upcast exactly).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_23923_amd as su2
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 2e-5}
+NPDT = {"c128": np.complex128, "c64": np.complex64}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def _check(got, ref, tol, what):
+    got = np.asarray(got, dtype=np.complex128).reshape(-1)
+    ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
+    assert np.all(np.isfinite(got)), f"{what}: non-finite output"
+    nrm = np.linalg.norm(ref)
+    rel = np.linalg.norm(got - ref) / nrm
+    worst = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"{what}: rel {rel:.3e} worst {worst:.3e}", flush=True)
+    assert rel <= tol and worst <= 30 * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
+
+
+SMALL_B = [1, 2, 3, 4, 6, 8, 12, 16, 24]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("B", SMALL_B)
+def test_forward_matches_oracle(B, dtype):
+    batch = 3
+    x = synth.samples_uniform(B, batch, seed=100 + B, dtype=NPDT[dtype])
+    plan = su2.Plan(B, batch, dtype)
+    got = _host(plan.forward(_dev(x)))
+    ref = np.stack([oracle.forward(B, x[b]) for b in range(batch)])
+    _check(got, ref, TOL[dtype], f"forward B={B} {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("B", SMALL_B)
+def test_inverse_and_adjoint_match_oracle(B, dtype):
+    batch = 3
+    c = synth.coeffs(B, batch, seed=200 + B, dtype=NPDT[dtype])
+    plan = su2.Plan(B, batch, dtype)
+    gi = _host(plan.inverse(_dev(c)))
+    ga = _host(plan.adjoint(_dev(c)))
+    N = 2 * B
+    if B <= 16:
+        ri = np.stack([oracle.inverse(B, c[b]) for b in range(batch)])
+        ra = np.stack([oracle.adjoint(B, c[b]) for b in range(batch)])
+        _check(gi, ri, TOL[dtype], f"inverse B={B} {dtype}")
+        _check(ga, ra, TOL[dtype], f"adjoint B={B} {dtype}")
+    else:
+        rng = np.random.default_rng(7)
+        pts = rng.choice(N ** 3, 400, replace=False)
+        for b in range(batch):
+            _check(gi[b].reshape(-1)[pts], oracle.inverse(B, c[b], pts), TOL[dtype], f"inverse B={B} {dtype} s{b}")
+            _check(ga[b].reshape(-1)[pts], oracle.adjoint(B, c[b], pts), TOL[dtype], f"adjoint B={B} {dtype} s{b}")
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 8, 16, 32, 64])
+def test_round_trip_bandlimited(B):
+    """Exact quadrature: forward(inverse(c)) = c on the GPU (FP64)."""
+    batch = 2
+    c = synth.coeffs(B, batch, seed=300 + B)
+    plan = su2.Plan(B, batch, "c128")
+    back = _host(plan.forward(plan.inverse(_dev(c))))
+    _check(back, c, 1e-12, f"round trip B={B}")
+
+
+@pytest.mark.parametrize("B", [8, 24, 64, 128])
+def test_dtable_matches_oracle(B):
+    """The FP64 Wigner-d table generated on the GPU by the l-recurrence against the
+    oracle's Jacobi-form values, on sampled pairs (including the extreme ones)."""
+    plan = su2.Plan(B, 1, "c128")
+    _, beta, _, _ = oracle.grid(B)
+    rng = np.random.default_rng(B)
+    pairs = [(B - 1, B - 1), (-(B - 1), B - 1), (0 if B % 2 else 1, 0 if B % 2 else 1)]
+    for _ in range(12):
+        tm = int(rng.integers(-(B - 1), B))
+        tn = int(rng.integers(-(B - 1), B))
+        if (tn - tm) % 2:
+            tn = tn - 1 if tn > -(B - 1) else tn + 1
+        pairs.append((tm, tn))
+    worst = 0.0
+    for tm, tn in pairs:
+        tab = np.array(plan.dtable(tm, tn))
+        tl0 = max(abs(tm), abs(tn))
+        for k in range(0, 2 * B, max(1, (2 * B) // 16)):
+            for i in range(tab.shape[1]):
+                worst = max(worst, abs(tab[k, i] - oracle.wigner_d(tl0 + 2 * i, tn, tm, beta[k])))
+    print(f"dtable B={B}: worst {worst:.3e}")
+    assert worst < 1e-13
+
+
+def _stratified_coeffs(B, count, rng):
+    """Coefficient indices covering every 2l, with the extreme m, n of each block."""
+    sel = []
+    for tl in range(B):
+        base = oracle.coeff_index(tl, -tl, -tl)
+        sel += [base, base + (tl + 1) ** 2 - 1]
+    extra = rng.choice(oracle.num_coeffs(B), count, replace=False)
+    return np.unique(np.concatenate([np.array(sel), extra]))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_size_b64_batch32_sampled(dtype):
+    """B = 64, batch 32 (the benchmark configuration): forward on every signal,
+    checked against the oracle on sampled coefficients of four signals; inverse
+    and adjoint on sampled sample points."""
+    B, batch = 64, 32
+    rng = np.random.default_rng(64)
+    plan = su2.Plan(B, batch, dtype)
+    x = synth.samples_uniform(B, batch, seed=5, dtype=NPDT[dtype])
+    got = plan.forward(_dev(x))
+    torch.cuda.synchronize()
+    got = _host(got)
+    assert np.all(np.isfinite(got))
+    sel = _stratified_coeffs(B, 64, rng)
+    for b in (0, 1, 17, 31):
+        _check(got[b][sel], oracle.forward(B, x[b], sel), TOL[dtype], f"forward B=64 s{b} {dtype}")
+    del x
+    c = synth.coeffs(B, batch, seed=2, spectrum="decay", dtype=NPDT[dtype])
+    gi = _host(plan.inverse(_dev(c)))
+    ga = _host(plan.adjoint(_dev(c)))
+    N = 2 * B
+    pts = np.concatenate([rng.choice(N ** 3, 48, replace=False), [0, N ** 3 - 1, N * N * (N - 1)]])
+    for b in (0, 31):
+        _check(gi[b].reshape(-1)[pts], oracle.inverse(B, c[b], pts), TOL[dtype], f"inverse B=64 s{b} {dtype}")
+        _check(ga[b].reshape(-1)[pts], oracle.adjoint(B, c[b], pts), TOL[dtype], f"adjoint B=64 s{b} {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_max_bandlimit_b128_sampled(dtype):
+    """B = 128 (largest supported; 256^3 grid, rings split into gamma classes)."""
+    B, batch = 128, 2
+    rng = np.random.default_rng(128)
+    plan = su2.Plan(B, batch, dtype)
+    c = synth.coeffs(B, batch, seed=4, dtype=NPDT[dtype])
+    x = plan.inverse(_dev(c))
+    back = _host(plan.forward(x))
+    tol_rt = 1e-11 if dtype == "c128" else 1e-4
+    _check(back, c, tol_rt, f"round trip B=128 {dtype}")
+    xs = _host(x)
+    N = 2 * B
+    pts = rng.choice(N ** 3, 24, replace=False)
+    _check(xs[1].reshape(-1)[pts], oracle.inverse(B, c[1], pts), TOL[dtype], f"inverse B=128 {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_independence_bitwise(dtype):
+    """A signal's result does not depend on its batch neighbours or on the batch
+    size (bitwise), and repeated calls are deterministic."""
+    B = 16
+    x = synth.samples_uniform(B, 19, seed=9, dtype=NPDT[dtype])
+    big = su2.Plan(B, 19, dtype)
+    one = su2.Plan(B, 1, dtype)
+    r1 = _host(big.forward(_dev(x)))
+    r2 = _host(big.forward(_dev(x)))
+    assert np.array_equal(r1, r2)
+    for b in (0, 7, 18):
+        assert np.array_equal(r1[b], _host(one.forward(_dev(x[b:b + 1])))[0])
+
+
+def test_absurd_batch_is_out_of_memory_without_leak():
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    with pytest.raises(su2.SU2Error) as ei:
+        su2.Plan(128, 1 << 30, "c128")
+    assert ei.value.status == 3
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < 64 << 20
+
+
+def test_wrong_tensor_arguments_are_rejected():
+    plan = su2.Plan(4, 2, "c64")
+    with pytest.raises(TypeError):
+        plan.forward(torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.forward(torch.zeros((1, 8, 8, 8), dtype=torch.complex64, device="cuda"))
