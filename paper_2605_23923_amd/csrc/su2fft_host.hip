@@ -117,6 +117,8 @@ struct su2_plan_s {
   bf16x2_t* d_tabbf = nullptr;
   int* d_fftpos = nullptr;
   int* d_colq = nullptr;
+  int* d_bins = nullptr;
+  bool fast = false;
   void* d_rho = nullptr;
   void* d_tw = nullptr;
   void* d_W = nullptr;
@@ -150,6 +152,17 @@ RingParams<T> ring_params(const su2_plan_s* pl, int adjoint) {
   r.fftpos = pl->d_fftpos;
   r.rho = (const cpx<T>*)pl->d_rho;
   r.colq = pl->d_colq;
+  r.adjoint = adjoint;
+  return r;
+}
+
+template <class T>
+FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
+  FastRingParams<T> r;
+  r.N = pl->N; r.batch = pl->batch;
+  r.tw = (const cpx<T>*)pl->d_tw;
+  r.W = (const T*)pl->d_W;
+  r.bins = pl->d_bins;
   r.adjoint = adjoint;
   return r;
 }
@@ -255,6 +268,15 @@ su2_status_t build_plan(su2_plan_s* pl) {
   }
   pl->tab_elems = tab;
   pl->h_pairs = pairs;
+  // bin -> pair map for the register-resident ring kernels
+  pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
+  std::vector<int> bins((size_t)N * N, -1);
+  for (int pidx = 0; pidx < pl->P; pidx++) {
+    const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
+    const int q = imod(tm, N);
+    const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
+    bins[(size_t)q * N + palpha] = (pidx << 2) | rho_e[pidx];
+  }
   std::vector<int> colq(pl->Nc);
   for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
 
@@ -272,6 +294,9 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_fftpos, sizeof(int) * pl->P_pad)) != hipSuccess) return hip_fail(e);
   if ((e = pl->alloc((void**)&pl->d_colq, sizeof(int) * pl->Nc)) != hipSuccess) return hip_fail(e);
   if ((e = pl->alloc((void**)&d_beta, sizeof(double) * N)) != hipSuccess) return hip_fail(e);
+  if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
   if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_pairs, pairs.data(), sizeof(PairInfo) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
@@ -310,7 +335,10 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
   hipError_t e = hipSuccess;
   switch (stage) {
     case SU2_STAGE_RING_FORWARD:
-      e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      if (pl->fast)
+        e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      else
+        e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
       break;
     case SU2_STAGE_BETA_FORWARD:
       e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
@@ -322,8 +350,12 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
-      e = launch_ring_inverse<T>(ring_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
-                                 (cpx<T>*)out, s);
+      if (pl->fast)
+        e = launch_ring_inverse_fast<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
+                                        (cpx<T>*)out, s);
+      else
+        e = launch_ring_inverse<T>(ring_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
+                                   (cpx<T>*)out, s);
       break;
     default:
       return SU2_ERR_INVALID_VALUE;

@@ -67,6 +67,16 @@ struct RingParams {
   int adjoint;              // inverse chain: 0 -> plain, 1 -> multiply by W_k
 };
 
+// Parameters of the register-resident ring FFT kernels (compile-time N).
+template <class T>
+struct FastRingParams {
+  int N, batch;
+  const cpx<T>* tw;   // e^{+i pi t / N}, t = 0..2N-1
+  const T* W;         // beta weights W_k
+  const int* bins;    // [q * N + p]: (pair << 2) | e with rho = i^e, or -1 if the bin is not retained
+  int adjoint;        // inverse chain: 0 -> plain, 1 -> multiply by W_k
+};
+
 // Parameters of the beta contraction kernels.
 template <class T>
 struct BetaParams {
@@ -95,6 +105,13 @@ hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const bf16x2_t
                                       cpx<float>* coeffs, hipStream_t s);
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const bf16x2_t* tab, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s);
+
+template <class T>
+bool fast_ring_supported(int N);
+template <class T>
+hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
+template <class T>
+hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s);
 
 // d-table generation: FP64 three-term recurrence in l, one thread per (pair, k).
 hipError_t launch_dtable(int B, int N, int npairs, const PairInfo* pairs, const double* beta, double* tab64,

@@ -1,0 +1,436 @@
+// Ring FFT (stage 1, Proposition 4.2 / Proposition 6.1) specialised at
+// compile time for N = N1 * N2 nodes per angle, held in registers.
+//
+// Each length-N transform is split four-step style: l = l1 + N1 l2,
+// q = q2 + N2 q1 (gamma) and j = j1 + N1 j2, p = p2 + N2 p1 (alpha):
+//   phase 1  radix-N2 DFT over l2, twiddle w^{q2 l1}          (thread: row j, l1)
+//   phase 2  radix-N1 DFT over l1 -> G[j][q2 + N2 q1]          (thread: j, q2)
+//   phase 3  radix-N2 DFT over j2 of G e^{2 pi i delta j2 / N2},
+//            twiddle e^{2 pi i (p2 + delta) j1 / N}             (thread: column q, j1)
+//   phase 4  radix-N1 DFT over j1 -> H[p2 + N2 p1][q]          (thread: q, p2)
+// with delta = 1/2 on odd q: the half-bin shift of half-integer n folded into
+// the alpha transform (sum_j G[j] e^{2 pi i (p + delta) j / N}).  Only the
+// output rows p1 in [0, N1/4) and [3 N1/4, N1) can hold retained bins
+// (|2n| <= B-1 with N = 2B), so the others are never formed.  Between phases
+// the data crosses LDS three times, each exchange in ROUNDS slices so that
+// the LDS buffer is 1/ROUNDS of the ring.  The inverse runs the phases in
+// reverse with conjugate roots and gathers its bins straight from the beta
+// stage output, so no LDS zero fill is needed.
+#include "su2fft_internal.h"
+
+namespace su2 {
+
+// multiply by e^{SIGN 2 pi i K / 16} for a compile-time K
+template <class T, int K, int SIGN>
+__device__ __forceinline__ cpx<T> rot16(cpx<T> a) {
+  constexpr int k = ((K % 16) + 16) % 16;
+  if constexpr (k == 0) return a;
+  else if constexpr (k == 4) return {-T(SIGN) * a.im, T(SIGN) * a.re};
+  else if constexpr (k == 8) return {-a.re, -a.im};
+  else if constexpr (k == 12) return {T(SIGN) * a.im, -T(SIGN) * a.re};
+  else {
+    constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                              0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    constexpr double s[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                              1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+    const T wr = T(c[k]), wi = T(SIGN) * T(s[k]);
+    return {a.re * wr - a.im * wi, a.re * wi + a.im * wr};
+  }
+}
+
+// In-register DFT of length R in {2, 4, 8, 16}: a[q] <- sum_n a[n] e^{SIGN 2 pi i q n / R}
+template <class T, int R, int SIGN>
+__device__ __forceinline__ void dftr(cpx<T>* a) {
+  if constexpr (R == 2) {
+    cpx<T> t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  } else if constexpr (R == 4) {
+    cpx<T> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    cpx<T> s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+    cpx<T> r13 = rot16<T, 4, SIGN>(d13);
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, r13);
+    a[3] = csub(d02, r13);
+  } else {
+    // R = 2 * H: even/odd split, twiddle e^{SIGN 2 pi i q / R} on the odd half
+    constexpr int H = R / 2;
+    cpx<T> e[H], o[H];
+#pragma unroll
+    for (int i = 0; i < H; i++) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
+    dftr<T, H, SIGN>(e);
+    dftr<T, H, SIGN>(o);
+#pragma unroll
+    for (int q = 0; q < H; q++) {
+      cpx<T> w;
+      // o[q] * e^{SIGN 2 pi i q / R}; 16 / R steps of 1/16 turn per q
+      switch (q * (16 / R)) {
+        case 0: w = o[q]; break;
+        case 1: w = rot16<T, 1, SIGN>(o[q]); break;
+        case 2: w = rot16<T, 2, SIGN>(o[q]); break;
+        case 3: w = rot16<T, 3, SIGN>(o[q]); break;
+        case 4: w = rot16<T, 4, SIGN>(o[q]); break;
+        case 5: w = rot16<T, 5, SIGN>(o[q]); break;
+        case 6: w = rot16<T, 6, SIGN>(o[q]); break;
+        default: w = rot16<T, 7, SIGN>(o[q]); break;
+      }
+      a[q] = cadd(e[q], w);
+      a[q + H] = csub(e[q], w);
+    }
+  }
+}
+
+template <int N1, int N2, int NT, int ROUNDS>
+struct FastGeom {
+  static constexpr int N = N1 * N2;
+  static constexpr int I1 = N * N1 / NT;   // phase 1 / 3 instances per thread
+  static constexpr int I2 = N * N2 / NT;   // phase 2 / 4 instances per thread
+  static constexpr int P1 = N + 1;         // exchange 1 pitch: Z[q2][l1][j]
+  static constexpr int P2 = N;             // exchange 2 pitch: G[q][j]
+  static constexpr int P3 = N1 + 1;        // exchange 3 pitch: Y[q][p2][j1]
+  static constexpr int Q2R = N2 / ROUNDS;  // q2 values per exchange-1 round
+  static constexpr int QR = N / ROUNDS;    // q values per exchange-2/3 round
+  static constexpr int BUF1 = Q2R * N1 * P1;
+  static constexpr int BUF2 = QR * P2;
+  static constexpr int BUF3 = QR * N2 * P3;
+  static constexpr int BUF = BUF1 > BUF2 ? (BUF1 > BUF3 ? BUF1 : BUF3) : (BUF2 > BUF3 ? BUF2 : BUF3);
+  static_assert(NT % N == 0 && NT % N1 == 0 && NT % N2 == 0, "thread count");
+  static_assert(N2 % ROUNDS == 0 && (N2 / ROUNDS) % (NT / N) == 0, "exchange-1 rounds align with phase-2 instances");
+  static_assert(QR % (NT / N1) == 0 && QR % N2 == 0, "exchange-2 rounds align with phase-3 instances");
+  static_assert(QR == NT / N2 * (I2 / ROUNDS) || I2 % ROUNDS == 0, "exchange-3 rounds align with phase-4 instances");
+  static_assert(N1 % 4 == 0, "alpha pruning");
+};
+
+template <class T>
+__device__ __forceinline__ cpx<T> ipow_mul(cpx<T> v, int e) {  // v * i^e
+  switch (e & 3) {
+    case 0: return v;
+    case 1: return {-v.im, v.re};
+    case 2: return {-v.re, -v.im};
+    default: return {v.im, -v.re};
+  }
+}
+
+// FP32 rings: two workgroups per CU (64 KB LDS slices, at most 128 VGPRs);
+// FP64 rings: one workgroup per CU.
+template <class T>
+constexpr int fast_waves_per_simd() { return sizeof(T) == 4 ? 4 : 2; }
+
+template <class T, int N1, int N2, int NT, int ROUNDS>
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S,
+                                                        FastRingParams<T> p) {
+  typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  constexpr int N = G::N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + G::BUF;  // e^{i pi t / N}, t = 0..2N-1
+  const int t = threadIdx.x;
+  const int ring = blockIdx.x;
+  const int b = ring / N, k = ring - b * N;
+  for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
+  const cpx<T>* x = samples + (size_t)ring * N * N;
+
+  // ---- phase 1: radix-N2 over l2 (coalesced rows: lanes run over l1)
+  const int l1 = t % N1;
+  cpx<T> a[G::I1][N2];
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+    const int j = t / N1 + (NT / N1) * s;
+#pragma unroll
+    for (int l2 = 0; l2 < N2; l2++) a[s][l2] = x[j * N + l1 + N1 * l2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+    dftr<T, N2, 1>(a[s]);
+#pragma unroll
+    for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmul(a[s][q2], tw[(2 * q2 * l1) % (2 * N)]);
+  }
+
+  // ---- exchange 1 (by q2 slices) and phase 2: radix-N1 over l1
+  const int jr = t % N;
+  cpx<T> c[G::I2][N1];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1; s++) {
+      const int j = t / N1 + (NT / N1) * s;
+#pragma unroll
+      for (int qq = 0; qq < G::Q2R; qq++) buf[(qq * N1 + l1) * G::P1 + j] = a[s][r * G::Q2R + qq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2 / ROUNDS; s++) {
+      const int si = r * (G::I2 / ROUNDS) + s;
+      const int q2 = t / N + (NT / N) * si;
+#pragma unroll
+      for (int m = 0; m < N1; m++) c[si][m] = buf[((q2 - r * G::Q2R) * N1 + m) * G::P1 + jr];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::I2; s++) dftr<T, N1, 1>(c[s]);   // c[s][q1] = G[jr][q2 + N2 q1]
+
+  // ---- exchange 2 (by q slices) and phase 3: radix-N2 over j2 with the half-bin shift
+  const int j1 = t % N1;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2; s++) {
+      const int q2 = t / N + (NT / N) * s;
+#pragma unroll
+      for (int q1 = r * (G::QR / N2); q1 < (r + 1) * (G::QR / N2); q1++)
+        buf[(q2 + N2 * q1 - r * G::QR) * G::P2 + jr] = c[s][q1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1 / ROUNDS; s++) {
+      const int si = r * (G::I1 / ROUNDS) + s;
+      const int q = t / N1 + (NT / N1) * si;
+#pragma unroll
+      for (int j2 = 0; j2 < N2; j2++) a[si][j2] = buf[(q - r * G::QR) * G::P2 + j1 + N1 * j2];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+    const int q = t / N1 + (NT / N1) * s;
+    const int odd = q & 1;
+    if (odd) {
+#pragma unroll
+      for (int j2 = 1; j2 < N2; j2++) a[s][j2] = cmul(a[s][j2], tw[j2 * N1]);   // e^{i pi j2 / N2}
+    }
+    dftr<T, N2, 1>(a[s]);
+#pragma unroll
+    for (int p2 = 0; p2 < N2; p2++) {
+      const int e = ((2 * p2 + odd) * j1) % (2 * N);                           // e^{2 pi i (p2 + delta) j1 / N}
+      if (e) a[s][p2] = cmul(a[s][p2], tw[e]);
+    }
+  }
+
+  // ---- exchange 3 (by q slices) and phase 4: radix-N1 over j1, pruned; epilogue
+  const int p2 = t % N2;
+  const T Wk = p.W[k];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1 / ROUNDS; s++) {
+      const int si = r * (G::I1 / ROUNDS) + s;
+      const int q = t / N1 + (NT / N1) * si;
+#pragma unroll
+      for (int pp = 0; pp < N2; pp++) buf[((q - r * G::QR) * N2 + pp) * G::P3 + j1] = a[si][pp];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2 / ROUNDS; s++) {
+      const int si = r * (G::I2 / ROUNDS) + s;
+      const int q = t / N2 + (NT / N2) * si;
+      cpx<T> h[N1];
+#pragma unroll
+      for (int m = 0; m < N1; m++) h[m] = buf[((q - r * G::QR) * N2 + p2) * G::P3 + m];
+      dftr<T, N1, 1>(h);
+#pragma unroll
+      for (int p1 = 0; p1 < N1; p1++) {
+        if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;  // never retained
+        const int pp = p2 + N2 * p1;
+        const int ent = p.bins[q * N + pp];
+        if (ent >= 0) {
+          const int pi = ent >> 2;
+          const int tile = pi / PT;
+          S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] = cscale(ipow_mul(h[p1], ent & 3), Wk);
+        }
+      }
+    }
+  }
+}
+
+template <class T, int N1, int N2, int NT, int ROUNDS>
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples,
+                                                        FastRingParams<T> p) {
+  typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  constexpr int N = G::N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + G::BUF;
+  const int t = threadIdx.x;
+  const int ring = blockIdx.x;
+  const int b = ring / N, k = ring - b * N;
+  for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
+  const T scale = p.adjoint ? p.W[k] : T(1);
+  const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
+
+  // ---- phase 4': gather the retained bins (times conj(rho) and the scale),
+  //      radix-N1 over p1 -> j1, twiddle e^{-2 pi i (p2 + delta) j1 / N}
+  cpx<T> h[G::I2][N1];
+#pragma unroll
+  for (int s = 0; s < G::I2; s++) {
+    const int q = t / N2 + (NT / N2) * s;
+#pragma unroll
+    for (int p1 = 0; p1 < N1; p1++) {
+      h[s][p1] = {T(0), T(0)};
+      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;
+      const int ent = p.bins[q * N + p2 + N2 * p1];
+      if (ent >= 0) {
+        const int pi = ent >> 2;
+        const int tile = pi / PT;
+        cpx<T> v = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
+        h[s][p1] = cscale(ipow_mul(v, 4 - (ent & 3)), scale);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < G::I2; s++) {
+    const int q = t / N2 + (NT / N2) * s;
+    const int odd = q & 1;
+    dftr<T, N1, -1>(h[s]);
+#pragma unroll
+    for (int m = 0; m < N1; m++) {
+      const int e = ((2 * p2 + odd) * m) % (2 * N);
+      if (e) h[s][m] = cmulc(h[s][m], tw[e]);
+    }
+  }
+
+  // ---- exchange 3' and phase 3': radix-N2 over p2 -> j2, times e^{-2 pi i delta j2 / N2}
+  cpx<T> a[G::I1][N2];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2 / ROUNDS; s++) {
+      const int si = r * (G::I2 / ROUNDS) + s;
+      const int q = t / N2 + (NT / N2) * si;
+#pragma unroll
+      for (int m = 0; m < N1; m++) buf[((q - r * G::QR) * N2 + p2) * G::P3 + m] = h[si][m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1 / ROUNDS; s++) {
+      const int si = r * (G::I1 / ROUNDS) + s;
+      const int q = t / N1 + (NT / N1) * si;
+#pragma unroll
+      for (int pp = 0; pp < N2; pp++) a[si][pp] = buf[((q - r * G::QR) * N2 + pp) * G::P3 + j1];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+    const int q = t / N1 + (NT / N1) * s;
+    dftr<T, N2, -1>(a[s]);
+    if (q & 1) {
+#pragma unroll
+      for (int j2 = 1; j2 < N2; j2++) a[s][j2] = cmulc(a[s][j2], tw[j2 * N1]);
+    }
+  }
+
+  // ---- exchange 2' and phase 2': radix-N1 over q1 -> l1, twiddle w^{-q2 l1}
+  cpx<T> c[G::I2][N1];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1 / ROUNDS; s++) {
+      const int si = r * (G::I1 / ROUNDS) + s;
+      const int q = t / N1 + (NT / N1) * si;
+#pragma unroll
+      for (int j2 = 0; j2 < N2; j2++) buf[(q - r * G::QR) * G::P2 + j1 + N1 * j2] = a[si][j2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2; s++) {
+      const int q2 = t / N + (NT / N) * s;
+#pragma unroll
+      for (int q1 = r * (G::QR / N2); q1 < (r + 1) * (G::QR / N2); q1++)
+        c[s][q1] = buf[(q2 + N2 * q1 - r * G::QR) * G::P2 + jr];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::I2; s++) {
+    const int q2 = t / N + (NT / N) * s;
+    dftr<T, N1, -1>(c[s]);
+#pragma unroll
+    for (int m = 1; m < N1; m++) {
+      const int e = (2 * q2 * m) % (2 * N);
+      if (e) c[s][m] = cmulc(c[s][m], tw[e]);
+    }
+  }
+
+  // ---- exchange 1' and phase 1': radix-N2 over q2 -> l2, coalesced store
+  cpx<T>* xo = samples + (size_t)ring * N * N;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I2 / ROUNDS; s++) {
+      const int si = r * (G::I2 / ROUNDS) + s;
+      const int q2 = t / N + (NT / N) * si;
+#pragma unroll
+      for (int m = 0; m < N1; m++) buf[((q2 - r * G::Q2R) * N1 + m) * G::P1 + jr] = c[si][m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < G::I1; s++) {
+      const int j = t / N1 + (NT / N1) * s;
+#pragma unroll
+      for (int qq = 0; qq < G::Q2R; qq++) a[s][r * G::Q2R + qq] = buf[(qq * N1 + l1) * G::P1 + j];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+    const int j = t / N1 + (NT / N1) * s;
+    dftr<T, N2, -1>(a[s]);
+#pragma unroll
+    for (int l2 = 0; l2 < N2; l2++) xo[j * N + l1 + N1 * l2] = a[s][l2];
+  }
+}
+
+template <class T, int N1, int N2, int NT, int ROUNDS>
+static size_t fast_smem() {
+  typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  return (size_t)(G::BUF + 2 * G::N) * sizeof(cpx<T>);
+}
+
+template <class T>
+bool fast_ring_supported(int N) {
+  return N == 128;
+}
+
+template <class T>
+hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s) {
+  constexpr int R = sizeof(T) == 8 ? 2 : 2;
+  auto kern = ring_forward_fast<T, 16, 8, 512, R>;
+  const size_t smem = fast_smem<T, 16, 8, 512, R>();
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(p.batch * p.N), dim3(512), smem, s, samples, S, p);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s) {
+  constexpr int R = sizeof(T) == 8 ? 2 : 2;
+  auto kern = ring_inverse_fast<T, 16, 8, 512, R>;
+  const size_t smem = fast_smem<T, 16, 8, 512, R>();
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(p.batch * p.N), dim3(512), smem, s, S, samples, p);
+  return hipGetLastError();
+}
+
+template bool fast_ring_supported<float>(int);
+template bool fast_ring_supported<double>(int);
+template hipError_t launch_ring_forward_fast<float>(const FastRingParams<float>&, const cpx<float>*, cpx<float>*,
+                                                    hipStream_t);
+template hipError_t launch_ring_forward_fast<double>(const FastRingParams<double>&, const cpx<double>*, cpx<double>*,
+                                                     hipStream_t);
+template hipError_t launch_ring_inverse_fast<float>(const FastRingParams<float>&, const cpx<float>*, cpx<float>*,
+                                                    hipStream_t);
+template hipError_t launch_ring_inverse_fast<double>(const FastRingParams<double>&, const cpx<double>*, cpx<double>*,
+                                                     hipStream_t);
+
+}  // namespace su2
