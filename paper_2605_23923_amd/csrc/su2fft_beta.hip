@@ -52,85 +52,163 @@ __device__ __forceinline__ long long coeff_index(int tl, int tm, int tn) {
   return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
 }
 
-constexpr int BT = 16;        // signals per workgroup (32 real columns)
-constexpr int KC = 16;        // beta nodes per LDS chunk (forward)
-constexpr int CPITCH = 2 * BT + 4;
+template <class T>
+struct BetaCfg;
+template <>
+struct BetaCfg<float> {
+  static constexpr int BT = 32;  // signals per workgroup (64 real columns)
+};
+template <>
+struct BetaCfg<double> {
+  static constexpr int BT = 16;  // 32 real columns
+};
 
-// Forward contraction.  Grid: (pair tiles, signal tiles).  Wave w owns pairs
-// w, w+4, w+8, w+12 of the tile; the tile's S slab streams through LDS in
-// chunks of KC nodes.
+constexpr int KC = 8;  // beta nodes per streamed chunk (forward)
+
+// Forward contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
+// pairs w and w + 8 of the tile.  The workgroup streams the tile's S slab and
+// table rows through LDS in chunks of KC nodes, fetching chunk c+1 into
+// registers (16-byte loads) while the matrix cores work on chunk c.
+constexpr int FWD_THREADS = 512;
+
 template <class T, int RTMAX>
-__global__ __launch_bounds__(GEMM_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
-                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
+__global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
+                                                                   cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   typedef typename acc4<T>::type accT;
-  __shared__ T lds[PT][KC][CPITCH];
+  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int PB = 2 * PT + 2;            // reals per (node, signal) row: 16 pairs x (re, im) + pad
+  constexpr int PK = BT * PB + 16;          // reals per node
+  constexpr int TMAX = PT * 16 * RTMAX;     // longest tile row
+  constexpr int VE = 16 / (int)sizeof(T);   // table elements per 16-byte load
+  constexpr int TV = (KC * TMAX) / VE + 2;  // 16-byte loads covering one table chunk
+  constexpr int TVT = (TV + FWD_THREADS - 1) / FWD_THREADS;
+  constexpr int VC = 16 / (int)sizeof(cpx<T>);            // complex values per 16-byte load
+  constexpr int SV = KC * BT * PT / VC;                     // 16-byte loads per S chunk
+  constexpr int SPT = SV / FWD_THREADS;
+  static_assert(SV % FWD_THREADS == 0, "chunk split");
+  __shared__ T sS[KC * PK];
+  __shared__ __align__(16) T sT[TVT * FWD_THREADS * VE];
+
   const int tile = blockIdx.x;
   const int b0 = blockIdx.y * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
+  const PairInfo p0 = p.pairs[tile * PT];
+  const int lsum = p0.lsum;
+  const long long tbase = p0.tab;                         // element offset of the tile block
+  const long long vlast = (tbase + (long long)N * lsum + VE - 1) / VE;   // one past the block's last vector
 
-  PairInfo pi[4];
+  PairInfo pi[2];
 #pragma unroll
-  for (int i = 0; i < 4; i++) pi[i] = p.pairs[tile * PT + wave + 4 * i];
+  for (int i = 0; i < 2; i++) pi[i] = p.pairs[tile * PT + wave + 8 * i];
 
-  accT acc[4][RTMAX][2];
+  accT acc[2][RTMAX][CT];
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+  for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++)
 #pragma unroll
-      for (int ct = 0; ct < 2; ct++)
+      for (int ct = 0; ct < CT; ct++)
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[i][rt][ct][r] = T(0);
 
-  const int lrow = lane & 15, lk = lane >> 4;
-  for (int k0 = 0; k0 < N; k0 += KC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < KC * BT * PT; e += GEMM_THREADS) {
-      const int pp = e % PT, bb = (e / PT) % BT, kk = e / (PT * BT);
-      const int k = k0 + kk;
-      cpx<T> v = {T(0), T(0)};
-      if (k < N && bb < nb) v = S[(((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pp];
-      lds[pp][kk][2 * bb] = v.re;
-      lds[pp][kk][2 * bb + 1] = v.im;
-    }
-    __syncthreads();
+  float4 sreg[SPT];
+  float4 treg[TVT];
+  const float4* tabv = reinterpret_cast<const float4*>(p.tab);
+  long long tv0 = 0;  // first table vector of the chunk held in sT
+  auto fetch = [&](int k0, long long& vstart) {
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < SPT; i++) {
+      const int v = threadIdx.x + FWD_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+      const int k = k0 + kk;
+      if (k < N && bb < nb)
+        sreg[i] = *reinterpret_cast<const float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
+      else
+        sreg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    vstart = (tbase + (long long)k0 * lsum) / VE;
+#pragma unroll
+    for (int i = 0; i < TVT; i++) {
+      const long long v = vstart + threadIdx.x + FWD_THREADS * i;
+      if (threadIdx.x + FWD_THREADS * i < TV && v < vlast) treg[i] = tabv[v];
+      else treg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+      const int v = threadIdx.x + FWD_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+      const T* src = reinterpret_cast<const T*>(&sreg[i]);
+#pragma unroll
+      for (int q = 0; q < 2 * VC; q++) sS[kk * PK + bb * PB + 2 * pv * VC + q] = src[q];
+    }
+#pragma unroll
+    for (int i = 0; i < TVT; i++)
+      reinterpret_cast<float4*>(sT)[threadIdx.x + FWD_THREADS * i] = treg[i];
+  };
+
+  const int nchunk = (N + KC - 1) / KC;
+  long long vnext = 0;
+  fetch(0, tv0);
+  commit();
+  for (int c = 0; c < nchunk; c++) {
+    __syncthreads();
+    if (c + 1 < nchunk) fetch((c + 1) * KC, vnext);
+    // position of this chunk's first table element inside sT
+    const int toff = (int)(tbase + (long long)c * KC * lsum - tv0 * VE);
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
       const int L = pi[i].L;
       if (L == 0) continue;
-      const int pp = wave + 4 * i;
-      const T* tab = p.tab + pi[i].tab;
+      const int pp = wave + 8 * i;
+      const int coff = pi[i].coff;
+#pragma unroll
       for (int ks = 0; ks < KC; ks += 4) {
-        const int k = k0 + ks + lk;
-        T bop0 = lds[pp][ks + lk][lrow];
-        T bop1 = lds[pp][ks + lk][16 + lrow];
+        const int kk = ks + lk;
+        const bool kin = c * KC + kk < N;
+        T bop[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          const int cc = ct * 16 + lrow;  // column: signal cc / 2, re/im cc % 2
+          bop[ct] = sS[kk * PK + (cc >> 1) * PB + 2 * pp + (cc & 1)];
+        }
 #pragma unroll
         for (int rt = 0; rt < RTMAX; rt++) {
           if (rt * 16 < L) {
             const int l = rt * 16 + lrow;
-            T a = (l < L && k < N) ? tab[(size_t)k * L + l] : T(0);
-            acc[i][rt][0] = mfma16x16x4(a, bop0, acc[i][rt][0]);
-            acc[i][rt][1] = mfma16x16x4(a, bop1, acc[i][rt][1]);
+            const T a = (l < L && kin) ? sT[toff + kk * lsum + coff + l] : T(0);
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = mfma16x16x4(a, bop[ct], acc[i][rt][ct]);
           }
         }
       }
     }
+    __syncthreads();
+    if (c + 1 < nchunk) {
+      commit();
+      tv0 = vnext;
+    }
   }
+
   // epilogue: scatter into the 2l-major coefficient layout
   T* out = reinterpret_cast<T*>(coeffs);
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < 2; i++) {
     const int L = pi[i].L;
     if (L == 0) continue;
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++) {
       if (rt * 16 >= L) continue;
 #pragma unroll
-      for (int ct = 0; ct < 2; ct++) {
-        const int c = ct * 16 + lrow;
-        const int bb = c >> 1, reim = c & 1;
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
         if (bb >= nb) continue;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -145,12 +223,20 @@ __global__ __launch_bounds__(GEMM_THREADS) void beta_forward_kernel(const cpx<T>
   }
 }
 
-// Inverse contraction.  Wave w handles pairs w, w+4, ... of the tile one at a
-// time; the N output rows are produced in groups of 4 row blocks (64 nodes).
-template <class T>
-__global__ __launch_bounds__(GEMM_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
-                                                                    cpx<T>* __restrict__ S, BetaParams<T> p) {
+// Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
+// pairs w and w + 8.  Each wave keeps its pairs' scaled coefficients as
+// matrix-core B operands in registers, then sweeps the N nodes in blocks of
+// 16; a block's outputs for all 16 pairs are gathered in LDS and written as
+// full PT-pair rows of S.
+constexpr int INV_THREADS = 512;
+
+template <class T, int LQ>
+__global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
+                                                                   cpx<T>* __restrict__ S, BetaParams<T> p) {
   typedef typename acc4<T>::type accT;
+  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int PB = 2 * PT + 2;  // reals per (node, signal) row in the staging buffer
+  __shared__ T stage[16 * BT * PB];
   const int tile = blockIdx.x;
   const int b0 = blockIdx.y * BT;
   const int nb = min(BT, p.batch - b0);
@@ -158,81 +244,110 @@ __global__ __launch_bounds__(GEMM_THREADS) void beta_inverse_kernel(const cpx<T>
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
   const T* cin = reinterpret_cast<const T*>(coeffs);
-  T* sout = reinterpret_cast<T*>(S);
-  for (int i = 0; i < 4; i++) {
-    const int pp = wave + 4 * i;
-    const PairInfo pi = p.pairs[tile * PT + pp];
-    const int L = pi.L;
-    if (L == 0) continue;
-    const T* tab = p.tab + pi.tab;
-    // B operand column of this lane: signal bb, re/im
-    const int c0 = lrow;  // columns c0 and 16 + c0
-    for (int kt0 = 0; kt0 < N; kt0 += 64) {
-      accT acc[4][2];
+  const PairInfo p0 = p.pairs[tile * PT];
+  const int lsum = p0.lsum;
+  const T* tabt = p.tab + p0.tab;
+
+  PairInfo pi[2];
+  T bop[2][LQ][CT];
 #pragma unroll
-      for (int t = 0; t < 4; t++)
+  for (int q = 0; q < 2; q++) {
+    pi[q] = p.pairs[tile * PT + wave + 8 * q];
 #pragma unroll
-        for (int ct = 0; ct < 2; ct++)
+    for (int s = 0; s < LQ; s++) {
+      const int l = 4 * s + lk;
 #pragma unroll
-          for (int r = 0; r < 4; r++) acc[t][ct][r] = T(0);
-      for (int l0 = 0; l0 < L; l0 += 4) {
-        const int l = l0 + lk;
-        T bop[2];
-#pragma unroll
-        for (int ct = 0; ct < 2; ct++) {
-          const int c = ct * 16 + c0;
-          const int bb = c >> 1, reim = c & 1;
-          T v = T(0);
-          if (l < L && bb < nb) {
-            const int tl = pi.tl0 + 2 * l;
-            const long long idx = coeff_index(tl, pi.tm, pi.tn);
-            const T s = p.scale_mode == 0 ? T(tl + 1) : T(1);
-            v = s * cin[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim];
-          }
-          bop[ct] = v;
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+        T v = T(0);
+        if (l < pi[q].L && bb < nb) {
+          const int tl = pi[q].tl0 + 2 * l;
+          const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
+          const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
+          v = sc * cin[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim];
         }
+        bop[q][s][ct] = v;
+      }
+    }
+  }
+
+  for (int k0 = 0; k0 < N; k0 += 16) {
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const int k = kt0 + t * 16 + lrow;
-          T a = (l < L && k < N) ? tab[(size_t)k * L + l] : T(0);
-          acc[t][0] = mfma16x16x4(a, bop[0], acc[t][0]);
-          acc[t][1] = mfma16x16x4(a, bop[1], acc[t][1]);
+    for (int q = 0; q < 2; q++) {
+      const int L = pi[q].L;
+      const int pp = wave + 8 * q;
+      accT acc[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[ct][r] = T(0);
+      const int k = k0 + lrow;
+      const T* trow = tabt + (size_t)k * lsum + pi[q].coff;
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+        if (4 * s < L) {
+          const int l = 4 * s + lk;
+          const T a = (l < L && k < N) ? trow[l] : T(0);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) acc[ct] = mfma16x16x4(a, bop[q][s][ct], acc[ct]);
         }
       }
 #pragma unroll
-      for (int t = 0; t < 4; t++)
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
 #pragma unroll
-        for (int ct = 0; ct < 2; ct++) {
-          const int c = ct * 16 + lrow;
-          const int bb = c >> 1, reim = c & 1;
-          if (bb >= nb) continue;
-#pragma unroll
-          for (int r = 0; r < 4; r++) {
-            const int k = kt0 + t * 16 + acc_row<T>(lane, r);
-            if (k < N) sout[((((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pp) * 2 + reim] = acc[t][ct][r];
-          }
-        }
+        for (int r = 0; r < 4; r++) stage[(acc_row<T>(lane, r) * BT + bb) * PB + 2 * pp + reim] = acc[ct][r];
+      }
     }
+    __syncthreads();
+    // write the block: rows (node, signal) of PT pairs, 16 bytes per thread-store
+    constexpr int VC = 16 / (int)sizeof(cpx<T>);
+    for (int v = threadIdx.x; v < 16 * BT * (PT / VC); v += INV_THREADS) {
+      const int row = v / (PT / VC), pv = v - row * (PT / VC);
+      const int kk = row / BT, bb = row - kk * BT;
+      const int k = k0 + kk;
+      if (k < N && bb < nb) {
+        const T* src = stage + row * PB + 2 * pv * VC;
+        float4 w;
+        T* wd = reinterpret_cast<T*>(&w);
+#pragma unroll
+        for (int q = 0; q < 2 * VC; q++) wd[q] = src[q];
+        *reinterpret_cast<float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC) = w;
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
+  constexpr int BT = BetaCfg<T>::BT;
   dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
   const int lmax = (p.B + 1) / 2;
   if (lmax <= 16)
-    hipLaunchKernelGGL((beta_forward_kernel<T, 1>), grid, dim3(GEMM_THREADS), 0, s, S, coeffs, p);
+    hipLaunchKernelGGL((beta_forward_kernel<T, 1>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
   else if (lmax <= 32)
-    hipLaunchKernelGGL((beta_forward_kernel<T, 2>), grid, dim3(GEMM_THREADS), 0, s, S, coeffs, p);
+    hipLaunchKernelGGL((beta_forward_kernel<T, 2>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
   else
-    hipLaunchKernelGGL((beta_forward_kernel<T, 4>), grid, dim3(GEMM_THREADS), 0, s, S, coeffs, p);
+    hipLaunchKernelGGL((beta_forward_kernel<T, 4>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
+  constexpr int BT = BetaCfg<T>::BT;
   dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
-  hipLaunchKernelGGL(beta_inverse_kernel<T>, grid, dim3(GEMM_THREADS), 0, s, coeffs, S, p);
+  const int lmax = (p.B + 1) / 2;
+  if (lmax <= 8)
+    hipLaunchKernelGGL((beta_inverse_kernel<T, 2>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
+  else if (lmax <= 16)
+    hipLaunchKernelGGL((beta_inverse_kernel<T, 4>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
+  else if (lmax <= 32)
+    hipLaunchKernelGGL((beta_inverse_kernel<T, 8>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
+  else
+    hipLaunchKernelGGL((beta_inverse_kernel<T, 16>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
   return hipGetLastError();
 }
 

@@ -244,8 +244,9 @@ su2_status_t build_plan(su2_plan_s* pl) {
         pi.tm = tm; pi.tn = tn;
         pi.tl0 = abs(tm) > abs(tn) ? abs(tm) : abs(tn);
         pi.L = (B - 1 - pi.tl0) / 2 + 1;
-        pi.tab = tab;
-        tab += (long long)N * pi.L;
+        pi.tab = 0;
+        pi.lsum = 0;
+        pi.coff = 0;
         pairs.push_back(pi);
         const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
         const int jrow = dif_position(palpha, N, pl->rad_n, pl->nrad_n);
@@ -261,10 +262,17 @@ su2_status_t build_plan(su2_plan_s* pl) {
   pl->ntiles = pl->P_pad / PT;
   while ((int)pairs.size() < pl->P_pad) {
     PairInfo pi;
-    pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0;
+    pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0; pi.lsum = 0; pi.coff = 0;
     pairs.push_back(pi);
     fftpos.push_back(0);
     rho_e.push_back(0);
+  }
+  // tile-major table blocks
+  for (int t0 = 0; t0 < pl->P_pad; t0 += PT) {
+    int lsum = 0;
+    for (int i = 0; i < PT; i++) { pairs[t0 + i].coff = lsum; lsum += pairs[t0 + i].L; }
+    for (int i = 0; i < PT; i++) { pairs[t0 + i].tab = tab; pairs[t0 + i].lsum = lsum; }
+    tab += (long long)N * lsum;
   }
   pl->tab_elems = tab;
   pl->h_pairs = pairs;
@@ -297,7 +305,8 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+  // tables are padded by 64 bytes: the contraction kernels read whole 16-byte vectors
+  if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_pairs, pairs.data(), sizeof(PairInfo) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipMemcpy(pl->d_fftpos, fftpos.data(), sizeof(int) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
@@ -314,10 +323,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
 
   if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
   if (pl->dtype == SU2_C64) {
-    if ((e = pl->alloc((void**)&pl->d_tab32, sizeof(float) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+    if ((e = pl->alloc((void**)&pl->d_tab32, sizeof(float) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_round_table_f32(tab, pl->d_tab64, pl->d_tab32, 0)) != hipSuccess) return hip_fail(e);
   } else if (pl->dtype == SU2_C64_BF16X3) {
-    if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab)) != hipSuccess) return hip_fail(e);
+    if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_split_table_bf16(tab, pl->d_tab64, pl->d_tabbf, 0)) != hipSuccess) return hip_fail(e);
   }
   if ((e = pl->alloc(&pl->d_S, cb * (size_t)pl->P_pad * N * pl->batch)) != hipSuccess) return hip_fail(e);
@@ -507,9 +516,12 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
     if (pi.tm != two_m || pi.tn != two_n) continue;
     if (L) *L = pi.L;
     if (host_out) {
-      hipError_t e = hipMemcpy(host_out, plan->d_tab64 + pi.tab, sizeof(double) * (size_t)plan->N * pi.L,
+      std::vector<double> rows((size_t)plan->N * pi.lsum);
+      hipError_t e = hipMemcpy(rows.data(), plan->d_tab64 + pi.tab, sizeof(double) * rows.size(),
                                hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(e);
+      for (int k = 0; k < plan->N; k++)
+        for (int i = 0; i < pi.L; i++) host_out[(size_t)k * pi.L + i] = rows[(size_t)k * pi.lsum + pi.coff + i];
     }
     return SU2_OK;
   }

@@ -39,12 +39,17 @@ __host__ __device__ inline cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re
 template <class T>
 __host__ __device__ inline cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
 
-// Per-pair data used by the beta contraction.
+// Per-pair data used by the beta contraction.  The Wigner-d table is stored
+// tile-major: the PT pairs of a tile share rows k of length lsum = sum of
+// their L, so that the table slice of one tile and one node range is a single
+// contiguous block:  d^{l0 + i}_{nm}(beta_k) = tab[tab + k * lsum + coff + i].
 struct PairInfo {
   int tm, tn;     // doubled m, n
   int tl0;        // doubled lowest degree: max(|tm|, |tn|)
   int L;          // number of degrees l (0 for padding pairs)
-  long long tab;  // offset of the pair's table block [k][L] (in table elements)
+  long long tab;  // offset of the pair's tile block (in table elements)
+  int lsum;       // row length of the tile block
+  int coff;       // column offset of this pair inside a row
 };
 
 // Parameters of the ring-FFT kernels (one workgroup per ring (signal, k)).
@@ -83,7 +88,7 @@ struct BetaParams {
   int B, N, batch, ntiles;
   long long ncoef;          // coefficients per signal
   const PairInfo* pairs;
-  const T* tab;             // Wigner-d table, per pair [k][L]
+  const T* tab;             // Wigner-d table, tile-major (see PairInfo)
   int scale_mode;           // inverse: 0 -> (2l+1) weights, 1 -> none (adjoint)
 };
 

@@ -29,7 +29,7 @@ __device__ double binom_d(int n, int k) {
   return r;
 }
 
-// table layout: per pair, [k][L] at offset pairs[p].tab
+// table layout: tile-major, d^{l0+i}(beta_k) at pairs[p].tab + k * lsum + coff + i
 __global__ void dtable_kernel(int B, int N, int npairs, const PairInfo* __restrict__ pairs,
                               const double* __restrict__ beta, double* __restrict__ tab) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -57,7 +57,7 @@ __global__ void dtable_kernel(int B, int N, int npairs, const PairInfo* __restri
   }
   double dl = sgn * sqrt(binom_d(t0, top)) * pow(ch, (double)pc) * pow(sh, (double)ps);
   double dlm1 = 0.0;
-  double* out = tab + pi.tab + (long long)k * pi.L;
+  double* out = tab + pi.tab + (long long)k * pi.lsum + pi.coff;
   out[0] = dl;
   const double a = 0.5 * ta, b = 0.5 * tb;
   for (int i = 1; i < pi.L; i++) {
