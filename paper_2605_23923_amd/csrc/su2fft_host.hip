@@ -119,6 +119,7 @@ struct su2_plan_s {
   int* d_colq = nullptr;
   int* d_bins = nullptr;
   bool fast = false;
+  int rbeg[FAST_ROUNDS] = {0}, rend[FAST_ROUNDS] = {0};
   void* d_rho = nullptr;
   void* d_tw = nullptr;
   void* d_W = nullptr;
@@ -164,6 +165,7 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   r.W = (const T*)pl->d_W;
   r.bins = pl->d_bins;
   r.adjoint = adjoint;
+  for (int i = 0; i < FAST_ROUNDS; i++) { r.rbeg[i] = pl->rbeg[i]; r.rend[i] = pl->rend[i]; }
   return r;
 }
 
@@ -222,6 +224,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
     if (need <= (size_t)max_lds) { split = s; break; }
   }
   if (split == 0) return SU2_ERR_UNSUPPORTED;
+  // the register-resident ring kernels handle the whole ring themselves and
+  // want the pairs ordered by 2m alone
+  pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
+  if (pl->fast) split = 1;
   pl->split = split;
   pl->Nc = N / split;
   pl->nrad_c = radix_plan(pl->Nc, pl->rad_c);
@@ -276,15 +282,21 @@ su2_status_t build_plan(su2_plan_s* pl) {
   }
   pl->tab_elems = tab;
   pl->h_pairs = pairs;
-  // bin -> pair map for the register-resident ring kernels
-  pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
+  // bin -> pair map for the register-resident ring kernels, and the pair range
+  // of each slice of q values they process together
   std::vector<int> bins((size_t)N * N, -1);
+  for (int r = 0; r < FAST_ROUNDS; r++) { pl->rbeg[r] = pl->P; pl->rend[r] = 0; }
   for (int pidx = 0; pidx < pl->P; pidx++) {
     const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
     const int q = imod(tm, N);
     const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
     bins[(size_t)q * N + palpha] = (pidx << 2) | rho_e[pidx];
+    const int r = q / (N / FAST_ROUNDS);
+    pl->rbeg[r] = pidx < pl->rbeg[r] ? pidx : pl->rbeg[r];
+    pl->rend[r] = pidx + 1 > pl->rend[r] ? pidx + 1 : pl->rend[r];
   }
+  for (int r = 0; r < FAST_ROUNDS; r++)
+    if (pl->rend[r] < pl->rbeg[r]) pl->rbeg[r] = pl->rend[r] = 0;
   std::vector<int> colq(pl->Nc);
   for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
 

@@ -72,7 +72,10 @@ struct RingParams {
   int adjoint;              // inverse chain: 0 -> plain, 1 -> multiply by W_k
 };
 
-// Parameters of the register-resident ring FFT kernels (compile-time N).
+// Parameters of the register-resident ring FFT kernels (compile-time N).  The
+// kernels process the gamma frequencies q in FAST_ROUNDS equal slices; the
+// retained pairs of slice r occupy the index range [rbeg[r], rend[r]).
+constexpr int FAST_ROUNDS = 2;
 template <class T>
 struct FastRingParams {
   int N, batch;
@@ -80,6 +83,7 @@ struct FastRingParams {
   const T* W;         // beta weights W_k
   const int* bins;    // [q * N + p]: (pair << 2) | e with rho = i^e, or -1 if the bin is not retained
   int adjoint;        // inverse chain: 0 -> plain, 1 -> multiply by W_k
+  int rbeg[FAST_ROUNDS], rend[FAST_ROUNDS];
 };
 
 // Parameters of the beta contraction kernels.

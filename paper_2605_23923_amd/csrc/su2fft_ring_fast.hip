@@ -121,11 +121,20 @@ __device__ __forceinline__ cpx<T> ipow_mul(cpx<T> v, int e) {  // v * i^e
 template <class T>
 constexpr int fast_waves_per_simd() { return sizeof(T) == 4 ? 4 : 2; }
 
+// multiply by e^{i pi j / N2} (the half-bin shift at node j of an N2-point
+// transform) with the root as a compile-time constant
+template <class T, int N2, int J, int SIGN>
+__device__ __forceinline__ cpx<T> halfbin(cpx<T> a) {
+  static_assert(16 % (2 * N2) == 0, "half-bin roots of an N2-point transform are 16th roots");
+  return rot16<T, J * (16 / (2 * N2)), SIGN>(a);
+}
+
 template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S,
-                                                        FastRingParams<T> p) {
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(
+    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
+  static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;  // e^{i pi t / N}, t = 0..2N-1
@@ -145,11 +154,14 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fas
     for (int l2 = 0; l2 < N2; l2++) a[s][l2] = x[j * N + l1 + N1 * l2];
   }
   __syncthreads();
+  cpx<T> tw1[N2];  // w^{q2 l1}: this thread's l1 is the same in every instance
+#pragma unroll
+  for (int q2 = 1; q2 < N2; q2++) tw1[q2] = tw[(2 * q2 * l1) % (2 * N)];
 #pragma unroll
   for (int s = 0; s < G::I1; s++) {
     dftr<T, N2, 1>(a[s]);
 #pragma unroll
-    for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmul(a[s][q2], tw[(2 * q2 * l1) % (2 * N)]);
+    for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmul(a[s][q2], tw1[q2]);
   }
 
   // ---- exchange 1 (by q2 slices) and phase 2: radix-N1 over l1
@@ -178,6 +190,11 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fas
 
   // ---- exchange 2 (by q slices) and phase 3: radix-N2 over j2 with the half-bin shift
   const int j1 = t % N1;
+  // every phase-3 instance of this thread has q of the same parity: (t / N1) & 1
+  const int odd = (t / N1) & 1;
+  cpx<T> tw3[N2];  // e^{2 pi i (p2 + delta) j1 / N}
+#pragma unroll
+  for (int p2 = 0; p2 < N2; p2++) tw3[p2] = tw[((2 * p2 + odd) * j1) % (2 * N)];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
     __syncthreads();
@@ -199,21 +216,26 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fas
   }
 #pragma unroll
   for (int s = 0; s < G::I1; s++) {
-    const int q = t / N1 + (NT / N1) * s;
-    const int odd = q & 1;
     if (odd) {
-#pragma unroll
-      for (int j2 = 1; j2 < N2; j2++) a[s][j2] = cmul(a[s][j2], tw[j2 * N1]);   // e^{i pi j2 / N2}
+      a[s][1] = halfbin<T, N2, 1, 1>(a[s][1]);
+      if constexpr (N2 > 2) {
+        a[s][2] = halfbin<T, N2, 2, 1>(a[s][2]);
+        a[s][3] = halfbin<T, N2, 3, 1>(a[s][3]);
+      }
+      if constexpr (N2 > 4) {
+        a[s][4] = halfbin<T, N2, 4, 1>(a[s][4]);
+        a[s][5] = halfbin<T, N2, 5, 1>(a[s][5]);
+        a[s][6] = halfbin<T, N2, 6, 1>(a[s][6]);
+        a[s][7] = halfbin<T, N2, 7, 1>(a[s][7]);
+      }
     }
     dftr<T, N2, 1>(a[s]);
 #pragma unroll
-    for (int p2 = 0; p2 < N2; p2++) {
-      const int e = ((2 * p2 + odd) * j1) % (2 * N);                           // e^{2 pi i (p2 + delta) j1 / N}
-      if (e) a[s][p2] = cmul(a[s][p2], tw[e]);
-    }
+    for (int p2 = 0; p2 < N2; p2++) a[s][p2] = cmul(a[s][p2], tw3[p2]);
   }
 
-  // ---- exchange 3 (by q slices) and phase 4: radix-N1 over j1, pruned; epilogue
+  // ---- exchange 3 (by q slices), phase 4: radix-N1 over j1 (pruned), and the
+  //      epilogue through LDS so that S is written in whole PT-pair rows
   const int p2 = t % N2;
   const T Wk = p.W[k];
 #pragma unroll
@@ -227,34 +249,34 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fas
       for (int pp = 0; pp < N2; pp++) buf[((q - r * G::QR) * N2 + pp) * G::P3 + j1] = a[si][pp];
     }
     __syncthreads();
+    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
+    const int q = t / N2 + (NT / N2) * r;
+    cpx<T> h[N1];
 #pragma unroll
-    for (int s = 0; s < G::I2 / ROUNDS; s++) {
-      const int si = r * (G::I2 / ROUNDS) + s;
-      const int q = t / N2 + (NT / N2) * si;
-      cpx<T> h[N1];
+    for (int m = 0; m < N1; m++) h[m] = buf[((q - r * G::QR) * N2 + p2) * G::P3 + m];
+    __syncthreads();
+    dftr<T, N1, 1>(h);
+    const int pb = p.rbeg[r], pe = p.rend[r];
 #pragma unroll
-      for (int m = 0; m < N1; m++) h[m] = buf[((q - r * G::QR) * N2 + p2) * G::P3 + m];
-      dftr<T, N1, 1>(h);
-#pragma unroll
-      for (int p1 = 0; p1 < N1; p1++) {
-        if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;  // never retained
-        const int pp = p2 + N2 * p1;
-        const int ent = p.bins[q * N + pp];
-        if (ent >= 0) {
-          const int pi = ent >> 2;
-          const int tile = pi / PT;
-          S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] = cscale(ipow_mul(h[p1], ent & 3), Wk);
-        }
-      }
+    for (int p1 = 0; p1 < N1; p1++) {
+      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;  // never retained
+      const int ent = p.bins[q * N + p2 + N2 * p1];
+      if (ent >= 0) buf[(ent >> 2) - pb] = cscale(ipow_mul(h[p1], ent & 3), Wk);
+    }
+    __syncthreads();
+    for (int pi = pb + t; pi < pe; pi += NT) {
+      const int tile = pi / PT;
+      S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] = buf[pi - pb];
     }
   }
 }
 
 template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples,
-                                                        FastRingParams<T> p) {
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
+    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
+  static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;
@@ -265,70 +287,69 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fas
   const T scale = p.adjoint ? p.W[k] : T(1);
   const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
 
-  // ---- phase 4': gather the retained bins (times conj(rho) and the scale),
-  //      radix-N1 over p1 -> j1, twiddle e^{-2 pi i (p2 + delta) j1 / N}
-  cpx<T> h[G::I2][N1];
-#pragma unroll
-  for (int s = 0; s < G::I2; s++) {
-    const int q = t / N2 + (NT / N2) * s;
-#pragma unroll
-    for (int p1 = 0; p1 < N1; p1++) {
-      h[s][p1] = {T(0), T(0)};
-      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;
-      const int ent = p.bins[q * N + p2 + N2 * p1];
-      if (ent >= 0) {
-        const int pi = ent >> 2;
-        const int tile = pi / PT;
-        cpx<T> v = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
-        h[s][p1] = cscale(ipow_mul(v, 4 - (ent & 3)), scale);
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < G::I2; s++) {
-    const int q = t / N2 + (NT / N2) * s;
-    const int odd = q & 1;
-    dftr<T, N1, -1>(h[s]);
-#pragma unroll
-    for (int m = 0; m < N1; m++) {
-      const int e = ((2 * p2 + odd) * m) % (2 * N);
-      if (e) h[s][m] = cmulc(h[s][m], tw[e]);
-    }
-  }
-
-  // ---- exchange 3' and phase 3': radix-N2 over p2 -> j2, times e^{-2 pi i delta j2 / N2}
+  // ---- per round: bring the slice's retained bins into LDS in whole rows,
+  //      gather, phase 4' (radix-N1 over p1 -> j1), exchange 3' (write)
   cpx<T> a[G::I1][N2];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
+    const int pb = p.rbeg[r], pe = p.rend[r];
     __syncthreads();
-#pragma unroll
-    for (int s = 0; s < G::I2 / ROUNDS; s++) {
-      const int si = r * (G::I2 / ROUNDS) + s;
-      const int q = t / N2 + (NT / N2) * si;
-#pragma unroll
-      for (int m = 0; m < N1; m++) buf[((q - r * G::QR) * N2 + p2) * G::P3 + m] = h[si][m];
+    for (int pi = pb + t; pi < pe; pi += NT) {
+      const int tile = pi / PT;
+      buf[pi - pb] = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
     }
     __syncthreads();
+    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
+    const int q = t / N2 + (NT / N2) * r;
+    cpx<T> h[N1];
+#pragma unroll
+    for (int p1 = 0; p1 < N1; p1++) {
+      h[p1] = {T(0), T(0)};
+      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;
+      const int ent = p.bins[q * N + p2 + N2 * p1];
+      if (ent >= 0) h[p1] = cscale(ipow_mul(buf[(ent >> 2) - pb], 4 - (ent & 3)), scale);
+    }
+    dftr<T, N1, -1>(h);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N1; m++) buf[((q - r * G::QR) * N2 + p2) * G::P3 + m] = h[m];
+    __syncthreads();
+    // exchange 3' (read) for the phase-3' instances of this round
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int q = t / N1 + (NT / N1) * si;
+      const int qq = t / N1 + (NT / N1) * si;
 #pragma unroll
-      for (int pp = 0; pp < N2; pp++) a[si][pp] = buf[((q - r * G::QR) * N2 + pp) * G::P3 + j1];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < G::I1; s++) {
-    const int q = t / N1 + (NT / N1) * s;
-    dftr<T, N2, -1>(a[s]);
-    if (q & 1) {
-#pragma unroll
-      for (int j2 = 1; j2 < N2; j2++) a[s][j2] = cmulc(a[s][j2], tw[j2 * N1]);
+      for (int pp = 0; pp < N2; pp++) a[si][pp] = buf[((qq - r * G::QR) * N2 + pp) * G::P3 + j1];
     }
   }
 
-  // ---- exchange 2' and phase 2': radix-N1 over q1 -> l1, twiddle w^{-q2 l1}
+  // ---- phase 3': conj twiddle, radix-N2 over p2 -> j2, times e^{-2 pi i delta j2 / N2}
+  const int odd = (t / N1) & 1;
+  cpx<T> tw3[N2];
+#pragma unroll
+  for (int pp = 0; pp < N2; pp++) tw3[pp] = tw[((2 * pp + odd) * j1) % (2 * N)];
+#pragma unroll
+  for (int s = 0; s < G::I1; s++) {
+#pragma unroll
+    for (int pp = 0; pp < N2; pp++) a[s][pp] = cmulc(a[s][pp], tw3[pp]);
+    dftr<T, N2, -1>(a[s]);
+    if (odd) {
+      a[s][1] = halfbin<T, N2, 1, -1>(a[s][1]);
+      if constexpr (N2 > 2) {
+        a[s][2] = halfbin<T, N2, 2, -1>(a[s][2]);
+        a[s][3] = halfbin<T, N2, 3, -1>(a[s][3]);
+      }
+      if constexpr (N2 > 4) {
+        a[s][4] = halfbin<T, N2, 4, -1>(a[s][4]);
+        a[s][5] = halfbin<T, N2, 5, -1>(a[s][5]);
+        a[s][6] = halfbin<T, N2, 6, -1>(a[s][6]);
+        a[s][7] = halfbin<T, N2, 7, -1>(a[s][7]);
+      }
+    }
+  }
+
+  // ---- exchange 2' and phase 2': radix-N1 over q1 -> l1
   cpx<T> c[G::I2][N1];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
@@ -350,17 +371,12 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fas
     }
   }
 #pragma unroll
-  for (int s = 0; s < G::I2; s++) {
-    const int q2 = t / N + (NT / N) * s;
-    dftr<T, N1, -1>(c[s]);
-#pragma unroll
-    for (int m = 1; m < N1; m++) {
-      const int e = (2 * q2 * m) % (2 * N);
-      if (e) c[s][m] = cmulc(c[s][m], tw[e]);
-    }
-  }
+  for (int s = 0; s < G::I2; s++) dftr<T, N1, -1>(c[s]);
 
-  // ---- exchange 1' and phase 1': radix-N2 over q2 -> l2, coalesced store
+  // ---- exchange 1', conj twiddle w^{-q2 l1}, phase 1': radix-N2 over q2 -> l2, coalesced store
+  cpx<T> tw1[N2];
+#pragma unroll
+  for (int q2 = 1; q2 < N2; q2++) tw1[q2] = tw[(2 * q2 * l1) % (2 * N)];
   cpx<T>* xo = samples + (size_t)ring * N * N;
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
@@ -383,6 +399,8 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fas
 #pragma unroll
   for (int s = 0; s < G::I1; s++) {
     const int j = t / N1 + (NT / N1) * s;
+#pragma unroll
+    for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmulc(a[s][q2], tw1[q2]);
     dftr<T, N2, -1>(a[s]);
 #pragma unroll
     for (int l2 = 0; l2 < N2; l2++) xo[j * N + l1 + N1 * l2] = a[s][l2];
@@ -400,9 +418,18 @@ bool fast_ring_supported(int N) {
   return N == 128;
 }
 
+// the epilogue / prologue stage a slice's pair range in the exchange buffer
+template <int N1, int N2, int NT, int ROUNDS, class T>
+static bool slices_fit(const FastRingParams<T>& p) {
+  for (int r = 0; r < FAST_ROUNDS; r++)
+    if (p.rend[r] - p.rbeg[r] > FastGeom<N1, N2, NT, ROUNDS>::BUF) return false;
+  return p.N == N1 * N2;
+}
+
 template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s) {
-  constexpr int R = sizeof(T) == 8 ? 2 : 2;
+  constexpr int R = FAST_ROUNDS;
+  if (!slices_fit<16, 8, 512, R>(p)) return hipErrorInvalidValue;
   auto kern = ring_forward_fast<T, 16, 8, 512, R>;
   const size_t smem = fast_smem<T, 16, 8, 512, R>();
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -413,7 +440,8 @@ hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* sa
 
 template <class T>
 hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s) {
-  constexpr int R = sizeof(T) == 8 ? 2 : 2;
+  constexpr int R = FAST_ROUNDS;
+  if (!slices_fit<16, 8, 512, R>(p)) return hipErrorInvalidValue;
   auto kern = ring_inverse_fast<T, 16, 8, 512, R>;
   const size_t smem = fast_smem<T, 16, 8, 512, R>();
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
