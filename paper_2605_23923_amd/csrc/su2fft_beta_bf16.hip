@@ -1,0 +1,358 @@
+// Beta contraction in split bfloat16 ("BF16x3"): every FP32 operand x is
+// carried as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to
+// nearest even), and a product A B is formed on the matrix cores as
+// A_hi B_hi + A_hi B_lo + A_lo B_hi with FP32 accumulation (the lo*lo term,
+// about 2^-16 relative, is dropped).  The contraction itself is the one of
+// the FP32 path (the inner products <s, P^l_{nm}> of Section 4 for every
+// pair); only the arithmetic of the matrix products changes.
+//
+// Instruction: V_MFMA_F32_16X16X32_BF16, A 16x32, B 32x16, lane l holding
+// A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i = 0..7, and
+// the accumulator D[4 (l / 16) + r][l % 16] (all measured).
+//
+// Tables (hi in the low 16 bits, lo in the high 16 bits of a 32-bit word):
+//   forward: [tile][k / 8][column j = coff + i][k % 8]  (a lane's 8 nodes are
+//            one aligned 32-byte load), rows k >= N zero;
+//   inverse: the tile-major [tile][k][lsum] layout of the other paths.
+#include "su2fft_internal.h"
+
+namespace su2 {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+__device__ __forceinline__ floatx4 mfma_bf16(u16x8 a, u16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                  0);
+}
+
+// split eight FP32 values into their bf16 hi and lo parts
+__device__ __forceinline__ void split8(const float* v, u16x8& hi, u16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const unsigned short h = bf16_rne_bits(v[i]);
+    hi[i] = h;
+    lo[i] = bf16_rne_bits(v[i] - bf16_bits_to_f32(h));
+  }
+}
+
+// eight table words -> hi and lo operands
+__device__ __forceinline__ void unpack8(const unsigned* w, u16x8& hi, u16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    hi[i] = (unsigned short)(w[i] & 0xffffu);
+    lo[i] = (unsigned short)(w[i] >> 16);
+  }
+}
+
+__device__ __forceinline__ long long coeff_index_bf(int tl, int tm, int tn) {
+  return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
+}
+
+constexpr int XB_THREADS = 512;
+constexpr int XB_BT = 32;   // inverse: signals per workgroup (64 real columns)
+constexpr int XBF_BT = 16;  // forward: signals per workgroup (a 32-node S chunk is 64 KB)
+constexpr int XB_KC = 32;   // nodes per chunk = K of one matrix instruction
+
+// Forward.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8.
+// S streams through LDS in chunks of 32 nodes with register prefetch; the
+// table operand is read straight from the node-interleaved layout.
+template <int RTMAX>
+__global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const cpx<float>* __restrict__ S,
+                                                                         cpx<float>* __restrict__ coeffs,
+                                                                         BetaParams<float> p,
+                                                                         const unsigned* __restrict__ tabf) {
+  constexpr int BT = XBF_BT, CT = 2 * BT / 16, KC = XB_KC;
+  constexpr int PB = 2 * PT + 2;
+  constexpr int PK = BT * PB + 16;
+  constexpr int VC = 2;                         // complex values per 16-byte load
+  constexpr int SV = KC * BT * PT / VC;
+  constexpr int SPT = SV / XB_THREADS;
+  static_assert(SV % XB_THREADS == 0, "chunk split");
+  __shared__ float sS[KC * PK];
+
+  const int tile = blockIdx.x;
+  const int b0 = blockIdx.y * BT;
+  const int nb = min(BT, p.batch - b0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane & 15, lg = lane >> 4;
+  const int N = p.N;
+  const int NB8 = (N + 7) / 8;
+  const PairInfo p0 = p.pairs[tile * PT];
+  const int lsum = p0.lsum;
+  // the node-interleaved table holds NB8 * 8 rows per tile: its tile block starts
+  // at (tab / N) * NB8 * 8, tab being the tile offset in the [k][lsum] layout
+  const unsigned* tb = tabf + (p0.tab / N) * (long long)NB8 * 8;
+
+  PairInfo pi[2];
+#pragma unroll
+  for (int i = 0; i < 2; i++) pi[i] = p.pairs[tile * PT + wave + 8 * i];
+
+  floatx4 acc[2][RTMAX][CT];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int rt = 0; rt < RTMAX; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  float4 sreg[SPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+      const int v = threadIdx.x + XB_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+      const int k = k0 + kk;
+      if (k < N && bb < nb)
+        sreg[i] = *reinterpret_cast<const float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
+      else
+        sreg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+      const int v = threadIdx.x + XB_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+      float* d = sS + kk * PK + bb * PB + 2 * pv * VC;
+      d[0] = sreg[i].x; d[1] = sreg[i].y; d[2] = sreg[i].z; d[3] = sreg[i].w;
+    }
+  };
+
+  const int nchunk = (N + KC - 1) / KC;
+  fetch(0);
+  commit();
+  for (int c = 0; c < nchunk; c++) {
+    __syncthreads();
+    if (c + 1 < nchunk) fetch((c + 1) * KC);
+    const int kb = c * (KC / 8) + lg;  // this lane's group of 8 nodes
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const int L = pi[i].L;
+      if (L == 0) continue;
+      const int pp = wave + 8 * i;
+      // B operands: 8 consecutive nodes of one column, split into hi and lo
+      u16x8 bhi[CT], blo[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = sS[(8 * lg + q) * PK + (cc >> 1) * PB + 2 * pp + (cc & 1)];
+        split8(v, bhi[ct], blo[ct]);
+      }
+#pragma unroll
+      for (int rt = 0; rt < RTMAX; rt++) {
+        if (rt * 16 < L) {
+          const int l = rt * 16 + lrow;
+          u16x8 ahi, alo;
+          if (l < L && kb < NB8) {
+            const uint4* src = reinterpret_cast<const uint4*>(tb + ((size_t)kb * lsum + pi[i].coff + l) * 8);
+            const uint4 w0 = src[0], w1 = src[1];
+            const unsigned w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+            unpack8(w, ahi, alo);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++) { ahi[q] = 0; alo[q] = 0; }
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) {
+            acc[i][rt][ct] = mfma_bf16(ahi, bhi[ct], acc[i][rt][ct]);
+            acc[i][rt][ct] = mfma_bf16(ahi, blo[ct], acc[i][rt][ct]);
+            acc[i][rt][ct] = mfma_bf16(alo, bhi[ct], acc[i][rt][ct]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nchunk) commit();
+  }
+
+  float* out = reinterpret_cast<float*>(coeffs);
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int L = pi[i].L;
+    if (L == 0) continue;
+#pragma unroll
+    for (int rt = 0; rt < RTMAX; rt++) {
+      if (rt * 16 >= L) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+        if (bb >= nb) continue;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int l = rt * 16 + 4 * lg + r;
+          if (l < L) {
+            const long long idx = coeff_index_bf(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
+            out[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim] = acc[i][rt][ct][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Inverse.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8 and
+// keeps their split, scaled coefficients as B operands (32 degrees per
+// instruction); the nodes are swept in blocks of 16 and staged through LDS so
+// that S is written in whole 16-pair rows.
+template <int LQ>
+__global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const cpx<float>* __restrict__ coeffs,
+                                                                         cpx<float>* __restrict__ S,
+                                                                         BetaParams<float> p,
+                                                                         const unsigned* __restrict__ tabi) {
+  constexpr int BT = XB_BT, CT = 2 * BT / 16;
+  constexpr int PB = 2 * PT + 2;
+  __shared__ float stage[16 * BT * PB];
+  const int tile = blockIdx.x;
+  const int b0 = blockIdx.y * BT;
+  const int nb = min(BT, p.batch - b0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane & 15, lg = lane >> 4;
+  const int N = p.N;
+  const float* cin = reinterpret_cast<const float*>(coeffs);
+  const PairInfo p0 = p.pairs[tile * PT];
+  const int lsum = p0.lsum;
+  const unsigned* tb = tabi + p0.tab;
+
+  PairInfo pi[2];
+  u16x8 bhi[2][LQ][CT], blo[2][LQ][CT];
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    pi[q] = p.pairs[tile * PT + wave + 8 * q];
+#pragma unroll
+    for (int s = 0; s < LQ; s++) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          const int l = 32 * s + 8 * lg + i;
+          v[i] = 0.f;
+          if (l < pi[q].L && bb < nb) {
+            const int tl = pi[q].tl0 + 2 * l;
+            const float sc = p.scale_mode == 0 ? float(tl + 1) : 1.f;
+            v[i] = sc * cin[(((size_t)(b0 + bb)) * p.ncoef + coeff_index_bf(tl, pi[q].tm, pi[q].tn)) * 2 + reim];
+          }
+        }
+        split8(v, bhi[q][s][ct], blo[q][s][ct]);
+      }
+    }
+  }
+
+  for (int k0 = 0; k0 < N; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int L = pi[q].L;
+      const int pp = wave + 8 * q;
+      floatx4 acc[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int k = k0 + lrow;
+      const unsigned* trow = tb + (size_t)k * lsum + pi[q].coff;
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+        if (32 * s < L) {
+          unsigned w[8];
+#pragma unroll
+          for (int i = 0; i < 8; i++) {
+            const int l = 32 * s + 8 * lg + i;
+            w[i] = (l < L && k < N) ? trow[l] : 0u;
+          }
+          u16x8 ahi, alo;
+          unpack8(w, ahi, alo);
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) {
+            acc[ct] = mfma_bf16(ahi, bhi[q][s][ct], acc[ct]);
+            acc[ct] = mfma_bf16(ahi, blo[q][s][ct], acc[ct]);
+            acc[ct] = mfma_bf16(alo, bhi[q][s][ct], acc[ct]);
+          }
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) stage[((4 * lg + r) * BT + bb) * PB + 2 * pp + reim] = acc[ct][r];
+      }
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < 16 * BT * (PT / 2); v += XB_THREADS) {
+      const int row = v / (PT / 2), pv = v - row * (PT / 2);
+      const int kk = row / BT, bb = row - kk * BT;
+      const int k = k0 + kk;
+      if (k < N && bb < nb) {
+        const float* src = stage + row * PB + 4 * pv;
+        *reinterpret_cast<float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + 2 * pv) =
+            make_float4(src[0], src[1], src[2], src[3]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Reorder the tile-major split table into the node-interleaved forward layout.
+// Grid: (chunks of one tile block, tiles).
+__global__ void interleave_bf16_table_kernel(int N, const PairInfo* __restrict__ pairs, const bf16x2_t* __restrict__ src,
+                                             unsigned* __restrict__ dst) {
+  const int NB8 = (N + 7) / 8;
+  const PairInfo p0 = pairs[blockIdx.y * PT];
+  const long long cnt = (long long)NB8 * 8 * p0.lsum;
+  const long long base = (p0.tab / N) * (long long)NB8 * 8;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / p0.lsum), j = (int)(e - (long long)k * p0.lsum);
+    unsigned w = 0u;
+    if (k < N) {
+      const bf16x2_t v = src[p0.tab + (long long)k * p0.lsum + j];
+      w = (unsigned)v.hi | ((unsigned)v.lo << 16);
+    }
+    dst[base + ((long long)(k / 8) * p0.lsum + j) * 8 + (k % 8)] = w;
+  }
+}
+
+hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
+                                      cpx<float>* coeffs, hipStream_t s) {
+  dim3 grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT);
+  const int lmax = (p.B + 1) / 2;
+  if (lmax <= 16)
+    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<1>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
+  else if (lmax <= 32)
+    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<2>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
+  else
+    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<4>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
+  return hipGetLastError();
+}
+
+hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
+                                      cpx<float>* S, hipStream_t s) {
+  dim3 grid(p.ntiles, (p.batch + XB_BT - 1) / XB_BT);
+  const int lmax = (p.B + 1) / 2;
+  if (lmax <= 32)
+    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<1>), grid, dim3(XB_THREADS), 0, s, coeffs, S, p, tabi);
+  else
+    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<2>), grid, dim3(XB_THREADS), 0, s, coeffs, S, p, tabi);
+  return hipGetLastError();
+}
+
+hipError_t launch_interleave_bf16_table(int N, int ntiles, const PairInfo* pairs, const bf16x2_t* src, unsigned* dst,
+                                        hipStream_t s) {
+  hipLaunchKernelGGL(interleave_bf16_table_kernel, dim3(16, ntiles), dim3(256), 0, s, N, pairs, src, dst);
+  return hipGetLastError();
+}
+
+}  // namespace su2

@@ -115,6 +115,7 @@ struct su2_plan_s {
   double* d_tab64 = nullptr;
   float* d_tab32 = nullptr;
   bf16x2_t* d_tabbf = nullptr;
+  unsigned* d_tabbf_fwd = nullptr;
   int* d_fftpos = nullptr;
   int* d_colq = nullptr;
   int* d_bins = nullptr;
@@ -340,6 +341,11 @@ su2_status_t build_plan(su2_plan_s* pl) {
   } else if (pl->dtype == SU2_C64_BF16X3) {
     if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_split_table_bf16(tab, pl->d_tab64, pl->d_tabbf, 0)) != hipSuccess) return hip_fail(e);
+    const long long fwd_words = tab / N * (long long)((N + 7) / 8) * 8;
+    if ((e = pl->alloc((void**)&pl->d_tabbf_fwd, sizeof(unsigned) * (size_t)fwd_words + 64)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = launch_interleave_bf16_table(N, pl->ntiles, pl->d_pairs, pl->d_tabbf, pl->d_tabbf_fwd, 0)) != hipSuccess)
+      return hip_fail(e);
   }
   if ((e = pl->alloc(&pl->d_S, cb * (size_t)pl->P_pad * N * pl->batch)) != hipSuccess) return hip_fail(e);
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
@@ -387,6 +393,20 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
 
 su2_status_t run_stage(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s) {
   if (pl->dtype == SU2_C128) return run_stage_t<double>(pl, stage, in, out, s);
+  if (pl->dtype == SU2_C64_BF16X3) {
+    hipError_t e = hipSuccess;
+    if (stage == SU2_STAGE_BETA_FORWARD) {
+      e = launch_beta_forward_bf16x3(beta_params<float>(pl, nullptr, 0), pl->d_tabbf_fwd,
+                                     (const cpx<float>*)pl->d_S, (cpx<float>*)out, s);
+    } else if (stage == SU2_STAGE_BETA_INVERSE || stage == SU2_STAGE_BETA_ADJOINT) {
+      e = launch_beta_inverse_bf16x3(beta_params<float>(pl, nullptr, stage == SU2_STAGE_BETA_ADJOINT),
+                                     (const unsigned*)pl->d_tabbf, (const cpx<float>*)in, (cpx<float>*)pl->d_S, s);
+    } else {
+      return run_stage_t<float>(pl, stage, in, out, s);
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    return SU2_OK;
+  }
   return run_stage_t<float>(pl, stage, in, out, s);
 }
 
@@ -448,7 +468,6 @@ su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_pl
   if (B < 1 || batch < 1) return SU2_ERR_INVALID_VALUE;
   if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
   if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
-  if (dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
   su2_status_t st = check_device();
   if (st != SU2_OK) return st;
   su2_plan_s* pl = new (std::nothrow) su2_plan_s();

@@ -110,10 +110,12 @@ template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s);
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s);
-hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const bf16x2_t* tab, const cpx<float>* S,
+hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s);
-hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const bf16x2_t* tab, const cpx<float>* coeffs,
+hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s);
+hipError_t launch_interleave_bf16_table(int N, int ntiles, const PairInfo* pairs, const bf16x2_t* src, unsigned* dst,
+                                        hipStream_t s);
 
 template <class T>
 bool fast_ring_supported(int N);
