@@ -203,8 +203,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); signals are independent, "
-              "so a multi-GPU run would shard the batch (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); signals are independent, so a "
+              "multi-GPU run would shard the batch by signal with no communication.", file=sys.stderr)
         sys.exit(2)
 
     import torch
