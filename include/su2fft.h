@@ -83,10 +83,14 @@ su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_pl
 /* Plan for a batch of signals with individual bandlimits B_per_signal[0..batch-1]
  * (each 1..128, N = 2B of the form 2^a 3^b).  Signals are concatenated in order
  * in the sample and coefficient buffers: signal s starts at the prefix sum of
- * the per-signal sizes (su2_num_samples / su2_num_coeffs of its B).  The plan
- * records every kernel of one call into a HIP graph (captured on the first
- * call on a stream) and replays it.  B_per_signal is a host array, read only
- * during the call. */
+ * the per-signal sizes (su2_num_samples / su2_num_coeffs of its B).  A call
+ * runs as two persistent work-list kernels covering every signal (ring FFTs,
+ * then contractions, or the reverse); they are captured into a HIP graph the
+ * first time a (direction, input, output, stream) combination is used, and
+ * the graph is replayed on later calls with the same buffers and stream (the
+ * plan keeps up to 16 such graphs).  Results are bit-identical to single-B
+ * plans of each signal.  B_per_signal is a host array, read only during the
+ * call.  su2_run_stage and su2_plan_dtable do not accept mixed plans. */
 su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype,
                                    su2_plan_t* out);
 
@@ -139,6 +143,16 @@ int64_t su2_coeff_index(int32_t two_l, int32_t two_m, int32_t two_n);  /* -1 if 
 /* Grid nodes and beta weights of the plan's quadrature (host arrays of 2B
  * doubles each; any pointer may be NULL to skip it).  w_beta receives W_k. */
 su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, double* w_beta);
+
+/* Mixed plans: the persistent grid size, in workgroups per compute unit, that
+ * the autotuner chose at plan creation for each of the four work-list kernels
+ * (ring forward, contraction forward, contraction inverse/adjoint, ring
+ * inverse/adjoint), written to workgroups_per_cu[0..3].  The choice does not
+ * change any result.  Setting the environment variable SU2_AUTOTUNE=0 before
+ * plan creation skips the search (default 2 each); SU2_AUTOTUNE_CACHE names a
+ * text file that caches choices across processes.  SU2_ERR_INVALID_VALUE for a
+ * single-B plan. */
+su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu);
 
 /* Plan queries: bandlimit (-1 for mixed plans), batch, dtype, device bytes held. */
 su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype,

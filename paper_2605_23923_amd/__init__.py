@@ -83,6 +83,8 @@ def _load():
     lib.su2_plan_info.restype = i32
     lib.su2_plan_dtable.argtypes = [vp, i32, i32, dp, ctypes.POINTER(i32)]
     lib.su2_plan_dtable.restype = i32
+    lib.su2_plan_tuning.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.su2_plan_tuning.restype = i32
     lib.su2_status_string.argtypes = [i32]
     lib.su2_status_string.restype = ctypes.c_char_p
     lib.su2_last_hip_error.argtypes = []
@@ -254,6 +256,12 @@ class MixedPlan(_PlanBase):
         self.total_coeffs = self.coeff_offsets[-1]
         self.sample_shape = (self.total_samples,)
         self.coeff_shape = (self.total_coeffs,)
+
+    def tuning(self):
+        """Workgroups per CU the autotuner chose for the four work-list kernels."""
+        arr = (ctypes.c_int32 * 4)()
+        _check(_load().su2_plan_tuning(self._handle, arr), "su2_plan_tuning")
+        return list(arr)
 
 
 class SU2Transform(torch.autograd.Function):

@@ -72,8 +72,20 @@ constexpr int KC = 8;  // beta nodes per streamed chunk (forward)
 constexpr int FWD_THREADS = 512;
 
 template <class T, int RTMAX>
-__global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
-                                                                   cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
+struct FwdGeom {
+  static constexpr int BT = BetaCfg<T>::BT;
+  static constexpr int PB = 2 * PT + 2;
+  static constexpr int PK = BT * PB + 16;
+  static constexpr int TMAX = PT * 16 * RTMAX;
+  static constexpr int VE = 16 / (int)sizeof(T);
+  static constexpr int TV = (KC * TMAX) / VE + 2;
+  static constexpr int TVT = (TV + FWD_THREADS - 1) / FWD_THREADS;
+  static constexpr size_t SMEM = (size_t)(KC * PK + TVT * FWD_THREADS * VE) * sizeof(T);
+};
+
+template <class T, int RTMAX>
+__device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
+                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem) {
   typedef typename acc4<T>::type accT;
   constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
   constexpr int PB = 2 * PT + 2;            // reals per (node, signal) row: 16 pairs x (re, im) + pad
@@ -86,11 +98,10 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>*
   constexpr int SV = KC * BT * PT / VC;                     // 16-byte loads per S chunk
   constexpr int SPT = SV / FWD_THREADS;
   static_assert(SV % FWD_THREADS == 0, "chunk split");
-  __shared__ T sS[KC * PK];
-  __shared__ __align__(16) T sT[TVT * FWD_THREADS * VE];
+  T* sS = reinterpret_cast<T*>(smem);      // KC * PK reals (a multiple of 16 bytes)
+  T* sT = sS + KC * PK;
 
-  const int tile = blockIdx.x;
-  const int b0 = blockIdx.y * BT;
+  const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane & 15, lk = lane >> 4;
@@ -215,12 +226,19 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>*
           const int l = rt * 16 + acc_row<T>(lane, r);
           if (l < L) {
             const long long idx = coeff_index(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
-            out[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim] = acc[i][rt][ct][r];
+            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
           }
         }
       }
     }
   }
+}
+
+template <class T, int RTMAX>
+__global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
+                                                                   cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_forward_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
@@ -230,15 +248,17 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>*
 // full PT-pair rows of S.
 constexpr int INV_THREADS = 512;
 
+template <class T>
+constexpr size_t inverse_smem() { return (size_t)16 * BetaCfg<T>::BT * (2 * PT + 2) * sizeof(T); }
+
 template <class T, int LQ>
-__global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
-                                                                   cpx<T>* __restrict__ S, BetaParams<T> p) {
+__device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
+                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem) {
   typedef typename acc4<T>::type accT;
   constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
   constexpr int PB = 2 * PT + 2;  // reals per (node, signal) row in the staging buffer
-  __shared__ T stage[16 * BT * PB];
-  const int tile = blockIdx.x;
-  const int b0 = blockIdx.y * BT;
+  T* stage = reinterpret_cast<T*>(smem);
+  const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane & 15, lk = lane >> 4;
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>*
           const int tl = pi[q].tl0 + 2 * l;
           const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
           const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
-          v = sc * cin[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim];
+          v = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim];
         }
         bop[q][s][ct] = v;
       }
@@ -321,17 +341,38 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>*
   }
 }
 
+template <class T, int LQ>
+__global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
+                                                                   cpx<T>* __restrict__ S, BetaParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_inverse_body<T, LQ>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)
+template <class K>
+static hipError_t set_smem(K kern, size_t smem) {
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+}
+
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
   constexpr int BT = BetaCfg<T>::BT;
   dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
-  const int lmax = (p.B + 1) / 2;
-  if (lmax <= 16)
-    hipLaunchKernelGGL((beta_forward_kernel<T, 1>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
-  else if (lmax <= 32)
-    hipLaunchKernelGGL((beta_forward_kernel<T, 2>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
-  else
-    hipLaunchKernelGGL((beta_forward_kernel<T, 4>), grid, dim3(FWD_THREADS), 0, s, S, coeffs, p);
+  const int rt = beta_rtmax(p.B);
+  hipError_t e;
+  if (rt == 1) {
+    if ((e = set_smem(beta_forward_kernel<T, 1>, FwdGeom<T, 1>::SMEM)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((beta_forward_kernel<T, 1>), grid, dim3(FWD_THREADS), (FwdGeom<T, 1>::SMEM), s, S, coeffs, p);
+  } else if (rt == 2) {
+    if ((e = set_smem(beta_forward_kernel<T, 2>, FwdGeom<T, 2>::SMEM)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((beta_forward_kernel<T, 2>), grid, dim3(FWD_THREADS), (FwdGeom<T, 2>::SMEM), s, S, coeffs, p);
+  } else {
+    if ((e = set_smem(beta_forward_kernel<T, 4>, FwdGeom<T, 4>::SMEM)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL((beta_forward_kernel<T, 4>), grid, dim3(FWD_THREADS), (FwdGeom<T, 4>::SMEM), s, S, coeffs, p);
+  }
   return hipGetLastError();
 }
 
@@ -339,16 +380,22 @@ template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
   constexpr int BT = BetaCfg<T>::BT;
   dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
-  const int lmax = (p.B + 1) / 2;
-  if (lmax <= 8)
-    hipLaunchKernelGGL((beta_inverse_kernel<T, 2>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
-  else if (lmax <= 16)
-    hipLaunchKernelGGL((beta_inverse_kernel<T, 4>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
-  else if (lmax <= 32)
-    hipLaunchKernelGGL((beta_inverse_kernel<T, 8>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
-  else
-    hipLaunchKernelGGL((beta_inverse_kernel<T, 16>), grid, dim3(INV_THREADS), 0, s, coeffs, S, p);
-  return hipGetLastError();
+  const size_t smem = inverse_smem<T>();
+  const int lq = beta_lq(p.B);
+  hipError_t e;
+#define SU2_INV_CASE(Q)                                                                             \
+  if (lq == Q) {                                                                                    \
+    if ((e = set_smem(beta_inverse_kernel<T, Q>, smem)) != hipSuccess) \
+      return e;                                                                                     \
+    hipLaunchKernelGGL((beta_inverse_kernel<T, Q>), grid, dim3(INV_THREADS), smem, s, coeffs, S, p); \
+    return hipGetLastError();                                                                       \
+  }
+  SU2_INV_CASE(2)
+  SU2_INV_CASE(4)
+  SU2_INV_CASE(8)
+  SU2_INV_CASE(16)
+#undef SU2_INV_CASE
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_beta_forward<float>(const BetaParams<float>&, const cpx<float>*, cpx<float>*, hipStream_t);

@@ -65,11 +65,14 @@ constexpr int XB_KC = 32;   // nodes per chunk = K of one matrix instruction
 // Forward.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8.
 // S streams through LDS in chunks of 32 nodes with register prefetch; the
 // table operand is read straight from the node-interleaved layout.
+constexpr size_t XBF_SMEM = (size_t)XB_KC * (XBF_BT * (2 * PT + 2) + 16) * sizeof(float);
+constexpr size_t XBI_SMEM = (size_t)16 * XB_BT * (2 * PT + 2) * sizeof(float);
+
 template <int RTMAX>
-__global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const cpx<float>* __restrict__ S,
-                                                                         cpx<float>* __restrict__ coeffs,
-                                                                         BetaParams<float> p,
-                                                                         const unsigned* __restrict__ tabf) {
+__device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __restrict__ S,
+                                                         cpx<float>* __restrict__ coeffs, const BetaParams<float>& p,
+                                                         const unsigned* __restrict__ tabf, int tile, int bt,
+                                                         unsigned char* smem) {
   constexpr int BT = XBF_BT, CT = 2 * BT / 16, KC = XB_KC;
   constexpr int PB = 2 * PT + 2;
   constexpr int PK = BT * PB + 16;
@@ -77,10 +80,9 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
   constexpr int SV = KC * BT * PT / VC;
   constexpr int SPT = SV / XB_THREADS;
   static_assert(SV % XB_THREADS == 0, "chunk split");
-  __shared__ float sS[KC * PK];
+  float* sS = reinterpret_cast<float*>(smem);
 
-  const int tile = blockIdx.x;
-  const int b0 = blockIdx.y * BT;
+  const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane & 15, lg = lane >> 4;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
           const int l = rt * 16 + 4 * lg + r;
           if (l < L) {
             const long long idx = coeff_index_bf(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
-            out[(((size_t)(b0 + bb)) * p.ncoef + idx) * 2 + reim] = acc[i][rt][ct][r];
+            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
           }
         }
       }
@@ -204,20 +206,28 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
   }
 }
 
+template <int RTMAX>
+__global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const cpx<float>* __restrict__ S,
+                                                                         cpx<float>* __restrict__ coeffs,
+                                                                         BetaParams<float> p,
+                                                                         const unsigned* __restrict__ tabf) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 // Inverse.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8 and
 // keeps their split, scaled coefficients as B operands (32 degrees per
 // instruction); the nodes are swept in blocks of 16 and staged through LDS so
 // that S is written in whole 16-pair rows.
 template <int LQ>
-__global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const cpx<float>* __restrict__ coeffs,
-                                                                         cpx<float>* __restrict__ S,
-                                                                         BetaParams<float> p,
-                                                                         const unsigned* __restrict__ tabi) {
+__device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __restrict__ coeffs,
+                                                         cpx<float>* __restrict__ S, const BetaParams<float>& p,
+                                                         const unsigned* __restrict__ tabi, int tile, int bt,
+                                                         unsigned char* smem) {
   constexpr int BT = XB_BT, CT = 2 * BT / 16;
   constexpr int PB = 2 * PT + 2;
-  __shared__ float stage[16 * BT * PB];
-  const int tile = blockIdx.x;
-  const int b0 = blockIdx.y * BT;
+  float* stage = reinterpret_cast<float*>(smem);
+  const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lrow = lane & 15, lg = lane >> 4;
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
           if (l < pi[q].L && bb < nb) {
             const int tl = pi[q].tl0 + 2 * l;
             const float sc = p.scale_mode == 0 ? float(tl + 1) : 1.f;
-            v[i] = sc * cin[(((size_t)(b0 + bb)) * p.ncoef + coeff_index_bf(tl, pi[q].tm, pi[q].tn)) * 2 + reim];
+            v[i] = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + coeff_index_bf(tl, pi[q].tm, pi[q].tn)) * 2 + reim];
           }
         }
         split8(v, bhi[q][s][ct], blo[q][s][ct]);
@@ -306,6 +316,15 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
   }
 }
 
+template <int LQ>
+__global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const cpx<float>* __restrict__ coeffs,
+                                                                         cpx<float>* __restrict__ S,
+                                                                         BetaParams<float> p,
+                                                                         const unsigned* __restrict__ tabi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_inverse_bf16x3_body<LQ>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 // Reorder the tile-major split table into the node-interleaved forward layout.
 // Grid: (chunks of one tile block, tiles).
 __global__ void interleave_bf16_table_kernel(int N, const PairInfo* __restrict__ pairs, const bf16x2_t* __restrict__ src,
@@ -325,28 +344,44 @@ __global__ void interleave_bf16_table_kernel(int N, const PairInfo* __restrict__
   }
 }
 
+template <class K>
+static hipError_t set_smem_bf(K kern, size_t smem) {
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+}
+
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s) {
   dim3 grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT);
-  const int lmax = (p.B + 1) / 2;
-  if (lmax <= 16)
-    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<1>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
-  else if (lmax <= 32)
-    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<2>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
-  else
-    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<4>), grid, dim3(XB_THREADS), 0, s, S, coeffs, p, tabf);
-  return hipGetLastError();
+  const int rt = beta_rtmax(p.B);
+  hipError_t e;
+#define SU2_XBF_CASE(R)                                                                                           \
+  if (rt == R) {                                                                                                  \
+    if ((e = set_smem_bf(beta_forward_bf16x3_kernel<R>, XBF_SMEM)) != hipSuccess) return e;                       \
+    hipLaunchKernelGGL((beta_forward_bf16x3_kernel<R>), grid, dim3(XB_THREADS), XBF_SMEM, s, S, coeffs, p, tabf); \
+    return hipGetLastError();                                                                                     \
+  }
+  SU2_XBF_CASE(1)
+  SU2_XBF_CASE(2)
+  SU2_XBF_CASE(4)
+#undef SU2_XBF_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s) {
   dim3 grid(p.ntiles, (p.batch + XB_BT - 1) / XB_BT);
-  const int lmax = (p.B + 1) / 2;
-  if (lmax <= 32)
-    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<1>), grid, dim3(XB_THREADS), 0, s, coeffs, S, p, tabi);
-  else
-    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<2>), grid, dim3(XB_THREADS), 0, s, coeffs, S, p, tabi);
-  return hipGetLastError();
+  const int lq2 = beta_bf16_lq(p.B);
+  hipError_t e;
+#define SU2_XBI_CASE(Q)                                                                                           \
+  if (lq2 == Q) {                                                                                                 \
+    if ((e = set_smem_bf(beta_inverse_bf16x3_kernel<Q>, XBI_SMEM)) != hipSuccess) return e;                       \
+    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<Q>), grid, dim3(XB_THREADS), XBI_SMEM, s, coeffs, S, p, tabi); \
+    return hipGetLastError();                                                                                     \
+  }
+  SU2_XBI_CASE(1)
+  SU2_XBI_CASE(2)
+#undef SU2_XBI_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_interleave_bf16_table(int N, int ntiles, const PairInfo* pairs, const bf16x2_t* src, unsigned* dst,

@@ -8,13 +8,15 @@
 #include <type_traits>
 #include <vector>
 
-#include "su2fft_internal.h"
+#include "su2fft_plan.h"
 
 using namespace su2;
 
 static thread_local int32_t g_last_hip_error = 0;
 
-namespace {
+namespace su2 {
+
+void set_last_hip_error(hipError_t e) { g_last_hip_error = (int32_t)e; }
 
 su2_status_t hip_fail(hipError_t e) {
   g_last_hip_error = (int32_t)e;
@@ -35,6 +37,10 @@ bool only_2_3(int n) {
 
 // radix sequence for a length that is a product of 2s and 3s: 8s first, then
 // a 4 or a 2 for the rest of the power of two, then 3s.
+}  // namespace su2
+
+namespace {
+
 int radix_plan(int L, int* rad) {
   int n = 0;
   int p2 = 0, p3 = 0;
@@ -99,87 +105,7 @@ void grid_ld(int B, std::vector<long double>& alpha, std::vector<long double>& b
 
 }  // namespace
 
-struct su2_plan_s {
-  int B = 0, N = 0, batch = 0;
-  su2_dtype_t dtype = SU2_C128;
-  int split = 1, Nc = 0;
-  int P = 0, P_pad = 0, ntiles = 0;
-  int nrad_c = 0, nrad_n = 0, rad_c[MAX_RADICES] = {0}, rad_n[MAX_RADICES] = {0};
-  int cls_begin[MAX_SPLIT] = {0}, cls_end[MAX_SPLIT] = {0};
-  long long ncoef = 0;
-  long long tab_elems = 0;
-  int device = 0;
-  int64_t bytes = 0;
-  // device memory
-  PairInfo* d_pairs = nullptr;
-  double* d_tab64 = nullptr;
-  float* d_tab32 = nullptr;
-  bf16x2_t* d_tabbf = nullptr;
-  unsigned* d_tabbf_fwd = nullptr;
-  int* d_fftpos = nullptr;
-  int* d_colq = nullptr;
-  int* d_bins = nullptr;
-  bool fast = false;
-  int rbeg[FAST_ROUNDS] = {0}, rend[FAST_ROUNDS] = {0};
-  void* d_rho = nullptr;
-  void* d_tw = nullptr;
-  void* d_W = nullptr;
-  void* d_S = nullptr;
-  std::vector<void*> allocs;
-  std::vector<PairInfo> h_pairs;
-
-  hipError_t alloc(void** p, size_t n) {
-    hipError_t e = hipMalloc(p, n == 0 ? 16 : n);
-    if (e == hipSuccess) { allocs.push_back(*p); bytes += (int64_t)n; }
-    return e;
-  }
-  void release() {
-    for (void* p : allocs) (void)hipFree(p);
-    allocs.clear();
-  }
-};
-
 namespace {
-
-template <class T>
-RingParams<T> ring_params(const su2_plan_s* pl, int adjoint) {
-  RingParams<T> r;
-  memset(&r, 0, sizeof(r));
-  r.N = pl->N; r.Nc = pl->Nc; r.split = pl->split; r.batch = pl->batch; r.ntiles = pl->ntiles;
-  r.nrad_c = pl->nrad_c; r.nrad_n = pl->nrad_n;
-  for (int i = 0; i < MAX_RADICES; i++) { r.rad_c[i] = pl->rad_c[i]; r.rad_n[i] = pl->rad_n[i]; }
-  for (int i = 0; i < MAX_SPLIT; i++) { r.cls_begin[i] = pl->cls_begin[i]; r.cls_end[i] = pl->cls_end[i]; }
-  r.tw = (const cpx<T>*)pl->d_tw;
-  r.W = (const T*)pl->d_W;
-  r.fftpos = pl->d_fftpos;
-  r.rho = (const cpx<T>*)pl->d_rho;
-  r.colq = pl->d_colq;
-  r.adjoint = adjoint;
-  return r;
-}
-
-template <class T>
-FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
-  FastRingParams<T> r;
-  r.N = pl->N; r.batch = pl->batch;
-  r.tw = (const cpx<T>*)pl->d_tw;
-  r.W = (const T*)pl->d_W;
-  r.bins = pl->d_bins;
-  r.adjoint = adjoint;
-  for (int i = 0; i < FAST_ROUNDS; i++) { r.rbeg[i] = pl->rbeg[i]; r.rend[i] = pl->rend[i]; }
-  return r;
-}
-
-template <class T>
-BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
-  BetaParams<T> b;
-  b.B = pl->B; b.N = pl->N; b.batch = pl->batch; b.ntiles = pl->ntiles;
-  b.ncoef = pl->ncoef;
-  b.pairs = pl->d_pairs;
-  b.tab = tab;
-  b.scale_mode = scale_mode;
-  return b;
-}
 
 template <class T>
 hipError_t upload_typed(su2_plan_s* pl, const std::vector<long double>& W, const std::vector<long double>& twr,
@@ -202,6 +128,10 @@ hipError_t upload_typed(su2_plan_s* pl, const std::vector<long double>& W, const
     return e;
   return hipSuccess;
 }
+
+}  // namespace
+
+namespace su2 {
 
 su2_status_t build_plan(su2_plan_s* pl) {
   const int B = pl->B, N = 2 * B;
@@ -352,6 +282,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
   return SU2_OK;
 }
 
+}  // namespace su2
+
+namespace {
+
 template <class T>
 const T* table_of(const su2_plan_s* pl) {
   return std::is_same<T, double>::value ? (const T*)pl->d_tab64 : (const T*)pl->d_tab32;
@@ -495,15 +429,36 @@ su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, s
     if (B_per_signal[i] < 1) return SU2_ERR_INVALID_VALUE;
     if (B_per_signal[i] > 128 || !only_2_3(2 * B_per_signal[i])) return SU2_ERR_UNSUPPORTED;
   }
-  return SU2_ERR_UNSUPPORTED;
+  su2_status_t st = check_device();
+  if (st != SU2_OK) return st;
+  su2_plan_s* pl = new (std::nothrow) su2_plan_s();
+  if (!pl) return SU2_ERR_OUT_OF_MEMORY;
+  st = create_mixed(B_per_signal, batch, dtype, pl);
+  if (st != SU2_OK) {
+    (void)hipDeviceSynchronize();
+    release_mixed(pl);
+    pl->release();
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return SU2_OK;
 }
 
 su2_status_t su2_plan_destroy(su2_plan_t plan) {
   if (!plan) return SU2_OK;
   hipError_t e = hipDeviceSynchronize();
+  release_mixed(plan);
   plan->release();
   delete plan;
   if (e != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu) {
+  if (!plan || !workgroups_per_cu) return SU2_ERR_INVALID_VALUE;
+  if (!plan->mixed) return SU2_ERR_INVALID_VALUE;
+  mixed_tuning(plan, workgroups_per_cu);
   return SU2_OK;
 }
 
@@ -518,21 +473,24 @@ su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t*
 
 su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (plan->mixed) return run_mixed(plan, 0, d_samples, d_coeffs, (hipStream_t)stream);
   return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, (hipStream_t)stream);
 }
 
 su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (plan->mixed) return run_mixed(plan, 1, d_coeffs, d_samples, (hipStream_t)stream);
   return run_pair(plan, SU2_STAGE_BETA_INVERSE, SU2_STAGE_RING_INVERSE, d_coeffs, d_samples, (hipStream_t)stream);
 }
 
 su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (plan->mixed) return run_mixed(plan, 2, d_coeffs, d_samples, (hipStream_t)stream);
   return run_pair(plan, SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT, d_coeffs, d_samples, (hipStream_t)stream);
 }
 
 su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream) {
-  if (!plan) return SU2_ERR_INVALID_VALUE;
+  if (!plan || plan->mixed) return SU2_ERR_INVALID_VALUE;
   if ((int)stage < 0 || (int)stage > (int)SU2_STAGE_RING_ADJOINT) return SU2_ERR_INVALID_VALUE;
   const bool needs_in = stage == SU2_STAGE_RING_FORWARD || stage == SU2_STAGE_BETA_INVERSE ||
                         stage == SU2_STAGE_BETA_ADJOINT;
@@ -541,7 +499,7 @@ su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, v
 }
 
 su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L) {
-  if (!plan || (!host_out && !L)) return SU2_ERR_INVALID_VALUE;
+  if (!plan || plan->mixed || (!host_out && !L)) return SU2_ERR_INVALID_VALUE;
   for (int p = 0; p < plan->P; p++) {
     const PairInfo& pi = plan->h_pairs[p];
     if (pi.tm != two_m || pi.tn != two_n) continue;

@@ -70,7 +70,14 @@ struct RingParams {
   const cpx<T>* rho;        // per pair: phase i^{n-m} (-1)^{2m} e^{-i pi n}
   const int* colq;          // per LDS column c': q' with pos(q') = c'
   int adjoint;              // inverse chain: 0 -> plain, 1 -> multiply by W_k
+  const long long* soff;    // per signal: offset of its samples (complex values), or null: b * N^3
 };
+
+// start of signal b's samples: an explicit offset table (batches of signals with
+// different bandlimits share one buffer) or the dense stride N^3
+__host__ __device__ inline size_t ring_offset(const long long* soff, int b, int N) {
+  return soff ? (size_t)soff[b] : (size_t)b * N * N * N;
+}
 
 // Parameters of the register-resident ring FFT kernels (compile-time N).  The
 // kernels process the gamma frequencies q in FAST_ROUNDS equal slices; the
@@ -84,6 +91,7 @@ struct FastRingParams {
   const int* bins;    // [q * N + p]: (pair << 2) | e with rho = i^e, or -1 if the bin is not retained
   int adjoint;        // inverse chain: 0 -> plain, 1 -> multiply by W_k
   int rbeg[FAST_ROUNDS], rend[FAST_ROUNDS];
+  const long long* soff;  // per signal sample offsets, or null
 };
 
 // Parameters of the beta contraction kernels.
@@ -94,7 +102,12 @@ struct BetaParams {
   const PairInfo* pairs;
   const T* tab;             // Wigner-d table, tile-major (see PairInfo)
   int scale_mode;           // inverse: 0 -> (2l+1) weights, 1 -> none (adjoint)
+  const long long* coff;    // per signal: offset of its coefficients (complex values), or null: b * ncoef
 };
+
+__host__ __device__ inline size_t coef_offset(const long long* coff, int b, long long ncoef) {
+  return coff ? (size_t)coff[b] : (size_t)b * ncoef;
+}
 
 // bf16 split table entry (hi, lo) for the split-precision contraction
 struct bf16x2_t {
@@ -116,6 +129,19 @@ hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned
                                       cpx<float>* S, hipStream_t s);
 hipError_t launch_interleave_bf16_table(int N, int ntiles, const PairInfo* pairs, const bf16x2_t* src, unsigned* dst,
                                         hipStream_t s);
+
+// compile-time shapes of the contraction kernels for bandlimit B:
+// row blocks of 16 degrees (forward) and groups of 4 degrees (inverse)
+inline int beta_rtmax(int B) {
+  const int lmax = (B + 1) / 2;
+  return lmax <= 16 ? 1 : (lmax <= 32 ? 2 : 4);
+}
+inline int beta_lq(int B) {
+  const int lmax = (B + 1) / 2;
+  return lmax <= 8 ? 2 : (lmax <= 16 ? 4 : (lmax <= 32 ? 8 : 16));
+}
+// split-BF16 inverse: groups of 32 degrees
+inline int beta_bf16_lq(int B) { return (B + 1) / 2 <= 32 ? 1 : 2; }
 
 template <class T>
 bool fast_ring_supported(int N);

@@ -1,0 +1,604 @@
+// All device code of su2fft in one translation unit, plus batches of signals
+// with different bandlimits ("mixed" plans).
+//
+// A mixed plan groups its signals by bandlimit B.  Each group has the tables
+// and the ring-spectrum workspace of a single-B plan; its signals stay where
+// the caller put them (concatenated in order), reached through per-signal
+// offset tables.  A transform runs as two persistent work-list kernels: one
+// walks every (group, signal, node) ring task, the other every (group, pair
+// tile, signal tile) contraction task, each calling the same kernel bodies as
+// the single-B launches (so every signal's result is bit-identical to a
+// single-B plan's).  Tasks are ordered by decreasing cost and taken in a
+// static stride by a grid of `knob x CUs` workgroups; the knob of each kernel
+// is chosen by timing the candidates at plan creation (autotuner, cached per
+// device, mode and bandlimit mix, optionally on disk).  The two launches of a
+// call are captured once into a HIP graph per (direction, buffers, stream)
+// and replayed.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <type_traits>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "su2fft_ring.hip"
+#include "su2fft_ring_fast.hip"
+#include "su2fft_beta.hip"
+#include "su2fft_beta_bf16.hip"
+#include "su2fft_plan.h"
+
+namespace su2 {
+
+struct WorkItem {
+  int g;     // group
+  int a, b;  // ring task: (signal in group, node); contraction task: (pair tile, signal tile)
+};
+
+template <class T>
+struct GroupDev {
+  int fast;               // register-resident N = 128 ring kernels
+  int rtmax, lq, lq2;     // contraction shapes of the group's bandlimit
+  RingParams<T> rp[3];    // generic ring kernels: forward, inverse, adjoint
+  FastRingParams<T> fp[3];
+  BetaParams<T> bp[3];    // contraction: forward, inverse, adjoint
+  const unsigned* tabf_bf;  // split-BF16 tables (forward / inverse layouts)
+  const unsigned* tabi_bf;
+  cpx<T>* S;
+};
+
+// ---- work-list kernels ----
+
+// dir 0: forward (in = samples -> workspaces); 1: inverse, 2: adjoint (workspaces -> out = samples)
+template <class T>
+__global__ __launch_bounds__(512, fast_waves_per_simd<T>()) void ring_worklist_kernel(
+    const WorkItem* __restrict__ items, int n, const GroupDev<T>* __restrict__ groups, const cpx<T>* __restrict__ in,
+    cpx<T>* __restrict__ out, int dir) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const GroupDev<T>& g = groups[w.g];
+    if (dir == 0) {
+      if (g.fast) {
+        const FastRingParams<T>& p = g.fp[0];
+        ring_forward_fast_body<T, 16, 8, 512, FAST_ROUNDS>(in + ring_offset(p.soff, w.a, 128) + (size_t)w.b * 128 * 128,
+                                                           g.S, p, w.a, w.b, smem);
+      } else {
+        const RingParams<T>& p = g.rp[0];
+        ring_forward_body<T>(in + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, g.S, p, w.a, w.b, smem);
+      }
+    } else {
+      if (g.fast) {
+        const FastRingParams<T>& p = g.fp[dir];
+        ring_inverse_fast_body<T, 16, 8, 512, FAST_ROUNDS>(g.S, out + ring_offset(p.soff, w.a, 128) +
+                                                                   (size_t)w.b * 128 * 128,
+                                                           p, w.a, w.b, smem);
+      } else {
+        const RingParams<T>& p = g.rp[dir];
+        ring_inverse_body<T>(g.S, out + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b, smem);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int RTMAX_MAX>
+__global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(const WorkItem* __restrict__ items, int n,
+                                                                            const GroupDev<T>* __restrict__ groups,
+                                                                            cpx<T>* __restrict__ coeffs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const GroupDev<T>& g = groups[w.g];
+    if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+    if constexpr (RTMAX_MAX >= 2)
+      if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+    if constexpr (RTMAX_MAX >= 4)
+      if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+    __syncthreads();
+  }
+}
+
+template <class T, int LQ_MAX>
+__global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(const WorkItem* __restrict__ items, int n,
+                                                                            const GroupDev<T>* __restrict__ groups,
+                                                                            const cpx<T>* __restrict__ coeffs, int dir) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const GroupDev<T>& g = groups[w.g];
+    const BetaParams<T>& p = g.bp[dir];
+    if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem);
+    if constexpr (LQ_MAX >= 4)
+      if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem);
+    if constexpr (LQ_MAX >= 8)
+      if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem);
+    if constexpr (LQ_MAX >= 16)
+      if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem);
+    __syncthreads();
+  }
+}
+
+template <int RTMAX_MAX>
+__global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kernel(
+    const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups, cpx<float>* __restrict__ coeffs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const GroupDev<float>& g = groups[w.g];
+    if (g.rtmax == 1) beta_forward_bf16x3_body<1>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+    if constexpr (RTMAX_MAX >= 2)
+      if (g.rtmax == 2) beta_forward_bf16x3_body<2>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+    if constexpr (RTMAX_MAX >= 4)
+      if (g.rtmax == 4) beta_forward_bf16x3_body<4>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+    __syncthreads();
+  }
+}
+
+template <int LQ2_MAX>
+__global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kernel(
+    const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups,
+    const cpx<float>* __restrict__ coeffs, int dir) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const GroupDev<float>& g = groups[w.g];
+    if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem);
+    if constexpr (LQ2_MAX >= 2)
+      if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem);
+    __syncthreads();
+  }
+}
+
+}  // namespace su2
+
+// ---- mixed plans (host) ----
+
+struct MixedGraph {
+  int dir;
+  const void* in;
+  void* out;
+  hipStream_t stream;
+  hipGraphExec_t exec;
+};
+
+struct MixedState {
+  std::vector<su2_plan_s*> groups;  // one single-B plan per distinct bandlimit
+  std::vector<int> group_B;
+  long long total_samples = 0, total_coeffs = 0;
+  void* d_groups = nullptr;         // GroupDev<T>[groups]
+  su2::WorkItem* d_ring = nullptr;
+  su2::WorkItem* d_betaf = nullptr;
+  su2::WorkItem* d_betai = nullptr;
+  int n_ring = 0, n_betaf = 0, n_betai = 0;
+  size_t smem_ring = 0, smem_betaf = 0, smem_betai = 0;
+  int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
+  int num_cu = 0;
+  int knob[4] = {2, 2, 2, 2};       // workgroups per CU: ring forward, contraction forward, contraction inverse, ring inverse
+  hipStream_t cap = nullptr;
+  std::vector<MixedGraph> graphs;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+using namespace su2;
+
+hipError_t mixed_alloc(MixedState* ms, void** p, size_t n) {
+  hipError_t e = hipMalloc(p, n == 0 ? 16 : n);
+  if (e == hipSuccess) ms->allocs.push_back(*p);
+  return e;
+}
+
+// kernel selection by the plan's largest shapes
+template <class T>
+void* ring_kernel_ptr() { return (void*)ring_worklist_kernel<T>; }
+
+template <class T>
+void* betaf_kernel_ptr(int rtmax) {
+  if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1>;
+  if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2>;
+  return (void*)beta_forward_worklist_kernel<T, 4>;
+}
+template <class T>
+void* betai_kernel_ptr(int lq) {
+  if (lq <= 2) return (void*)beta_inverse_worklist_kernel<T, 2>;
+  if (lq <= 4) return (void*)beta_inverse_worklist_kernel<T, 4>;
+  if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8>;
+  return (void*)beta_inverse_worklist_kernel<T, 16>;
+}
+void* betaf_bf16_kernel_ptr(int rtmax) {
+  if (rtmax <= 1) return (void*)beta_forward_bf16x3_worklist_kernel<1>;
+  if (rtmax <= 2) return (void*)beta_forward_bf16x3_worklist_kernel<2>;
+  return (void*)beta_forward_bf16x3_worklist_kernel<4>;
+}
+void* betai_bf16_kernel_ptr(int lq2) {
+  if (lq2 <= 1) return (void*)beta_inverse_bf16x3_worklist_kernel<1>;
+  return (void*)beta_inverse_bf16x3_worklist_kernel<2>;
+}
+
+// enqueue one work-list launch: which = 0 ring forward, 1 contraction forward,
+// 2 contraction inverse/adjoint, 3 ring inverse/adjoint
+template <class T>
+hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out, hipStream_t s, int knob) {
+  MixedState* ms = pl->mixed;
+  const GroupDev<T>* g = (const GroupDev<T>*)ms->d_groups;
+  const bool bf = pl->dtype == SU2_C64_BF16X3;
+  auto grid_of = [&](int n) { return dim3((unsigned)std::max(1, std::min(n, knob * ms->num_cu))); };
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL(ring_worklist_kernel<T>, grid_of(ms->n_ring), dim3(512), ms->smem_ring, s, ms->d_ring,
+                         ms->n_ring, g, (const cpx<T>*)in, (cpx<T>*)nullptr, 0);
+      break;
+    case 3:
+      hipLaunchKernelGGL(ring_worklist_kernel<T>, grid_of(ms->n_ring), dim3(512), ms->smem_ring, s, ms->d_ring,
+                         ms->n_ring, g, (const cpx<T>*)nullptr, (cpx<T>*)out, dir);
+      break;
+    case 1:
+      if (bf) {
+        void* k = betaf_bf16_kernel_ptr(ms->rtmax);
+        void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
+        return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(XB_THREADS), args, ms->smem_betaf, s);
+      } else {
+        void* k = betaf_kernel_ptr<T>(ms->rtmax);
+        void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
+        return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(FWD_THREADS), args, ms->smem_betaf, s);
+      }
+    case 2:
+      if (bf) {
+        void* k = betai_bf16_kernel_ptr(ms->lq2);
+        void* args[] = {(void*)&ms->d_betai, (void*)&ms->n_betai, (void*)&g, (void*)&in, (void*)&dir};
+        return hipLaunchKernel(k, grid_of(ms->n_betai), dim3(XB_THREADS), args, ms->smem_betai, s);
+      } else {
+        void* k = betai_kernel_ptr<T>(ms->lq);
+        void* args[] = {(void*)&ms->d_betai, (void*)&ms->n_betai, (void*)&g, (void*)&in, (void*)&dir};
+        return hipLaunchKernel(k, grid_of(ms->n_betai), dim3(INV_THREADS), args, ms->smem_betai, s);
+      }
+  }
+  return hipGetLastError();
+}
+
+hipError_t enqueue_any(su2_plan_s* pl, int which, int dir, const void* in, void* out, hipStream_t s, int knob) {
+  return pl->dtype == SU2_C128 ? enqueue<double>(pl, which, dir, in, out, s, knob)
+                               : enqueue<float>(pl, which, dir, in, out, s, knob);
+}
+
+hipError_t enqueue_call(su2_plan_s* pl, int dir, const void* in, void* out, hipStream_t s) {
+  MixedState* ms = pl->mixed;
+  hipError_t e;
+  if (dir == 0) {
+    if ((e = enqueue_any(pl, 0, 0, in, nullptr, s, ms->knob[0])) != hipSuccess) return e;
+    return enqueue_any(pl, 1, 0, nullptr, out, s, ms->knob[1]);
+  }
+  if ((e = enqueue_any(pl, 2, dir, in, nullptr, s, ms->knob[2])) != hipSuccess) return e;
+  return enqueue_any(pl, 3, dir, nullptr, out, s, ms->knob[3]);
+}
+
+// The dynamic-LDS limit is a property of the kernel function, shared by every
+// plan: raise it to the device maximum (each launch still asks only for what
+// its plan needs).
+template <class T>
+hipError_t set_worklist_smem(su2_plan_s* pl) {
+  MixedState* ms = pl->mixed;
+  const bool bf = pl->dtype == SU2_C64_BF16X3;
+  int max_lds = 0;
+  hipError_t e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
+  if (e != hipSuccess) return e;
+  if (ms->smem_ring > (size_t)max_lds || ms->smem_betaf > (size_t)max_lds || ms->smem_betai > (size_t)max_lds)
+    return hipErrorInvalidValue;
+  void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax);
+  void* ki = bf ? betai_bf16_kernel_ptr(ms->lq2) : betai_kernel_ptr<T>(ms->lq);
+  if ((e = hipFuncSetAttribute(ring_kernel_ptr<T>(), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess) return e;
+  return hipFuncSetAttribute(ki, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+// build the per-group device descriptors, work lists and LDS sizes
+template <class T>
+su2_status_t build_worklists(su2_plan_s* pl) {
+  MixedState* ms = pl->mixed;
+  const bool bf = pl->dtype == SU2_C64_BF16X3;
+  const int ng = (int)ms->groups.size();
+  std::vector<GroupDev<T>> hg(ng);
+  std::vector<std::pair<double, WorkItem>> ring, betaf, betai;
+  for (int gi = 0; gi < ng; gi++) {
+    su2_plan_s* gp = ms->groups[gi];
+    GroupDev<T>& d = hg[gi];
+    memset(&d, 0, sizeof(d));
+    d.fast = gp->fast ? 1 : 0;
+    d.rtmax = beta_rtmax(gp->B);
+    d.lq = beta_lq(gp->B);
+    d.lq2 = beta_bf16_lq(gp->B);
+    const T* tab = std::is_same<T, double>::value ? (const T*)gp->d_tab64 : (const T*)gp->d_tab32;
+    for (int dir = 0; dir < 3; dir++) {
+      d.rp[dir] = ring_params<T>(gp, dir == 2);
+      d.fp[dir] = fast_params<T>(gp, dir == 2);
+      d.bp[dir] = beta_params<T>(gp, tab, dir == 2);
+    }
+    d.tabf_bf = gp->d_tabbf_fwd;
+    d.tabi_bf = (const unsigned*)gp->d_tabbf;
+    d.S = (cpx<T>*)gp->d_S;
+    ms->rtmax = std::max(ms->rtmax, d.rtmax);
+    ms->lq = std::max(ms->lq, d.lq);
+    ms->lq2 = std::max(ms->lq2, d.lq2);
+    const int N = gp->N;
+    // ring LDS
+    size_t rs = gp->fast ? fast_smem<T, 16, 8, 512, FAST_ROUNDS>() : ring_smem_bytes<T>(d.rp[0]);
+    ms->smem_ring = std::max(ms->smem_ring, rs);
+    const double ring_cost = (double)N * N * (N > 1 ? std::log2((double)N) : 1.0);
+    for (int i = 0; i < gp->batch; i++)
+      for (int k = 0; k < N; k++) ring.push_back({ring_cost, WorkItem{gi, i, k}});
+    const int btf = bf ? XBF_BT : BetaCfg<T>::BT;
+    const int bti = bf ? XB_BT : BetaCfg<T>::BT;
+    for (int t = 0; t < gp->ntiles; t++) {
+      const double tile_cost = (double)N * std::max(1, gp->h_pairs[t * PT].lsum);
+      for (int b = 0; b * btf < gp->batch; b++)
+        betaf.push_back({tile_cost * std::min(btf, gp->batch - b * btf), WorkItem{gi, t, b}});
+      for (int b = 0; b * bti < gp->batch; b++)
+        betai.push_back({tile_cost * std::min(bti, gp->batch - b * bti), WorkItem{gi, t, b}});
+    }
+  }
+  if (bf) {
+    ms->smem_betaf = XBF_SMEM;
+    ms->smem_betai = XBI_SMEM;
+  } else {
+    ms->smem_betaf = ms->rtmax <= 1 ? FwdGeom<T, 1>::SMEM : (ms->rtmax <= 2 ? FwdGeom<T, 2>::SMEM : FwdGeom<T, 4>::SMEM);
+    ms->smem_betai = inverse_smem<T>();
+  }
+  auto by_cost = [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
+    return x.first > y.first;
+  };
+  std::stable_sort(ring.begin(), ring.end(), by_cost);
+  std::stable_sort(betaf.begin(), betaf.end(), by_cost);
+  std::stable_sort(betai.begin(), betai.end(), by_cost);
+  std::vector<WorkItem> r, f, i;
+  for (auto& x : ring) r.push_back(x.second);
+  for (auto& x : betaf) f.push_back(x.second);
+  for (auto& x : betai) i.push_back(x.second);
+  ms->n_ring = (int)r.size();
+  ms->n_betaf = (int)f.size();
+  ms->n_betai = (int)i.size();
+  hipError_t e;
+  if ((e = mixed_alloc(ms, &ms->d_groups, sizeof(GroupDev<T>) * ng)) != hipSuccess) return hip_fail(e);
+  if ((e = mixed_alloc(ms, (void**)&ms->d_ring, sizeof(WorkItem) * r.size())) != hipSuccess) return hip_fail(e);
+  if ((e = mixed_alloc(ms, (void**)&ms->d_betaf, sizeof(WorkItem) * f.size())) != hipSuccess) return hip_fail(e);
+  if ((e = mixed_alloc(ms, (void**)&ms->d_betai, sizeof(WorkItem) * i.size())) != hipSuccess) return hip_fail(e);
+  if ((e = hipMemcpy(ms->d_groups, hg.data(), sizeof(GroupDev<T>) * ng, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(ms->d_ring, r.data(), sizeof(WorkItem) * r.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(ms->d_betaf, f.data(), sizeof(WorkItem) * f.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipMemcpy(ms->d_betai, i.data(), sizeof(WorkItem) * i.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = set_worklist_smem<T>(pl)) != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+// ---- autotuner: persistent grid size (workgroups per CU) of each work-list kernel ----
+
+std::mutex g_tune_mu;
+std::map<std::string, std::vector<int>> g_tune_cache;
+bool g_tune_file_loaded = false;
+
+std::string tune_key(const su2_plan_s* pl) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
+  std::string k = arch + ":" + std::to_string((int)pl->dtype);
+  const MixedState* ms = pl->mixed;
+  for (size_t g = 0; g < ms->groups.size(); g++)
+    k += ":" + std::to_string(ms->group_B[g]) + "x" + std::to_string(ms->groups[g]->batch);
+  return k;
+}
+
+void load_tune_file() {
+  if (g_tune_file_loaded) return;
+  g_tune_file_loaded = true;
+  const char* path = getenv("SU2_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[4096];
+  int a, b, c, d;
+  while (fscanf(f, "%4095s %d %d %d %d", key, &a, &b, &c, &d) == 5) g_tune_cache[key] = {a, b, c, d};
+  fclose(f);
+}
+
+void store_tune_file(const std::string& key, const int* k) {
+  const char* path = getenv("SU2_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %d\n", key.c_str(), k[0], k[1], k[2], k[3]);
+  fclose(f);
+}
+
+su2_status_t autotune(su2_plan_s* pl) {
+  MixedState* ms = pl->mixed;
+  const char* env = getenv("SU2_AUTOTUNE");
+  if (env && env[0] == '0') return SU2_OK;  // keep the defaults
+  const std::string key = tune_key(pl);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int i = 0; i < 4; i++) ms->knob[i] = it->second[i];
+      return SU2_OK;
+    }
+  }
+  const size_t cb = pl->dtype == SU2_C128 ? 16 : 8;
+  void *din = nullptr, *dout = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&din, cb * (size_t)ms->total_samples)) != hipSuccess) return hip_fail(e);
+  if ((e = hipMalloc(&dout, cb * (size_t)std::max(ms->total_samples, ms->total_coeffs))) != hipSuccess) {
+    (void)hipFree(din);
+    return hip_fail(e);
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipMemset(din, 0, cb * (size_t)ms->total_samples);
+  (void)hipMemset(dout, 0, cb * (size_t)std::max(ms->total_samples, ms->total_coeffs));
+  // stage order: ring forward (samples -> S), contraction forward, contraction inverse, ring inverse
+  const void* ins[4] = {din, nullptr, dout, nullptr};
+  void* outs[4] = {nullptr, dout, nullptr, din};
+  const int dirs[4] = {0, 0, 1, 1};
+  su2_status_t st = SU2_OK;
+  for (int which = 0; which < 4 && st == SU2_OK; which++) {
+    float best = 1e30f;
+    int best_k = ms->knob[which];
+    for (int kn = 1; kn <= 4; kn++) {
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; rep++) {
+        (void)hipEventRecord(e0, ms->cap);
+        if ((e = enqueue_any(pl, which, dirs[which], ins[which], outs[which], ms->cap, kn)) != hipSuccess) {
+          st = hip_fail(e);
+          break;
+        }
+        (void)hipEventRecord(e1, ms->cap);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+          st = hip_fail(e);
+          break;
+        }
+        float ms_t = 0.f;
+        (void)hipEventElapsedTime(&ms_t, e0, e1);
+        if (rep > 0) tmin = std::min(tmin, ms_t);
+      }
+      if (st != SU2_OK) break;
+      if (tmin < best) { best = tmin; best_k = kn; }
+    }
+    ms->knob[which] = best_k;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(din);
+  (void)hipFree(dout);
+  if (st != SU2_OK) return st;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = {ms->knob[0], ms->knob[1], ms->knob[2], ms->knob[3]};
+  store_tune_file(key, ms->knob);
+  return SU2_OK;
+}
+
+void destroy_mixed(su2_plan_s* pl) {
+  MixedState* ms = pl->mixed;
+  if (!ms) return;
+  for (auto& g : ms->graphs) (void)hipGraphExecDestroy(g.exec);
+  ms->graphs.clear();
+  for (su2_plan_s* gp : ms->groups) {
+    gp->release();
+    delete gp;
+  }
+  ms->groups.clear();
+  for (void* p : ms->allocs) (void)hipFree(p);
+  ms->allocs.clear();
+  if (ms->cap) (void)hipStreamDestroy(ms->cap);
+  delete ms;
+  pl->mixed = nullptr;
+}
+
+}  // namespace
+
+namespace su2 {
+
+su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, su2_plan_s* pl) {
+  MixedState* ms = new (std::nothrow) MixedState();
+  if (!ms) return SU2_ERR_OUT_OF_MEMORY;
+  pl->mixed = ms;
+  pl->dtype = dtype;
+  pl->batch = batch;
+  pl->B = -1;
+  hipError_t e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
+  pl->device = dev;
+  if ((e = hipDeviceGetAttribute(&ms->num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(e);
+  // signal offsets in the concatenated buffers, and the groups
+  std::vector<long long> soff(batch), coff(batch);
+  std::map<int, std::vector<int>> by_B;
+  for (int s = 0; s < batch; s++) {
+    const long long N = 2LL * Bs[s];
+    soff[s] = ms->total_samples;
+    coff[s] = ms->total_coeffs;
+    ms->total_samples += N * N * N;
+    ms->total_coeffs += (long long)Bs[s] * (Bs[s] + 1) * (2 * Bs[s] + 1) / 6;
+    by_B[Bs[s]].push_back(s);
+  }
+  for (auto& kv : by_B) {
+    su2_plan_s* gp = new (std::nothrow) su2_plan_s();
+    if (!gp) return SU2_ERR_OUT_OF_MEMORY;
+    ms->groups.push_back(gp);
+    ms->group_B.push_back(kv.first);
+    gp->B = kv.first;
+    gp->batch = (int)kv.second.size();
+    gp->dtype = dtype;
+    std::vector<long long> so, co;
+    for (int s : kv.second) { so.push_back(soff[s]); co.push_back(coff[s]); }
+    long long *dso = nullptr, *dco = nullptr;
+    if ((e = gp->alloc((void**)&dso, sizeof(long long) * so.size())) != hipSuccess) return hip_fail(e);
+    if ((e = gp->alloc((void**)&dco, sizeof(long long) * co.size())) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpy(dso, so.data(), sizeof(long long) * so.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipMemcpy(dco, co.data(), sizeof(long long) * co.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e);
+    gp->d_soff = dso;
+    gp->d_coff = dco;
+    su2_status_t st = build_plan(gp);
+    if (st != SU2_OK) return st;
+    pl->bytes += gp->bytes;
+  }
+  su2_status_t st = dtype == SU2_C128 ? build_worklists<double>(pl) : build_worklists<float>(pl);
+  if (st != SU2_OK) return st;
+  if ((e = hipStreamCreateWithFlags(&ms->cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+  st = autotune(pl);
+  if (st != SU2_OK) return st;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
+  return SU2_OK;
+}
+
+void release_mixed(su2_plan_s* pl) { destroy_mixed(pl); }
+
+su2_status_t run_mixed(su2_plan_s* pl, int dir, const void* in, void* out, hipStream_t stream) {
+  MixedState* ms = pl->mixed;
+  for (auto& g : ms->graphs)
+    if (g.dir == dir && g.in == in && g.out == out && g.stream == stream) {
+      hipError_t e = hipGraphLaunch(g.exec, stream);
+      return e == hipSuccess ? SU2_OK : hip_fail(e);
+    }
+  hipError_t e;
+  hipGraph_t graph = nullptr;
+  if ((e = hipStreamBeginCapture(ms->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e);
+  hipError_t le = enqueue_call(pl, dir, in, out, ms->cap);
+  e = hipStreamEndCapture(ms->cap, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(le);
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e);
+  if (ms->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(ms->graphs.front().exec);
+    ms->graphs.erase(ms->graphs.begin());
+  }
+  ms->graphs.push_back(MixedGraph{dir, in, out, stream, exec});
+  e = hipGraphLaunch(exec, stream);
+  return e == hipSuccess ? SU2_OK : hip_fail(e);
+}
+
+void mixed_tuning(const su2_plan_s* pl, int32_t* knobs) {
+  for (int i = 0; i < 4; i++) knobs[i] = pl->mixed ? pl->mixed->knob[i] : 0;
+}
+
+}  // namespace su2

@@ -160,17 +160,15 @@ __device__ void run_dit(cpx<T>* X, int nlines, int L, int es, int ls, bool line_
   }
 }
 
+// Body of one ring (signal b, node k): x is the ring's N x N input block, smem
+// holds N * Nc + 2N complex values.
 template <class T>
-__global__ __launch_bounds__(FFT_THREADS) void ring_forward_kernel(const cpx<T>* __restrict__ samples,
-                                                                   cpx<T>* __restrict__ S, RingParams<T> p) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ void ring_forward_body(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ S, const RingParams<T>& p,
+                                  int b, int k, unsigned char* smem_raw) {
   const int N = p.N, Nc = p.Nc, R = p.split, twoN = 2 * N;
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = X + N * Nc;
-  const int ring = blockIdx.x;
-  const int b = ring / N, k = ring - b * N;
   for (int t = threadIdx.x; t < twoN; t += blockDim.x) tw[t] = p.tw[t];
-  const cpx<T>* x = samples + (size_t)ring * N * N;
   const T Wk = p.W[k];
   for (int r = 0; r < R; r++) {
     __syncthreads();
@@ -212,16 +210,21 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_forward_kernel(const cpx<T>*
 }
 
 template <class T>
-__global__ __launch_bounds__(FFT_THREADS) void ring_inverse_kernel(const cpx<T>* __restrict__ S,
-                                                                   cpx<T>* __restrict__ samples, RingParams<T> p) {
+__global__ __launch_bounds__(FFT_THREADS) void ring_forward_kernel(const cpx<T>* __restrict__ samples,
+                                                                   cpx<T>* __restrict__ S, RingParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ring = blockIdx.x;
+  const int b = ring / p.N, k = ring - b * p.N;
+  ring_forward_body<T>(samples + ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, S, p, b, k, smem_raw);
+}
+
+template <class T>
+__device__ void ring_inverse_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ x, const RingParams<T>& p,
+                                  int b, int k, unsigned char* smem_raw) {
   const int N = p.N, Nc = p.Nc, R = p.split, twoN = 2 * N;
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = X + N * Nc;
-  const int ring = blockIdx.x;
-  const int b = ring / N, k = ring - b * N;
   for (int t = threadIdx.x; t < twoN; t += blockDim.x) tw[t] = p.tw[t];
-  cpx<T>* x = samples + (size_t)ring * N * N;
   const T scale = p.adjoint ? p.W[k] : T(1);
   for (int r = 0; r < R; r++) {
     __syncthreads();
@@ -260,7 +263,16 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_inverse_kernel(const cpx<T>*
 }
 
 template <class T>
-static size_t ring_smem_bytes(const RingParams<T>& p) {
+__global__ __launch_bounds__(FFT_THREADS) void ring_inverse_kernel(const cpx<T>* __restrict__ S,
+                                                                   cpx<T>* __restrict__ samples, RingParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ring = blockIdx.x;
+  const int b = ring / p.N, k = ring - b * p.N;
+  ring_inverse_body<T>(S, samples + ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, p, b, k, smem_raw);
+}
+
+template <class T>
+size_t ring_smem_bytes(const RingParams<T>& p) {
   return (size_t)(p.N * p.Nc + 2 * p.N) * sizeof(cpx<T>);
 }
 
@@ -284,6 +296,8 @@ hipError_t launch_ring_inverse(const RingParams<T>& p, const cpx<T>* S, cpx<T>* 
   return hipGetLastError();
 }
 
+template size_t ring_smem_bytes<float>(const RingParams<float>&);
+template size_t ring_smem_bytes<double>(const RingParams<double>&);
 template hipError_t launch_ring_forward<float>(const RingParams<float>&, const cpx<float>*, cpx<float>*, hipStream_t);
 template hipError_t launch_ring_forward<double>(const RingParams<double>&, const cpx<double>*, cpx<double>*,
                                                 hipStream_t);

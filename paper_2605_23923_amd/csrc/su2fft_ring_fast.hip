@@ -129,20 +129,18 @@ __device__ __forceinline__ cpx<T> halfbin(cpx<T> a) {
   return rot16<T, J * (16 / (2 * N2)), SIGN>(a);
 }
 
+// One ring (signal b, node k); x is the ring's N x N input block.
 template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(
-    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
+__device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ S,
+                                                       const FastRingParams<T>& p, int b, int k,
+                                                       unsigned char* smem_raw) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;  // e^{i pi t / N}, t = 0..2N-1
   const int t = threadIdx.x;
-  const int ring = blockIdx.x;
-  const int b = ring / N, k = ring - b * N;
   for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
-  const cpx<T>* x = samples + (size_t)ring * N * N;
 
   // ---- phase 1: radix-N2 over l2 (coalesced rows: lanes run over l1)
   const int l1 = t % N1;
@@ -272,17 +270,25 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fas
 }
 
 template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
-    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(
+    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int N = N1 * N2;
+  const int b = blockIdx.x / N, k = blockIdx.x - b * N;
+  ring_forward_fast_body<T, N1, N2, NT, ROUNDS>(samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, S, p, b, k,
+                                                smem_raw);
+}
+
+template <class T, int N1, int N2, int NT, int ROUNDS>
+__device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xo,
+                                                       const FastRingParams<T>& p, int b, int k,
+                                                       unsigned char* smem_raw) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;
   const int t = threadIdx.x;
-  const int ring = blockIdx.x;
-  const int b = ring / N, k = ring - b * N;
   for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
   const T scale = p.adjoint ? p.W[k] : T(1);
   const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
@@ -377,7 +383,6 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fas
   cpx<T> tw1[N2];
 #pragma unroll
   for (int q2 = 1; q2 < N2; q2++) tw1[q2] = tw[(2 * q2 * l1) % (2 * N)];
-  cpx<T>* xo = samples + (size_t)ring * N * N;
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
     __syncthreads();
@@ -405,6 +410,16 @@ __global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fas
 #pragma unroll
     for (int l2 = 0; l2 < N2; l2++) xo[j * N + l1 + N1 * l2] = a[s][l2];
   }
+}
+
+template <class T, int N1, int N2, int NT, int ROUNDS>
+__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
+    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int N = N1 * N2;
+  const int b = blockIdx.x / N, k = blockIdx.x - b * N;
+  ring_inverse_fast_body<T, N1, N2, NT, ROUNDS>(S, samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, p, b, k,
+                                                smem_raw);
 }
 
 template <class T, int N1, int N2, int NT, int ROUNDS>

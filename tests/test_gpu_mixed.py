@@ -1,0 +1,160 @@
+"""Mixed-bandlimit batches: persistent work-list kernels, HIP graph replay,
+autotuned grid sizes.
+
+Every signal of a mixed plan runs the same kernel bodies as a single-B plan,
+so its results must be bit-identical to a batch-1 single-B plan of that
+signal; the oracle then pins one signal per distinct bandlimit.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_23923_amd as su2
+import synth
+
+pytestmark = pytest.mark.gpu
+
+NPDT = {"c128": np.complex128, "c64": np.complex64, "c64_bf16x3": np.complex64}
+TOL = {"c128": 1e-10, "c64": 2e-5, "c64_bf16x3": 1e-5}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _mixed_inputs(Bs, dtype, seed):
+    rng = np.random.default_rng(seed)
+    xs = [synth.samples_uniform(B, 1, seed=int(rng.integers(1 << 30)), dtype=NPDT[dtype])[0].reshape(-1) for B in Bs]
+    cs = [synth.coeffs(B, 1, seed=int(rng.integers(1 << 30)), dtype=NPDT[dtype])[0] for B in Bs]
+    return xs, cs
+
+
+def _split(flat, offsets):
+    return [flat[offsets[i]:offsets[i + 1]] for i in range(len(offsets) - 1)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
+def test_mixed_bitwise_equals_single_plans(dtype):
+    Bs = [16, 64, 24, 3, 32, 48, 16, 8, 64, 32]
+    xs, cs = _mixed_inputs(Bs, dtype, 1)
+    mp = su2.MixedPlan(Bs, dtype)
+    k = mp.tuning()
+    assert len(k) == 4 and all(1 <= v <= 4 for v in k)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    f = _split(_host(mp.forward(x)), mp.coeff_offsets)
+    i = _split(_host(mp.inverse(c)), mp.sample_offsets)
+    a = _split(_host(mp.adjoint(c)), mp.sample_offsets)
+    for s, B in enumerate(Bs):
+        p = su2.Plan(B, 1, dtype)
+        N = 2 * B
+        assert np.array_equal(f[s], _host(p.forward(_dev(xs[s].reshape(1, N, N, N))))[0]), (s, B, "forward")
+        assert np.array_equal(i[s], _host(p.inverse(_dev(cs[s].reshape(1, -1)))).reshape(-1)), (s, B, "inverse")
+        assert np.array_equal(a[s], _host(p.adjoint(_dev(cs[s].reshape(1, -1)))).reshape(-1)), (s, B, "adjoint")
+        p.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_mixed_matches_oracle_one_signal_per_bandlimit(dtype):
+    Bs = [12, 24, 6, 12, 24, 32]
+    xs, cs = _mixed_inputs(Bs, dtype, 2)
+    mp = su2.MixedPlan(Bs, dtype)
+    f = _split(_host(mp.forward(_dev(np.concatenate(xs)))), mp.coeff_offsets)
+    inv = _split(_host(mp.inverse(_dev(np.concatenate(cs)))), mp.sample_offsets)
+    rng = np.random.default_rng(3)
+    seen = set()
+    for s, B in enumerate(Bs):
+        if B in seen:
+            continue
+        seen.add(B)
+        C = oracle.num_coeffs(B)
+        sel = rng.choice(C, min(C, 200), replace=False)
+        ref = oracle.forward(B, xs[s].astype(np.complex128), sel)
+        got = f[s][sel]
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert rel <= TOL[dtype], (B, rel)
+        pts = rng.choice((2 * B) ** 3, 100, replace=False)
+        ref = oracle.inverse(B, cs[s].astype(np.complex128), pts)
+        rel = np.linalg.norm(inv[s][pts] - ref) / np.linalg.norm(ref)
+        assert rel <= TOL[dtype], (B, rel)
+
+
+def test_mixed_graph_replays_with_eager_work_between():
+    """The call is captured once and replayed: replays interleaved with eager
+    torch work and synchronisations all give the eager-launch result."""
+    Bs = [16, 32, 24, 64]
+    xs, _ = _mixed_inputs(Bs, "c64", 4)
+    mp = su2.MixedPlan(Bs, "c64")
+    x = _dev(np.concatenate(xs))
+    out = torch.empty(mp.coeff_shape, dtype=torch.complex64, device="cuda")
+    ref = None
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device="cuda").cumsum(0)      # unrelated eager work
+        out.zero_()
+        mp.forward(x, out=out)
+        torch.cuda.synchronize()
+        got = _host(out).copy()
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), rep
+        del junk
+    out2 = mp.forward(x)                                          # new buffers: new graph
+    assert np.array_equal(_host(out2), ref)
+    singles = _split(ref, mp.coeff_offsets)
+    p = su2.Plan(64, 1, "c64")
+    assert np.array_equal(singles[3], _host(p.forward(_dev(xs[3].reshape(1, 128, 128, 128))))[0])
+
+
+def test_autotuner_choice_does_not_change_results():
+    Bs = [16, 48, 32, 24]
+    xs, cs = _mixed_inputs(Bs, "c64", 5)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    tuned = su2.MixedPlan(Bs, "c64")
+    old = os.environ.get("SU2_AUTOTUNE")
+    os.environ["SU2_AUTOTUNE"] = "0"
+    try:
+        plain = su2.MixedPlan(Bs, "c64")
+    finally:
+        if old is None:
+            del os.environ["SU2_AUTOTUNE"]
+        else:
+            os.environ["SU2_AUTOTUNE"] = old
+    assert plain.tuning() == [2, 2, 2, 2]
+    assert np.array_equal(_host(tuned.forward(x)), _host(plain.forward(x)))
+    assert np.array_equal(_host(tuned.adjoint(c)), _host(plain.adjoint(c)))
+
+
+def test_mixed_batch_configuration_320_signals():
+    """256 signals at B = 32 plus 64 signals with B drawn from {16, 24, 32, 48, 64}
+    (seed 33), FP32, one mixed plan; sampled signals against batch-1 plans
+    (bitwise) and one signal per distinct B against the oracle."""
+    Bs = [32] * 256 + synth.bandlimits_mixed(64, seed=33)
+    mp = su2.MixedPlan(Bs, "c64")
+    rng = np.random.default_rng(34)
+    xs = [synth.samples_uniform(B, 1, seed=1000 + s, dtype=np.complex64)[0].reshape(-1) for s, B in enumerate(Bs)]
+    f = _split(_host(mp.forward(_dev(np.concatenate(xs)))), mp.coeff_offsets)
+    checked = set()
+    for s in list(rng.choice(len(Bs), 6, replace=False)) + [256 + i for i in range(64)]:
+        B = Bs[s]
+        if s >= 256 and B in checked:
+            continue
+        p = su2.Plan(B, 1, "c64")
+        N = 2 * B
+        assert np.array_equal(f[s], _host(p.forward(_dev(xs[s].reshape(1, N, N, N))))[0]), (s, B)
+        p.close()
+        if s >= 256:
+            checked.add(B)
+            C = oracle.num_coeffs(B)
+            sel = rng.choice(C, 64, replace=False)
+            ref = oracle.forward(B, xs[s].astype(np.complex128), sel)
+            rel = np.linalg.norm(f[s][sel] - ref) / np.linalg.norm(ref)
+            assert rel <= TOL["c64"], (B, rel)
+    assert checked == set(Bs[256:])
