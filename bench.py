@@ -32,9 +32,15 @@ HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
-KERNEL_NAME = {"ring_forward": "ring_forward_kernel", "beta_forward": "beta_forward_kernel",
-               "beta_inverse": "beta_inverse_kernel", "ring_inverse": "ring_inverse_kernel",
-               "beta_adjoint": "beta_inverse_kernel", "ring_adjoint": "ring_inverse_kernel"}
+def kernel_name(stage: str, mode: str) -> str:
+    """Name of the kernel that runs `stage` at B=64, as rocprofv3 lists it (template type kept)."""
+    t = "double" if mode == "c128" else "float"
+    if stage.startswith("ring"):
+        return f"ring_{'forward' if stage == 'ring_forward' else 'inverse'}_fast<{t}>"
+    kind = "forward" if stage == "beta_forward" else "inverse"
+    if mode == "c64_bf16x3":
+        return f"beta_{kind}_bf16x3_kernel"
+    return f"beta_{kind}_kernel<{t}>"
 
 
 def retained_pairs(B: int) -> int:
@@ -148,6 +154,67 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
     return out
 
 
+def run_whole(make_plan, x, c, steps: int, warmup: int, batch: int):
+    """Time forward + inverse + adjoint through the public calls (no stage split)."""
+    import torch
+
+    plan = make_plan()
+    y = plan.forward(x)
+    xi = plan.inverse(c)
+    xa = plan.adjoint(c)
+
+    def step():
+        plan.forward(x, out=y)
+        plan.inverse(c, out=xi)
+        plan.adjoint(c, out=xa)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    info = {"ms_per_step": round(dt * 1e3, 4), "transforms_per_s": round(3 * batch / dt, 2)}
+    if hasattr(plan, "tuning"):
+        info["workgroups_per_cu"] = plan.tuning()
+    plan.close()
+    return info
+
+
+def secondary_configs(steps: int, warmup: int):
+    """The other workload shapes, timed through the public calls."""
+    import numpy as np
+    import torch
+
+    import paper_2605_23923_amd as su2
+    import synth
+
+    out = {}
+    # mixed bandlimits: 256 signals at B = 32 plus 64 with B from {16, 24, 32, 48, 64}, FP32, one plan
+    Bs = [32] * 256 + synth.bandlimits_mixed(64, seed=33)
+    ns = sum((2 * b) ** 3 for b in Bs)
+    nc = sum(b * (b + 1) * (2 * b + 1) // 6 for b in Bs)
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy((rng.uniform(-1, 1, ns) + 1j * rng.uniform(-1, 1, ns)).astype(np.complex64)).to("cuda")
+    c = torch.from_numpy(((rng.standard_normal(nc) + 1j * rng.standard_normal(nc)) / np.sqrt(2)).astype(np.complex64)).to("cuda")
+    out["mixed_320_signals_c64"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup, len(Bs))
+    out["mixed_320_signals_c64"]["signals"] = "256 x B=32 + 64 x B in {16,24,32,48,64} (seed 33)"
+    del x, c
+    torch.cuda.empty_cache()
+    # B = 128, batch 16, split-BF16 contraction
+    B, batch = 128, 16
+    N = 2 * B
+    x = torch.from_numpy(synth.samples_uniform(B, batch, seed=4, dtype=np.complex64)).to("cuda")
+    c = torch.from_numpy(synth.coeffs(B, batch, seed=4, dtype=np.complex64)).to("cuda")
+    out["b128_batch16_c64_bf16x3"] = run_whole(lambda: su2.Plan(B, batch, "c64_bf16x3"), x, c, max(2, steps // 5),
+                                               1, batch)
+    del x, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(B: int, budget_s: float):
     """The oracle's direct sum on a bounded sample: the forward transform of one
     signal restricted to a subset of its coefficients (a few of every 2l), timed
@@ -186,6 +253,8 @@ def main():
                     help="comma-separated modes also timed and reported under 'modes' ('' for none)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the mixed-bandlimit and B=128 workloads reported under 'other_workloads'")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes three times (reference for "
                          "the HBM byte counters) and exit")
@@ -223,10 +292,10 @@ def main():
     dom_ms = head["stage_ms"][dom]
     ab = algorithmic_bytes(dom, B, batch, args.mode)
     achieved = ab / (dom_ms * 1e-3)
-    roof = {"bound": "hbm", "kernel": KERNEL_NAME[dom], "stage": dom, "achieved": round(achieved / 1e9, 2),
+    roof = {"bound": "hbm", "kernel": kernel_name(dom, args.mode), "stage": dom, "achieved": round(achieved / 1e9, 2),
             "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
             "algorithmic_bytes_per_launch": ab, "avg_launch_ms": round(dom_ms, 5),
-            "traffic": measured_traffic(KERNEL_NAME[dom], args.mode, digest)}
+            "traffic": measured_traffic(kernel_name(dom, args.mode), args.mode, digest)}
 
     line = {
         "metric": "SU(2) FFT transforms/s at B=64 batch 32; %HBM/MFMA peak; plain vs BF16x2",
@@ -244,6 +313,8 @@ def main():
         "modes": {m: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for m, r in modes.items()},
         "source_digest": digest,
     }
+    if not args.no_secondary:
+        line["other_workloads"] = secondary_configs(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(B, args.cpu_budget)
     print(json.dumps(line), flush=True)
