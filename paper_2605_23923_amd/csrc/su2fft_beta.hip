@@ -125,7 +125,8 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[i][rt][ct][r] = T(0);
 
-  float4 sreg[SPT];
+  typedef T vec16 __attribute__((ext_vector_type(16 / sizeof(T))));   // one 16-byte load of S, kept in T lanes
+  vec16 sreg[SPT];
   float4 treg[TVT];
   const float4* tabv = reinterpret_cast<const float4*>(p.tab);
   long long tv0 = 0;  // first table vector of the chunk held in sT
@@ -137,9 +138,9 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       const int k = k0 + kk;
       if (k < N && bb < nb)
-        sreg[i] = *reinterpret_cast<const float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
+        sreg[i] = *reinterpret_cast<const vec16*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
       else
-        sreg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sreg[i] = vec16(T(0));
     }
     vstart = (tbase + (long long)k0 * lsum) / VE;
 #pragma unroll
@@ -155,9 +156,8 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
       const int v = threadIdx.x + FWD_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
-      const T* src = reinterpret_cast<const T*>(&sreg[i]);
 #pragma unroll
-      for (int q = 0; q < 2 * VC; q++) sS[kk * PK + bb * PB + 2 * pv * VC + q] = src[q];
+      for (int q = 0; q < 2 * VC; q++) sS[kk * PK + bb * PB + 2 * pv * VC + q] = sreg[i][q];
     }
 #pragma unroll
     for (int i = 0; i < TVT; i++)

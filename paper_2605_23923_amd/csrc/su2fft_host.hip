@@ -226,8 +226,11 @@ su2_status_t build_plan(su2_plan_s* pl) {
     pl->rbeg[r] = pidx < pl->rbeg[r] ? pidx : pl->rbeg[r];
     pl->rend[r] = pidx + 1 > pl->rend[r] ? pidx + 1 : pl->rend[r];
   }
-  for (int r = 0; r < FAST_ROUNDS; r++)
+  for (int r = 0; r < FAST_ROUNDS; r++) {
     if (pl->rend[r] < pl->rbeg[r]) pl->rbeg[r] = pl->rend[r] = 0;
+    const int cap = pl->dtype == SU2_C128 ? fast_ring_slice_capacity<double>(N) : fast_ring_slice_capacity<float>(N);
+    if (pl->fast && pl->rend[r] - pl->rbeg[r] > cap) return SU2_ERR_UNSUPPORTED;
+  }
   std::vector<int> colq(pl->Nc);
   for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
 

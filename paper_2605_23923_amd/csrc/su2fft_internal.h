@@ -83,6 +83,7 @@ __host__ __device__ inline size_t ring_offset(const long long* soff, int b, int 
 // kernels process the gamma frequencies q in FAST_ROUNDS equal slices; the
 // retained pairs of slice r occupy the index range [rbeg[r], rend[r]).
 constexpr int FAST_ROUNDS = 2;
+constexpr int FAST_NT = 512;  // threads per workgroup
 template <class T>
 struct FastRingParams {
   int N, batch;
@@ -145,6 +146,14 @@ inline int beta_bf16_lq(int B) { return (B + 1) / 2 <= 32 ? 1 : 2; }
 
 template <class T>
 bool fast_ring_supported(int N);
+// dynamic LDS bytes of one workgroup of the register-resident ring kernels,
+// and the number of rings (consecutive nodes of one signal) it transforms
+template <class T>
+size_t fast_ring_smem(int N);
+int fast_rings_per_group(int N);
+// pairs of one q slice that the kernels can stage in LDS
+template <class T>
+int fast_ring_slice_capacity(int N);
 template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
 template <class T>

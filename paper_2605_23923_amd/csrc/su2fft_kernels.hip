@@ -37,12 +37,12 @@ namespace su2 {
 
 struct WorkItem {
   int g;     // group
-  int a, b;  // ring task: (signal in group, node); contraction task: (pair tile, signal tile)
+  int a, b;  // ring task: (signal in group, first node); contraction task: (pair tile, signal tile)
 };
 
 template <class T>
 struct GroupDev {
-  int fast;               // register-resident N = 128 ring kernels
+  int fast;               // register-resident ring kernels
   int rtmax, lq, lq2;     // contraction shapes of the group's bandlimit
   RingParams<T> rp[3];    // generic ring kernels: forward, inverse, adjoint
   FastRingParams<T> fp[3];
@@ -54,35 +54,57 @@ struct GroupDev {
 
 // ---- work-list kernels ----
 
+// Ring tasks come in two lists, one per ring kernel family, so that each
+// work-list kernel keeps the register budget of its single-B counterpart.
 // dir 0: forward (in = samples -> workspaces); 1: inverse, 2: adjoint (workspaces -> out = samples)
-template <class T>
-__global__ __launch_bounds__(512, fast_waves_per_simd<T>()) void ring_worklist_kernel(
+template <class T, bool FWD>
+__global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_fast_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<T>* __restrict__ groups, const cpx<T>* __restrict__ in,
     cpx<T>* __restrict__ out, int dir) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const WorkItem w = items[it];
-    const GroupDev<T>& g = groups[w.g];
-    if (dir == 0) {
-      if (g.fast) {
-        const FastRingParams<T>& p = g.fp[0];
-        ring_forward_fast_body<T, 16, 8, 512, FAST_ROUNDS>(in + ring_offset(p.soff, w.a, 128) + (size_t)w.b * 128 * 128,
-                                                           g.S, p, w.a, w.b, smem);
-      } else {
-        const RingParams<T>& p = g.rp[0];
-        ring_forward_body<T>(in + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, g.S, p, w.a, w.b, smem);
-      }
-    } else {
-      if (g.fast) {
-        const FastRingParams<T>& p = g.fp[dir];
-        ring_inverse_fast_body<T, 16, 8, 512, FAST_ROUNDS>(g.S, out + ring_offset(p.soff, w.a, 128) +
-                                                                   (size_t)w.b * 128 * 128,
-                                                           p, w.a, w.b, smem);
-      } else {
-        const RingParams<T>& p = g.rp[dir];
-        ring_inverse_body<T>(g.S, out + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b, smem);
-      }
+    const WorkItem w = items[it];   // (signal, first node)
+    const FastRingParams<T>& p = groups[w.g].fp[dir];
+    cpx<T>* S = groups[w.g].S;
+    // The thread index passes through an empty asm statement so that the
+    // per-thread twiddle and index set-up stays inside the loop instead of
+    // being hoisted in front of it, where it would hold registers for the
+    // whole loop and spill.
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+#define SU2_FAST_CASE(NN)                                                    \
+  case NN:                                                                   \
+    if constexpr (FWD)                                                       \
+      ring_forward_fast_group<T, NN>(in, S, p, w.a, w.b, smem, t);           \
+    else                                                                     \
+      ring_inverse_fast_group<T, NN>(S, out, p, w.a, w.b, smem, t);          \
+    break;
+    switch (p.N) {
+      SU2_FAST_CASE(16)
+      SU2_FAST_CASE(32)
+      SU2_FAST_CASE(64)
+      SU2_FAST_CASE(128)
     }
+#undef SU2_FAST_CASE
+    __syncthreads();
+  }
+}
+
+template <class T, bool FWD>
+__global__ __launch_bounds__(FFT_THREADS) void ring_generic_worklist_kernel(const WorkItem* __restrict__ items, int n,
+                                                                            const GroupDev<T>* __restrict__ groups,
+                                                                            const cpx<T>* __restrict__ in,
+                                                                            cpx<T>* __restrict__ out, int dir) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const RingParams<T>& p = groups[w.g].rp[dir];
+    if constexpr (FWD)
+      ring_forward_body<T>(in + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, groups[w.g].S, p, w.a, w.b,
+                           smem);
+    else
+      ring_inverse_body<T>(groups[w.g].S, out + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b,
+                           smem);
     __syncthreads();
   }
 }
@@ -172,15 +194,18 @@ struct MixedState {
   std::vector<int> group_B;
   long long total_samples = 0, total_coeffs = 0;
   void* d_groups = nullptr;         // GroupDev<T>[groups]
-  su2::WorkItem* d_ring = nullptr;
+  su2::WorkItem* d_ringf = nullptr;   // ring tasks of the register-resident N = 128 kernels
+  su2::WorkItem* d_ringg = nullptr;   // ring tasks of the generic kernels
   su2::WorkItem* d_betaf = nullptr;
   su2::WorkItem* d_betai = nullptr;
-  int n_ring = 0, n_betaf = 0, n_betai = 0;
-  size_t smem_ring = 0, smem_betaf = 0, smem_betai = 0;
+  int n_ringf = 0, n_ringg = 0, n_betaf = 0, n_betai = 0;
+  size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
   int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
   int num_cu = 0;
   int knob[4] = {2, 2, 2, 2};       // workgroups per CU: ring forward, contraction forward, contraction inverse, ring inverse
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr;          // capture stream
+  hipStream_t side = nullptr;         // second branch: generic ring tasks run beside the fast ones
+  hipEvent_t fork = nullptr, join = nullptr;
   std::vector<MixedGraph> graphs;
   std::vector<void*> allocs;
 };
@@ -197,7 +222,13 @@ hipError_t mixed_alloc(MixedState* ms, void** p, size_t n) {
 
 // kernel selection by the plan's largest shapes
 template <class T>
-void* ring_kernel_ptr() { return (void*)ring_worklist_kernel<T>; }
+void* ringf_kernel_ptr(bool fwd) {
+  return fwd ? (void*)ring_fast_worklist_kernel<T, true> : (void*)ring_fast_worklist_kernel<T, false>;
+}
+template <class T>
+void* ringg_kernel_ptr(bool fwd) {
+  return fwd ? (void*)ring_generic_worklist_kernel<T, true> : (void*)ring_generic_worklist_kernel<T, false>;
+}
 
 template <class T>
 void* betaf_kernel_ptr(int rtmax) {
@@ -232,13 +263,40 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
   auto grid_of = [&](int n) { return dim3((unsigned)std::max(1, std::min(n, knob * ms->num_cu))); };
   switch (which) {
     case 0:
-      hipLaunchKernelGGL(ring_worklist_kernel<T>, grid_of(ms->n_ring), dim3(512), ms->smem_ring, s, ms->d_ring,
-                         ms->n_ring, g, (const cpx<T>*)in, (cpx<T>*)nullptr, 0);
+    case 3: {
+      // both ring lists present: the generic one runs on a second branch
+      // (fork/join through events, also inside a stream capture)
+      const bool both = ms->n_ringf > 0 && ms->n_ringg > 0;
+      hipStream_t sg = both ? ms->side : s;
+      hipError_t e;
+      if (both) {
+        if ((e = hipEventRecord(ms->fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ms->side, ms->fork, 0)) != hipSuccess) return e;
+      }
+      int d = which == 0 ? 0 : dir;
+      const cpx<T>* xin = (const cpx<T>*)in;
+      cpx<T>* xout = (cpx<T>*)out;
+      void* args[] = {nullptr, nullptr, (void*)&g, (void*)&xin, (void*)&xout, (void*)&d};
+      if (ms->n_ringg > 0) {
+        args[0] = (void*)&ms->d_ringg;
+        args[1] = (void*)&ms->n_ringg;
+        if ((e = hipLaunchKernel(ringg_kernel_ptr<T>(which == 0), grid_of(ms->n_ringg), dim3(FFT_THREADS), args,
+                                 ms->smem_ringg, sg)) != hipSuccess)
+          return e;
+      }
+      if (ms->n_ringf > 0) {
+        args[0] = (void*)&ms->d_ringf;
+        args[1] = (void*)&ms->n_ringf;
+        if ((e = hipLaunchKernel(ringf_kernel_ptr<T>(which == 0), grid_of(ms->n_ringf), dim3(FAST_NT), args,
+                                 ms->smem_ringf, s)) != hipSuccess)
+          return e;
+      }
+      if (both) {
+        if ((e = hipEventRecord(ms->join, ms->side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, ms->join, 0)) != hipSuccess) return e;
+      }
       break;
-    case 3:
-      hipLaunchKernelGGL(ring_worklist_kernel<T>, grid_of(ms->n_ring), dim3(512), ms->smem_ring, s, ms->d_ring,
-                         ms->n_ring, g, (const cpx<T>*)nullptr, (cpx<T>*)out, dir);
-      break;
+    }
     case 1:
       if (bf) {
         void* k = betaf_bf16_kernel_ptr(ms->rtmax);
@@ -289,12 +347,19 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
   int max_lds = 0;
   hipError_t e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
   if (e != hipSuccess) return e;
-  if (ms->smem_ring > (size_t)max_lds || ms->smem_betaf > (size_t)max_lds || ms->smem_betai > (size_t)max_lds)
+  if (ms->smem_ringf > (size_t)max_lds || ms->smem_ringg > (size_t)max_lds || ms->smem_betaf > (size_t)max_lds ||
+      ms->smem_betai > (size_t)max_lds)
     return hipErrorInvalidValue;
   void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax);
   void* ki = bf ? betai_bf16_kernel_ptr(ms->lq2) : betai_kernel_ptr<T>(ms->lq);
-  if ((e = hipFuncSetAttribute(ring_kernel_ptr<T>(), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
-    return e;
+  for (int fwd = 0; fwd < 2; fwd++) {
+    if ((e = hipFuncSetAttribute(ringf_kernel_ptr<T>(fwd), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipFuncSetAttribute(ringg_kernel_ptr<T>(fwd), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) !=
+        hipSuccess)
+      return e;
+  }
   if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess) return e;
   return hipFuncSetAttribute(ki, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
@@ -306,7 +371,7 @@ su2_status_t build_worklists(su2_plan_s* pl) {
   const bool bf = pl->dtype == SU2_C64_BF16X3;
   const int ng = (int)ms->groups.size();
   std::vector<GroupDev<T>> hg(ng);
-  std::vector<std::pair<double, WorkItem>> ring, betaf, betai;
+  std::vector<std::pair<double, WorkItem>> ringf, ringg, betaf, betai;
   for (int gi = 0; gi < ng; gi++) {
     su2_plan_s* gp = ms->groups[gi];
     GroupDev<T>& d = hg[gi];
@@ -329,11 +394,18 @@ su2_status_t build_worklists(su2_plan_s* pl) {
     ms->lq2 = std::max(ms->lq2, d.lq2);
     const int N = gp->N;
     // ring LDS
-    size_t rs = gp->fast ? fast_smem<T, 16, 8, 512, FAST_ROUNDS>() : ring_smem_bytes<T>(d.rp[0]);
-    ms->smem_ring = std::max(ms->smem_ring, rs);
     const double ring_cost = (double)N * N * (N > 1 ? std::log2((double)N) : 1.0);
-    for (int i = 0; i < gp->batch; i++)
-      for (int k = 0; k < N; k++) ring.push_back({ring_cost, WorkItem{gi, i, k}});
+    if (gp->fast) {
+      // one task per workgroup's worth of consecutive rings of a signal
+      ms->smem_ringf = std::max(ms->smem_ringf, fast_ring_smem<T>(N));
+      const int rpw = fast_rings_per_group(N);
+      for (int i = 0; i < gp->batch; i++)
+        for (int k = 0; k < N; k += rpw) ringf.push_back({ring_cost * rpw, WorkItem{gi, i, k}});
+    } else {
+      ms->smem_ringg = std::max(ms->smem_ringg, ring_smem_bytes<T>(d.rp[0]));
+      for (int i = 0; i < gp->batch; i++)
+        for (int k = 0; k < N; k++) ringg.push_back({ring_cost, WorkItem{gi, i, k}});
+    }
     const int btf = bf ? XBF_BT : BetaCfg<T>::BT;
     const int bti = bf ? XB_BT : BetaCfg<T>::BT;
     for (int t = 0; t < gp->ntiles; t++) {
@@ -354,29 +426,25 @@ su2_status_t build_worklists(su2_plan_s* pl) {
   auto by_cost = [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
     return x.first > y.first;
   };
-  std::stable_sort(ring.begin(), ring.end(), by_cost);
-  std::stable_sort(betaf.begin(), betaf.end(), by_cost);
-  std::stable_sort(betai.begin(), betai.end(), by_cost);
-  std::vector<WorkItem> r, f, i;
-  for (auto& x : ring) r.push_back(x.second);
-  for (auto& x : betaf) f.push_back(x.second);
-  for (auto& x : betai) i.push_back(x.second);
-  ms->n_ring = (int)r.size();
-  ms->n_betaf = (int)f.size();
-  ms->n_betai = (int)i.size();
   hipError_t e;
   if ((e = mixed_alloc(ms, &ms->d_groups, sizeof(GroupDev<T>) * ng)) != hipSuccess) return hip_fail(e);
-  if ((e = mixed_alloc(ms, (void**)&ms->d_ring, sizeof(WorkItem) * r.size())) != hipSuccess) return hip_fail(e);
-  if ((e = mixed_alloc(ms, (void**)&ms->d_betaf, sizeof(WorkItem) * f.size())) != hipSuccess) return hip_fail(e);
-  if ((e = mixed_alloc(ms, (void**)&ms->d_betai, sizeof(WorkItem) * i.size())) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(ms->d_groups, hg.data(), sizeof(GroupDev<T>) * ng, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
-  if ((e = hipMemcpy(ms->d_ring, r.data(), sizeof(WorkItem) * r.size(), hipMemcpyHostToDevice)) != hipSuccess)
-    return hip_fail(e);
-  if ((e = hipMemcpy(ms->d_betaf, f.data(), sizeof(WorkItem) * f.size(), hipMemcpyHostToDevice)) != hipSuccess)
-    return hip_fail(e);
-  if ((e = hipMemcpy(ms->d_betai, i.data(), sizeof(WorkItem) * i.size(), hipMemcpyHostToDevice)) != hipSuccess)
-    return hip_fail(e);
+  // each list: sorted by decreasing cost, uploaded
+  auto upload = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem** dst, int* n) -> hipError_t {
+    std::stable_sort(lst.begin(), lst.end(), by_cost);
+    std::vector<WorkItem> v;
+    for (auto& x : lst) v.push_back(x.second);
+    *n = (int)v.size();
+    hipError_t err = mixed_alloc(ms, (void**)dst, sizeof(WorkItem) * v.size());
+    if (err == hipSuccess && !v.empty())
+      err = hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice);
+    return err;
+  };
+  if ((e = upload(ringf, &ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(ringg, &ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(betaf, &ms->d_betaf, &ms->n_betaf)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(betai, &ms->d_betai, &ms->n_betai)) != hipSuccess) return hip_fail(e);
   if ((e = set_worklist_smem<T>(pl)) != hipSuccess) return hip_fail(e);
   return SU2_OK;
 }
@@ -455,7 +523,8 @@ su2_status_t autotune(su2_plan_s* pl) {
   for (int which = 0; which < 4 && st == SU2_OK; which++) {
     float best = 1e30f;
     int best_k = ms->knob[which];
-    for (int kn = 1; kn <= 4; kn++) {
+    static const int cand[] = {1, 2, 3, 4, 6, 8};
+    for (int kn : cand) {
       float tmin = 1e30f;
       for (int rep = 0; rep < 3; rep++) {
         (void)hipEventRecord(e0, ms->cap);
@@ -500,6 +569,9 @@ void destroy_mixed(su2_plan_s* pl) {
   ms->groups.clear();
   for (void* p : ms->allocs) (void)hipFree(p);
   ms->allocs.clear();
+  if (ms->fork) (void)hipEventDestroy(ms->fork);
+  if (ms->join) (void)hipEventDestroy(ms->join);
+  if (ms->side) (void)hipStreamDestroy(ms->side);
   if (ms->cap) (void)hipStreamDestroy(ms->cap);
   delete ms;
   pl->mixed = nullptr;
@@ -559,6 +631,9 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
   su2_status_t st = dtype == SU2_C128 ? build_worklists<double>(pl) : build_worklists<float>(pl);
   if (st != SU2_OK) return st;
   if ((e = hipStreamCreateWithFlags(&ms->cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+  if ((e = hipStreamCreateWithFlags(&ms->side, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+  if ((e = hipEventCreateWithFlags(&ms->fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+  if ((e = hipEventCreateWithFlags(&ms->join, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
   st = autotune(pl);
   if (st != SU2_OK) return st;
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);

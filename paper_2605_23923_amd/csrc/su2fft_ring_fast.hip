@@ -16,6 +16,11 @@
 // the LDS buffer is 1/ROUNDS of the ring.  The inverse runs the phases in
 // reverse with conjugate roots and gathers its bins straight from the beta
 // stage output, so no LDS zero fill is needed.
+//
+// A workgroup has FAST_NT threads.  For N = 128 they all work on one ring;
+// for smaller N the workgroup is split into sub-groups of NTR threads, each
+// with its own slice of LDS, working on consecutive rings of one signal (the
+// sub-groups run the same code, so the workgroup barriers line up).
 #include "su2fft_internal.h"
 
 namespace su2 {
@@ -129,17 +134,17 @@ __device__ __forceinline__ cpx<T> halfbin(cpx<T> a) {
   return rot16<T, J * (16 / (2 * N2)), SIGN>(a);
 }
 
-// One ring (signal b, node k); x is the ring's N x N input block.
+// One ring (signal b, node k); x is the ring's N x N input block, t the
+// thread's index in the workgroup.
 template <class T, int N1, int N2, int NT, int ROUNDS>
 __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ S,
                                                        const FastRingParams<T>& p, int b, int k,
-                                                       unsigned char* smem_raw) {
+                                                       unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;  // e^{i pi t / N}, t = 0..2N-1
-  const int t = threadIdx.x;
   for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
 
   // ---- phase 1: radix-N2 over l2 (coalesced rows: lanes run over l1)
@@ -270,25 +275,14 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
 }
 
 template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_forward_fast(
-    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int N = N1 * N2;
-  const int b = blockIdx.x / N, k = blockIdx.x - b * N;
-  ring_forward_fast_body<T, N1, N2, NT, ROUNDS>(samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, S, p, b, k,
-                                                smem_raw);
-}
-
-template <class T, int N1, int N2, int NT, int ROUNDS>
 __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xo,
                                                        const FastRingParams<T>& p, int b, int k,
-                                                       unsigned char* smem_raw) {
+                                                       unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;
-  const int t = threadIdx.x;
   for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
   const T scale = p.adjoint ? p.W[k] : T(1);
   const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
@@ -412,59 +406,166 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
   }
 }
 
-template <class T, int N1, int N2, int NT, int ROUNDS>
-__global__ __launch_bounds__(NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
-    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int N = N1 * N2;
-  const int b = blockIdx.x / N, k = blockIdx.x - b * N;
-  ring_inverse_fast_body<T, N1, N2, NT, ROUNDS>(S, samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, p, b, k,
-                                                smem_raw);
+// Split of the N-point transforms and threads per ring for each supported N
+// (the constraints are the static assertions of FastGeom).
+template <int N>
+struct FastCfg;
+template <>
+struct FastCfg<128> {
+  static constexpr int N1 = 16, N2 = 8, NTR = 512;
+};
+template <>
+struct FastCfg<64> {
+  static constexpr int N1 = 16, N2 = 4, NTR = 128;
+};
+template <>
+struct FastCfg<32> {
+  static constexpr int N1 = 8, N2 = 4, NTR = 64;
+};
+template <>
+struct FastCfg<16> {
+  static constexpr int N1 = 4, N2 = 4, NTR = 32;
+};
+
+template <class T, int N>
+struct FastRing {
+  typedef FastCfg<N> C;
+  typedef FastGeom<C::N1, C::N2, C::NTR, FAST_ROUNDS> G;
+  static constexpr int RPW = FAST_NT / C::NTR;  // rings per workgroup
+  static constexpr size_t RING_SMEM = ((G::BUF + 2 * N) * sizeof(cpx<T>) + 15) / 16 * 16;
+  static constexpr size_t SMEM = RPW * RING_SMEM;
+  static_assert(FAST_NT % C::NTR == 0 && N % RPW == 0, "rings per workgroup");
+};
+
+// The workgroup's RPW rings (signal b, nodes k0 .. k0 + RPW - 1); t is the
+// thread's index in the workgroup.
+template <class T, int N>
+__device__ __forceinline__ void ring_forward_fast_group(const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S,
+                                                        const FastRingParams<T>& p, int b, int k0,
+                                                        unsigned char* smem, int t) {
+  typedef FastRing<T, N> R;
+  const int sub = R::RPW == 1 ? 0 : t / R::C::NTR, k = k0 + sub;
+  ring_forward_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS>(
+      samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, S, p, b, k, smem + sub * R::RING_SMEM,
+      R::RPW == 1 ? t : t - sub * R::C::NTR);
 }
 
-template <class T, int N1, int N2, int NT, int ROUNDS>
-static size_t fast_smem() {
-  typedef FastGeom<N1, N2, NT, ROUNDS> G;
-  return (size_t)(G::BUF + 2 * G::N) * sizeof(cpx<T>);
+template <class T, int N>
+__device__ __forceinline__ void ring_inverse_fast_group(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples,
+                                                        const FastRingParams<T>& p, int b, int k0,
+                                                        unsigned char* smem, int t) {
+  typedef FastRing<T, N> R;
+  const int sub = R::RPW == 1 ? 0 : t / R::C::NTR, k = k0 + sub;
+  ring_inverse_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS>(
+      S, samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, p, b, k, smem + sub * R::RING_SMEM,
+      R::RPW == 1 ? t : t - sub * R::C::NTR);
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_forward_fast(
+    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ring0 = blockIdx.x * FastRing<T, N>::RPW;
+  const int b = ring0 / N;
+  ring_forward_fast_group<T, N>(samples, S, p, b, ring0 - b * N, smem_raw, threadIdx.x);
+}
+
+template <class T, int N>
+__global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
+    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ring0 = blockIdx.x * FastRing<T, N>::RPW;
+  const int b = ring0 / N;
+  ring_inverse_fast_group<T, N>(S, samples, p, b, ring0 - b * N, smem_raw, threadIdx.x);
 }
 
 template <class T>
 bool fast_ring_supported(int N) {
-  return N == 128;
+  return N == 16 || N == 32 || N == 64 || N == 128;
 }
 
-// the epilogue / prologue stage a slice's pair range in the exchange buffer
-template <int N1, int N2, int NT, int ROUNDS, class T>
+template <class T>
+size_t fast_ring_smem(int N) {
+  switch (N) {
+    case 16: return FastRing<T, 16>::SMEM;
+    case 32: return FastRing<T, 32>::SMEM;
+    case 64: return FastRing<T, 64>::SMEM;
+    case 128: return FastRing<T, 128>::SMEM;
+  }
+  return 0;
+}
+
+template <class T>
+int fast_ring_slice_capacity(int N) {
+  switch (N) {
+    case 16: return FastRing<T, 16>::G::BUF;
+    case 32: return FastRing<T, 32>::G::BUF;
+    case 64: return FastRing<T, 64>::G::BUF;
+    case 128: return FastRing<T, 128>::G::BUF;
+  }
+  return 0;
+}
+
+int fast_rings_per_group(int N) {
+  switch (N) {
+    case 16: return FastRing<float, 16>::RPW;
+    case 32: return FastRing<float, 32>::RPW;
+    case 64: return FastRing<float, 64>::RPW;
+    case 128: return FastRing<float, 128>::RPW;
+  }
+  return 0;
+}
+
+// the epilogue / prologue stage a slice's pair range in the ring's exchange buffer
+template <class T, int N>
 static bool slices_fit(const FastRingParams<T>& p) {
   for (int r = 0; r < FAST_ROUNDS; r++)
-    if (p.rend[r] - p.rbeg[r] > FastGeom<N1, N2, NT, ROUNDS>::BUF) return false;
-  return p.N == N1 * N2;
+    if (p.rend[r] - p.rbeg[r] > FastRing<T, N>::G::BUF) return false;
+  return p.N == N;
+}
+
+template <class T, int N>
+static hipError_t launch_fast(bool forward, const FastRingParams<T>& p, const cpx<T>* in, cpx<T>* out,
+                              hipStream_t s) {
+  typedef FastRing<T, N> R;
+  if (!slices_fit<T, N>(p)) return hipErrorInvalidValue;
+  const void* kern = forward ? (const void*)ring_forward_fast<T, N> : (const void*)ring_inverse_fast<T, N>;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)R::SMEM);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((long long)p.batch * N / R::RPW));
+  if (forward)
+    hipLaunchKernelGGL((ring_forward_fast<T, N>), grid, dim3(FAST_NT), R::SMEM, s, in, out, p);
+  else
+    hipLaunchKernelGGL((ring_inverse_fast<T, N>), grid, dim3(FAST_NT), R::SMEM, s, in, out, p);
+  return hipGetLastError();
+}
+
+template <class T>
+static hipError_t launch_fast_any(bool forward, const FastRingParams<T>& p, const cpx<T>* in, cpx<T>* out,
+                                  hipStream_t s) {
+  switch (p.N) {
+    case 16: return launch_fast<T, 16>(forward, p, in, out, s);
+    case 32: return launch_fast<T, 32>(forward, p, in, out, s);
+    case 64: return launch_fast<T, 64>(forward, p, in, out, s);
+    case 128: return launch_fast<T, 128>(forward, p, in, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s) {
-  constexpr int R = FAST_ROUNDS;
-  if (!slices_fit<16, 8, 512, R>(p)) return hipErrorInvalidValue;
-  auto kern = ring_forward_fast<T, 16, 8, 512, R>;
-  const size_t smem = fast_smem<T, 16, 8, 512, R>();
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.batch * p.N), dim3(512), smem, s, samples, S, p);
-  return hipGetLastError();
+  return launch_fast_any<T>(true, p, samples, S, s);
 }
 
 template <class T>
 hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s) {
-  constexpr int R = FAST_ROUNDS;
-  if (!slices_fit<16, 8, 512, R>(p)) return hipErrorInvalidValue;
-  auto kern = ring_inverse_fast<T, 16, 8, 512, R>;
-  const size_t smem = fast_smem<T, 16, 8, 512, R>();
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(p.batch * p.N), dim3(512), smem, s, S, samples, p);
-  return hipGetLastError();
+  return launch_fast_any<T>(false, p, S, samples, s);
 }
 
+template size_t fast_ring_smem<float>(int);
+template size_t fast_ring_smem<double>(int);
+template int fast_ring_slice_capacity<float>(int);
+template int fast_ring_slice_capacity<double>(int);
 template bool fast_ring_supported<float>(int);
 template bool fast_ring_supported<double>(int);
 template hipError_t launch_ring_forward_fast<float>(const FastRingParams<float>&, const cpx<float>*, cpx<float>*,

@@ -79,6 +79,26 @@ def test_inverse_and_adjoint_match_oracle(B, dtype):
             _check(ga[b].reshape(-1)[pts], oracle.adjoint(B, c[b], pts), TOL[dtype], f"adjoint B={B} {dtype} s{b}")
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_b32_several_rings_per_workgroup_sampled(dtype):
+    """B = 32 (N = 64, four rings per ring-kernel workgroup), odd batch: sampled
+    coefficients of the forward and sampled points of the inverse/adjoint."""
+    B, batch = 32, 5
+    x = synth.samples_uniform(B, batch, seed=131, dtype=NPDT[dtype])
+    c = synth.coeffs(B, batch, seed=132, dtype=NPDT[dtype])
+    plan = su2.Plan(B, batch, dtype)
+    got = _host(plan.forward(_dev(x)))
+    gi = _host(plan.inverse(_dev(c)))
+    ga = _host(plan.adjoint(_dev(c)))
+    rng = np.random.default_rng(33)
+    sel = rng.choice(oracle.num_coeffs(B), 300, replace=False)
+    pts = rng.choice((2 * B) ** 3, 300, replace=False)
+    for b in (0, 4):
+        _check(got[b][sel], oracle.forward(B, x[b], sel), TOL[dtype], f"forward B=32 {dtype} s{b}")
+        _check(gi[b].reshape(-1)[pts], oracle.inverse(B, c[b], pts), TOL[dtype], f"inverse B=32 {dtype} s{b}")
+        _check(ga[b].reshape(-1)[pts], oracle.adjoint(B, c[b], pts), TOL[dtype], f"adjoint B=32 {dtype} s{b}")
+
+
 @pytest.mark.parametrize("B", [1, 2, 3, 8, 16, 32, 64])
 def test_round_trip_bandlimited(B):
     """Exact quadrature: forward(inverse(c)) = c on the GPU (FP64)."""
