@@ -111,15 +111,18 @@ struct FastGeom {
   static_assert(N1 % 4 == 0, "alpha pruning");
 };
 
+// v * i^e * s for e in 0..3, without branches (e differs between lanes)
 template <class T>
-__device__ __forceinline__ cpx<T> ipow_mul(cpx<T> v, int e) {  // v * i^e
-  switch (e & 3) {
-    case 0: return v;
-    case 1: return {-v.im, v.re};
-    case 2: return {-v.re, -v.im};
-    default: return {v.im, -v.re};
-  }
+__device__ __forceinline__ cpx<T> ipow_scale(cpx<T> v, int e, T s) {
+  const T ss = (e & 2) ? -s : s;
+  const T c = (e & 1) ? T(0) : ss;  // Re(i^e) s
+  const T d = (e & 1) ? ss : T(0);  // Im(i^e) s
+  return {v.re * c - v.im * d, v.re * d + v.im * c};
 }
+
+// rows p1 of an N1-point output that can hold retained bins: [0, N1/4) and [3 N1/4, N1)
+template <int N1>
+__device__ __forceinline__ constexpr int kept_row(int i) { return i < N1 / 4 ? i : i + N1 / 2; }
 
 // FP32 rings: two workgroups per CU (64 KB LDS slices, at most 128 VGPRs);
 // FP64 rings: one workgroup per CU.
@@ -243,17 +246,22 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
   const T Wk = p.W[k];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
+    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
+    const int q = t / N2 + (NT / N2) * r;
+    // this thread's bin entries for the round, fetched before the exchange so
+    // that their latency hides behind it
+    int ent[N1 / 2];
+#pragma unroll
+    for (int i = 0; i < N1 / 2; i++) ent[i] = p.bins[q * N + p2 + N2 * kept_row<N1>(i)];
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int q = t / N1 + (NT / N1) * si;
+      const int qq = t / N1 + (NT / N1) * si;
 #pragma unroll
-      for (int pp = 0; pp < N2; pp++) buf[((q - r * G::QR) * N2 + pp) * G::P3 + j1] = a[si][pp];
+      for (int pp = 0; pp < N2; pp++) buf[((qq - r * G::QR) * N2 + pp) * G::P3 + j1] = a[si][pp];
     }
     __syncthreads();
-    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
-    const int q = t / N2 + (NT / N2) * r;
     cpx<T> h[N1];
 #pragma unroll
     for (int m = 0; m < N1; m++) h[m] = buf[((q - r * G::QR) * N2 + p2) * G::P3 + m];
@@ -261,11 +269,8 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
     dftr<T, N1, 1>(h);
     const int pb = p.rbeg[r], pe = p.rend[r];
 #pragma unroll
-    for (int p1 = 0; p1 < N1; p1++) {
-      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;  // never retained
-      const int ent = p.bins[q * N + p2 + N2 * p1];
-      if (ent >= 0) buf[(ent >> 2) - pb] = cscale(ipow_mul(h[p1], ent & 3), Wk);
-    }
+    for (int i = 0; i < N1 / 2; i++)
+      if (ent[i] >= 0) buf[(ent[i] >> 2) - pb] = ipow_scale(h[kept_row<N1>(i)], ent[i] & 3, Wk);
     __syncthreads();
     for (int pi = pb + t; pi < pe; pi += NT) {
       const int tile = pi / PT;
@@ -293,21 +298,26 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
     const int pb = p.rbeg[r], pe = p.rend[r];
+    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
+    const int q = t / N2 + (NT / N2) * r;
+    int ent[N1 / 2];
+#pragma unroll
+    for (int i = 0; i < N1 / 2; i++) ent[i] = p.bins[q * N + p2 + N2 * kept_row<N1>(i)];
     __syncthreads();
     for (int pi = pb + t; pi < pe; pi += NT) {
       const int tile = pi / PT;
       buf[pi - pb] = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
     }
     __syncthreads();
-    static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
-    const int q = t / N2 + (NT / N2) * r;
     cpx<T> h[N1];
 #pragma unroll
-    for (int p1 = 0; p1 < N1; p1++) {
-      h[p1] = {T(0), T(0)};
-      if (p1 >= N1 / 4 && p1 < 3 * N1 / 4) continue;
-      const int ent = p.bins[q * N + p2 + N2 * p1];
-      if (ent >= 0) h[p1] = cscale(ipow_mul(buf[(ent >> 2) - pb], 4 - (ent & 3)), scale);
+    for (int p1 = 0; p1 < N1; p1++) h[p1] = {T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < N1 / 2; i++) {
+      // every lane reads a valid slot; bins that are not retained are zeroed
+      const int e = ent[i];
+      const cpx<T> v = ipow_scale(buf[e >= 0 ? (e >> 2) - pb : 0], (4 - (e & 3)) & 3, scale);
+      h[kept_row<N1>(i)] = e >= 0 ? v : cpx<T>{T(0), T(0)};
     }
     dftr<T, N1, -1>(h);
     __syncthreads();
