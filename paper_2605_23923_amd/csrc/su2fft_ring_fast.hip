@@ -104,12 +104,29 @@ struct FastGeom {
   static constexpr int BUF2 = QR * P2;
   static constexpr int BUF3 = QR * N2 * P3;
   static constexpr int BUF = BUF1 > BUF2 ? (BUF1 > BUF3 ? BUF1 : BUF3) : (BUF2 > BUF3 ? BUF2 : BUF3);
+  // A q slice (half of the gamma frequencies) holds at most (N/2)^2 retained
+  // pairs; the inverse keeps a slice in registers, SLICE_PER_THREAD per thread.
+  static constexpr int SLICE_PER_THREAD = (N / 2) * (N / 2) / NT;
+  static constexpr int SLICE_CAP = SLICE_PER_THREAD * NT < BUF ? SLICE_PER_THREAD * NT : BUF;
+  static_assert((N / 2) * (N / 2) % NT == 0, "slice split");
   static_assert(NT % N == 0 && NT % N1 == 0 && NT % N2 == 0, "thread count");
   static_assert(N2 % ROUNDS == 0 && (N2 / ROUNDS) % (NT / N) == 0, "exchange-1 rounds align with phase-2 instances");
   static_assert(QR % (NT / N1) == 0 && QR % N2 == 0, "exchange-2 rounds align with phase-3 instances");
   static_assert(QR == NT / N2 * (I2 / ROUNDS) || I2 % ROUNDS == 0, "exchange-3 rounds align with phase-4 instances");
   static_assert(N1 % 4 == 0, "alpha pruning");
 };
+
+// The samples are read or written exactly once: non-temporal accesses keep
+// them from evicting the ring spectra and tables from the caches.
+template <class T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T>* a) {
+  return {__builtin_nontemporal_load(&a->re), __builtin_nontemporal_load(&a->im)};
+}
+template <class T>
+__device__ __forceinline__ void st_stream(cpx<T>* a, cpx<T> v) {
+  __builtin_nontemporal_store(v.re, &a->re);
+  __builtin_nontemporal_store(v.im, &a->im);
+}
 
 // v * i^e * s for e in 0..3, without branches (e differs between lanes)
 template <class T>
@@ -157,7 +174,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
   for (int s = 0; s < G::I1; s++) {
     const int j = t / N1 + (NT / N1) * s;
 #pragma unroll
-    for (int l2 = 0; l2 < N2; l2++) a[s][l2] = x[j * N + l1 + N1 * l2];
+    for (int l2 = 0; l2 < N2; l2++) a[s][l2] = ld_stream(x + j * N + l1 + N1 * l2);
   }
   __syncthreads();
   cpx<T> tw1[N2];  // w^{q2 l1}: this thread's l1 is the same in every instance
@@ -292,8 +309,21 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
   const T scale = p.adjoint ? p.W[k] : T(1);
   const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
 
-  // ---- per round: bring the slice's retained bins into LDS in whole rows,
-  //      gather, phase 4' (radix-N1 over p1 -> j1), exchange 3' (write)
+  // ---- the retained bins of both slices are fetched up front (one exposed
+  //      latency per ring); then per round: stage the slice in LDS, gather,
+  //      phase 4' (radix-N1 over p1 -> j1), exchange 3' (write)
+  constexpr int SPR = G::SLICE_PER_THREAD;
+  cpx<T> sv[ROUNDS][SPR];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; r++) {
+    const int pb = p.rbeg[r], pe = p.rend[r];
+#pragma unroll
+    for (int i = 0; i < SPR; i++) {
+      const int pi = pb + t + NT * i;
+      const int tile = pi / PT;
+      sv[r][i] = pi < pe ? S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] : cpx<T>{T(0), T(0)};
+    }
+  }
   cpx<T> a[G::I1][N2];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
@@ -304,10 +334,9 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
     for (int i = 0; i < N1 / 2; i++) ent[i] = p.bins[q * N + p2 + N2 * kept_row<N1>(i)];
     __syncthreads();
-    for (int pi = pb + t; pi < pe; pi += NT) {
-      const int tile = pi / PT;
-      buf[pi - pb] = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
-    }
+#pragma unroll
+    for (int i = 0; i < SPR; i++)
+      if (pb + t + NT * i < pe) buf[t + NT * i] = sv[r][i];
     __syncthreads();
     cpx<T> h[N1];
 #pragma unroll
@@ -412,7 +441,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmulc(a[s][q2], tw1[q2]);
     dftr<T, N2, -1>(a[s]);
 #pragma unroll
-    for (int l2 = 0; l2 < N2; l2++) xo[j * N + l1 + N1 * l2] = a[s][l2];
+    for (int l2 = 0; l2 < N2; l2++) st_stream(xo + j * N + l1 + N1 * l2, a[s][l2]);
   }
 }
 
@@ -508,10 +537,10 @@ size_t fast_ring_smem(int N) {
 template <class T>
 int fast_ring_slice_capacity(int N) {
   switch (N) {
-    case 16: return FastRing<T, 16>::G::BUF;
-    case 32: return FastRing<T, 32>::G::BUF;
-    case 64: return FastRing<T, 64>::G::BUF;
-    case 128: return FastRing<T, 128>::G::BUF;
+    case 16: return FastRing<T, 16>::G::SLICE_CAP;
+    case 32: return FastRing<T, 32>::G::SLICE_CAP;
+    case 64: return FastRing<T, 64>::G::SLICE_CAP;
+    case 128: return FastRing<T, 128>::G::SLICE_CAP;
   }
   return 0;
 }
@@ -530,7 +559,7 @@ int fast_rings_per_group(int N) {
 template <class T, int N>
 static bool slices_fit(const FastRingParams<T>& p) {
   for (int r = 0; r < FAST_ROUNDS; r++)
-    if (p.rend[r] - p.rbeg[r] > FastRing<T, N>::G::BUF) return false;
+    if (p.rend[r] - p.rbeg[r] > FastRing<T, N>::G::SLICE_CAP) return false;
   return p.N == N;
 }
 
