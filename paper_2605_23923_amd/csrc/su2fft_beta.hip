@@ -63,8 +63,6 @@ struct BetaCfg<double> {
   static constexpr int BT = 16;  // 32 real columns
 };
 
-constexpr int KC = 8;  // beta nodes per streamed chunk (forward)
-
 // Forward contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
 // pairs w and w + 8 of the tile.  The workgroup streams the tile's S slab and
 // table rows through LDS in chunks of KC nodes, fetching chunk c+1 into
@@ -73,6 +71,7 @@ constexpr int FWD_THREADS = 512;
 
 template <class T, int RTMAX>
 struct FwdGeom {
+  static constexpr int KC = 8;  // beta nodes per streamed chunk
   static constexpr int BT = BetaCfg<T>::BT;
   static constexpr int PB = 2 * PT + 2;
   static constexpr int PK = BT * PB + 16;
@@ -85,9 +84,10 @@ struct FwdGeom {
 
 template <class T, int RTMAX>
 __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
-                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem) {
+                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
   typedef typename acc4<T>::type accT;
   constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int KC = FwdGeom<T, RTMAX>::KC;
   constexpr int PB = 2 * PT + 2;            // reals per (node, signal) row: 16 pairs x (re, im) + pad
   constexpr int PK = BT * PB + 16;          // reals per node
   constexpr int TMAX = PT * 16 * RTMAX;     // longest tile row
@@ -103,7 +103,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
 
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
   const PairInfo p0 = p.pairs[tile * PT];
@@ -133,7 +133,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   auto fetch = [&](int k0, long long& vstart) {
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
-      const int v = threadIdx.x + FWD_THREADS * i;
+      const int v = tid + FWD_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       const int k = k0 + kk;
@@ -142,18 +142,20 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
       else
         sreg[i] = vec16(T(0));
     }
+    // the chunk's table rows only: [k0 lsum, (k0 + KC) lsum) of the tile block
     vstart = (tbase + (long long)k0 * lsum) / VE;
+    const long long vend = min(vlast, (tbase + (long long)(k0 + KC) * lsum + VE - 1) / VE);
 #pragma unroll
     for (int i = 0; i < TVT; i++) {
-      const long long v = vstart + threadIdx.x + FWD_THREADS * i;
-      if (threadIdx.x + FWD_THREADS * i < TV && v < vlast) treg[i] = tabv[v];
+      const long long v = vstart + tid + FWD_THREADS * i;
+      if (tid + FWD_THREADS * i < TV && v < vend) treg[i] = tabv[v];
       else treg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   auto commit = [&]() {
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
-      const int v = threadIdx.x + FWD_THREADS * i;
+      const int v = tid + FWD_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
 #pragma unroll
@@ -161,7 +163,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
     }
 #pragma unroll
     for (int i = 0; i < TVT; i++)
-      reinterpret_cast<float4*>(sT)[threadIdx.x + FWD_THREADS * i] = treg[i];
+      reinterpret_cast<float4*>(sT)[tid + FWD_THREADS * i] = treg[i];
   };
 
   const int nchunk = (N + KC - 1) / KC;
@@ -238,29 +240,39 @@ template <class T, int RTMAX>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw);
+  beta_forward_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
 // pairs w and w + 8.  Each wave keeps its pairs' scaled coefficients as
 // matrix-core B operands in registers, then sweeps the N nodes in blocks of
 // 16; a block's outputs for all 16 pairs are gathered in LDS and written as
-// full PT-pair rows of S.
+// full PT-pair rows of S.  The table values of the next block are fetched
+// while the current block is staged and written.
 constexpr int INV_THREADS = 512;
 
+// staging buffer: 16 node rows of BT (signal) rows of PB reals, each node row
+// padded by 4 reals so that the four accumulator row groups of a wave's
+// stores fall into different LDS banks
 template <class T>
-constexpr size_t inverse_smem() { return (size_t)16 * BetaCfg<T>::BT * (2 * PT + 2) * sizeof(T); }
+struct InvStage {
+  static constexpr int PB = 2 * PT + 2;
+  static constexpr int NRS = BetaCfg<T>::BT * PB + 4;
+};
+
+template <class T>
+constexpr size_t inverse_smem() { return (size_t)16 * InvStage<T>::NRS * sizeof(T); }
 
 template <class T, int LQ>
 __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
-                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem) {
+                                                  const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
   typedef typename acc4<T>::type accT;
   constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
-  constexpr int PB = 2 * PT + 2;  // reals per (node, signal) row in the staging buffer
+  constexpr int PB = InvStage<T>::PB, NRS = InvStage<T>::NRS;
   T* stage = reinterpret_cast<T*>(smem);
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
   const T* cin = reinterpret_cast<const T*>(coeffs);
@@ -292,6 +304,22 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
     }
   }
 
+  // table values of a block of 16 nodes: A operands (row = node, col = degree)
+  T av[2][LQ];
+  auto fetch_a = [&](int k0) {
+    const int k = k0 + lrow;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int L = pi[q].L;
+      const T* trow = tabt + (size_t)k * lsum + pi[q].coff;
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+        const int l = 4 * s + lk;
+        av[q][s] = (4 * s < L && l < L && k < N) ? trow[l] : T(0);
+      }
+    }
+  };
+  fetch_a(0);
   for (int k0 = 0; k0 < N; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < 2; q++) {
@@ -302,15 +330,11 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
       for (int ct = 0; ct < CT; ct++)
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[ct][r] = T(0);
-      const int k = k0 + lrow;
-      const T* trow = tabt + (size_t)k * lsum + pi[q].coff;
 #pragma unroll
       for (int s = 0; s < LQ; s++) {
         if (4 * s < L) {
-          const int l = 4 * s + lk;
-          const T a = (l < L && k < N) ? trow[l] : T(0);
 #pragma unroll
-          for (int ct = 0; ct < CT; ct++) acc[ct] = mfma16x16x4(a, bop[q][s][ct], acc[ct]);
+          for (int ct = 0; ct < CT; ct++) acc[ct] = mfma16x16x4(av[q][s], bop[q][s][ct], acc[ct]);
         }
       }
 #pragma unroll
@@ -318,18 +342,19 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
         const int cc = ct * 16 + lrow;
         const int bb = cc >> 1, reim = cc & 1;
 #pragma unroll
-        for (int r = 0; r < 4; r++) stage[(acc_row<T>(lane, r) * BT + bb) * PB + 2 * pp + reim] = acc[ct][r];
+        for (int r = 0; r < 4; r++) stage[acc_row<T>(lane, r) * NRS + bb * PB + 2 * pp + reim] = acc[ct][r];
       }
     }
+    if (k0 + 16 < N) fetch_a(k0 + 16);
     __syncthreads();
     // write the block: rows (node, signal) of PT pairs, 16 bytes per thread-store
     constexpr int VC = 16 / (int)sizeof(cpx<T>);
-    for (int v = threadIdx.x; v < 16 * BT * (PT / VC); v += INV_THREADS) {
+    for (int v = tid; v < 16 * BT * (PT / VC); v += INV_THREADS) {
       const int row = v / (PT / VC), pv = v - row * (PT / VC);
       const int kk = row / BT, bb = row - kk * BT;
       const int k = k0 + kk;
       if (k < N && bb < nb) {
-        const T* src = stage + row * PB + 2 * pv * VC;
+        const T* src = stage + kk * NRS + bb * PB + 2 * pv * VC;
         float4 w;
         T* wd = reinterpret_cast<T*>(&w);
 #pragma unroll
@@ -345,7 +370,7 @@ template <class T, int LQ>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
                                                                    cpx<T>* __restrict__ S, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_body<T, LQ>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw);
+  beta_inverse_body<T, LQ>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)

@@ -72,7 +72,7 @@ template <int RTMAX>
 __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __restrict__ S,
                                                          cpx<float>* __restrict__ coeffs, const BetaParams<float>& p,
                                                          const unsigned* __restrict__ tabf, int tile, int bt,
-                                                         unsigned char* smem) {
+                                                         unsigned char* smem, int tid) {
   constexpr int BT = XBF_BT, CT = 2 * BT / 16, KC = XB_KC;
   constexpr int PB = 2 * PT + 2;
   constexpr int PK = BT * PB + 16;
@@ -84,7 +84,7 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
 
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lg = lane >> 4;
   const int N = p.N;
   const int NB8 = (N + 7) / 8;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
-      const int v = threadIdx.x + XB_THREADS * i;
+      const int v = tid + XB_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       const int k = k0 + kk;
@@ -123,7 +123,7 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
   auto commit = [&]() {
 #pragma unroll
     for (int i = 0; i < SPT; i++) {
-      const int v = threadIdx.x + XB_THREADS * i;
+      const int v = tid + XB_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       float* d = sS + kk * PK + bb * PB + 2 * pv * VC;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, blockIdx.x, blockIdx.y, smem_raw);
+  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8 and
@@ -223,13 +223,13 @@ template <int LQ>
 __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __restrict__ coeffs,
                                                          cpx<float>* __restrict__ S, const BetaParams<float>& p,
                                                          const unsigned* __restrict__ tabi, int tile, int bt,
-                                                         unsigned char* smem) {
+                                                         unsigned char* smem, int tid) {
   constexpr int BT = XB_BT, CT = 2 * BT / 16;
   constexpr int PB = 2 * PT + 2;
   float* stage = reinterpret_cast<float*>(smem);
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lg = lane >> 4;
   const int N = p.N;
   const float* cin = reinterpret_cast<const float*>(coeffs);
@@ -302,7 +302,7 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
       }
     }
     __syncthreads();
-    for (int v = threadIdx.x; v < 16 * BT * (PT / 2); v += XB_THREADS) {
+    for (int v = tid; v < 16 * BT * (PT / 2); v += XB_THREADS) {
       const int row = v / (PT / 2), pv = v - row * (PT / 2);
       const int kk = row / BT, bb = row - kk * BT;
       const int k = k0 + kk;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_bf16x3_body<LQ>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw);
+  beta_inverse_bf16x3_body<LQ>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Reorder the tile-major split table into the node-interleaved forward layout.

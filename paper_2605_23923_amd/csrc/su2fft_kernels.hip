@@ -116,12 +116,14 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+    if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     if constexpr (RTMAX_MAX >= 2)
-      if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+      if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     if constexpr (RTMAX_MAX >= 4)
-      if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem);
+      if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     __syncthreads();
   }
 }
@@ -133,15 +135,17 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
     const BetaParams<T>& p = g.bp[dir];
-    if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem);
+    if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
     if constexpr (LQ_MAX >= 4)
-      if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem);
+      if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem, t);
     if constexpr (LQ_MAX >= 8)
-      if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem);
+      if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem, t);
     if constexpr (LQ_MAX >= 16)
-      if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem);
+      if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
     __syncthreads();
   }
 }
@@ -152,12 +156,14 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kerne
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.rtmax == 1) beta_forward_bf16x3_body<1>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+    if (g.rtmax == 1) beta_forward_bf16x3_body<1>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     if constexpr (RTMAX_MAX >= 2)
-      if (g.rtmax == 2) beta_forward_bf16x3_body<2>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+      if (g.rtmax == 2) beta_forward_bf16x3_body<2>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     if constexpr (RTMAX_MAX >= 4)
-      if (g.rtmax == 4) beta_forward_bf16x3_body<4>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem);
+      if (g.rtmax == 4) beta_forward_bf16x3_body<4>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     __syncthreads();
   }
 }
@@ -169,10 +175,12 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem);
+    if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     if constexpr (LQ2_MAX >= 2)
-      if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem);
+      if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     __syncthreads();
   }
 }
