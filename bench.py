@@ -14,7 +14,8 @@ around the K timed steps (bracketed by device synchronisation).  Every kernel
 is bracketed by HIP events on the stream it runs on; `roofline` reports the
 kernel with the largest share of the step against the HBM peak, with its
 algorithmic bytes per launch.  `cpu_baseline` times the CPU oracle (direct
-quadrature sum) on a bounded sample of the same forward workload.
+quadrature sum) on a bounded sample of the same forward workload, and
+`cpu_fft_baseline` a plain CPU FFT-based separated transform (float64) beside it.
 """
 from __future__ import annotations
 
@@ -242,6 +243,26 @@ def cpu_baseline(B: int, budget_s: float):
                       f"{(2 * B) ** 3} terms each), {dt:.1f} s; scaled by {C}/{count}"}
 
 
+def cpu_fft_baseline(B: int):
+    """A plain CPU FFT-based separated transform (scipy.fft + numpy matmul,
+    float64, all host cores): forward transforms of a batch of 4 signals,
+    best of 3 after a warm-up; tables built once, before timing."""
+    import oracle.cpu_fft as cf
+    import synth
+
+    plan = cf.CpuFFTPlan(B)
+    x = synth.samples_uniform(B, 4, seed=5)
+    plan.forward(x)
+    best = 1e30
+    for _ in range(3):
+        t0 = time.perf_counter()
+        plan.forward(x)
+        best = min(best, time.perf_counter() - t0)
+    return {"value": round(4 / best, 3), "unit": "transforms/s", "cores": plan.workers, "kind": "cpu_fft",
+            "sample": f"forward, B={B}, batch 4, scipy.fft (workers={plan.workers}) + numpy matmul in float64, "
+                      f"best of 3: {best:.2f} s; table build excluded"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +338,7 @@ def main():
         line["other_workloads"] = secondary_configs(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(B, args.cpu_budget)
+        line["cpu_fft_baseline"] = cpu_fft_baseline(B)
     print(json.dumps(line), flush=True)
 
 

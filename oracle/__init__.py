@@ -55,6 +55,9 @@ def _load():
     lib.orc_jacobi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.orc_wigner_d.restype = ctypes.c_double
     lib.orc_wigner_d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_wigner_d_many.restype = None
+    lib.orc_wigner_d_many.argtypes = [i64, ip, ip, ip, dp, dp]
     lib.orc_basis.restype = None
     lib.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
     lib.orc_forward.restype = None
@@ -107,6 +110,17 @@ def jacobi(s: int, a: int, b: int, x: float) -> float:
 def wigner_d(tl: int, ta: int, tb: int, beta: float) -> float:
     """Wigner small-d d^l_{a b}(beta) with doubled indices."""
     return float(_load().orc_wigner_d(tl, ta, tb, float(beta)))
+
+
+def wigner_d_many(tl, ta, tb, beta) -> np.ndarray:
+    """Vectorised ``wigner_d`` over equally long argument arrays."""
+    tl, ta, tb = (np.ascontiguousarray(np.asarray(v, dtype=np.int32)) for v in (tl, ta, tb))
+    be = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+    out = np.zeros(be.size)
+    ip = ctypes.POINTER(ctypes.c_int)
+    _load().orc_wigner_d_many(be.size, tl.ctypes.data_as(ip), ta.ctypes.data_as(ip), tb.ctypes.data_as(ip),
+                              _dptr(be), _dptr(out))
+    return out
 
 
 def basis(tl: int, tm: int, tn: int, beta: float) -> complex:

@@ -162,6 +162,13 @@ double orc_wigner_d(int tl, int ta, int tb, double beta) {
   return sign * exp(lognorm) * pa * pb * orc_jacobi(kk, a, b, cos(beta));
 }
 
+/* d^l_{ab}(beta) for n independent argument tuples (doubled indices), in
+ * parallel; used to fill the tables of the CPU FFT-based baseline. */
+void orc_wigner_d_many(int64_t n, const int* tl, const int* ta, const int* tb, const double* beta, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; i++) out[i] = orc_wigner_d(tl[i], ta[i], tb[i], beta[i]);
+}
+
 /* P^l_{nm}(cos beta) = i^{m-n} d^l_{nm}(beta) (doubled indices) */
 static cplx basis_P(int tl, int tm, int tn, double beta) {
   return c_scale(i_pow((tm - tn) / 2), orc_wigner_d(tl, tn, tm, beta));
