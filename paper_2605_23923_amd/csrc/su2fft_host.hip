@@ -158,7 +158,8 @@ su2_status_t build_plan(su2_plan_s* pl) {
   // the register-resident ring kernels handle the whole ring themselves and
   // want the pairs ordered by 2m alone
   pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
-  if (pl->fast) split = 1;
+  pl->large = !pl->fast && pl->allow_large && large_ring_supported(N);
+  if (pl->fast || pl->large) split = 1;
   pl->split = split;
   pl->Nc = N / split;
   pl->nrad_c = radix_plan(pl->Nc, pl->rad_c);
@@ -231,6 +232,22 @@ su2_status_t build_plan(su2_plan_s* pl) {
     const int cap = pl->dtype == SU2_C128 ? fast_ring_slice_capacity<double>(N) : fast_ring_slice_capacity<float>(N);
     if (pl->fast && pl->rend[r] - pl->rbeg[r] > cap) return SU2_ERR_UNSUPPORTED;
   }
+  // two-pass kernels: pair range of every block of gamma frequencies
+  std::vector<int> qrange;
+  if (pl->large) {
+    const int qb = large_ring_block(), nblk = N / qb;
+    qrange.assign(2 * nblk, 0);
+    for (int blk = 0; blk < nblk; blk++) { qrange[2 * blk] = pl->P; qrange[2 * blk + 1] = 0; }
+    for (int pidx = 0; pidx < pl->P; pidx++) {
+      const int blk = imod(pairs[pidx].tm, N) / qb;
+      qrange[2 * blk] = std::min(qrange[2 * blk], pidx);
+      qrange[2 * blk + 1] = std::max(qrange[2 * blk + 1], pidx + 1);
+    }
+    for (int blk = 0; blk < nblk; blk++) {
+      if (qrange[2 * blk + 1] < qrange[2 * blk]) qrange[2 * blk] = qrange[2 * blk + 1] = 0;
+      if (qrange[2 * blk + 1] - qrange[2 * blk] > large_ring_slice_capacity()) return SU2_ERR_UNSUPPORTED;
+    }
+  }
   std::vector<int> colq(pl->Nc);
   for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
 
@@ -281,6 +298,16 @@ su2_status_t build_plan(su2_plan_s* pl) {
       return hip_fail(e);
   }
   if ((e = pl->alloc(&pl->d_S, cb * (size_t)pl->P_pad * N * pl->batch)) != hipSuccess) return hip_fail(e);
+  if (pl->large) {
+    // intermediate of the two-pass ring kernels: a chunk of rings, at most 128 MB
+    const size_t ring_bytes = cb * (size_t)N * N;
+    pl->large_chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)pl->batch * N, (128u << 20) / ring_bytes));
+    if ((e = pl->alloc(&pl->d_G, ring_bytes * pl->large_chunk)) != hipSuccess) return hip_fail(e);
+    if ((e = pl->alloc((void**)&pl->d_qrange, sizeof(int) * qrange.size())) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpy(pl->d_qrange, qrange.data(), sizeof(int) * qrange.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
   return SU2_OK;
 }
@@ -299,7 +326,9 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
   hipError_t e = hipSuccess;
   switch (stage) {
     case SU2_STAGE_RING_FORWARD:
-      if (pl->fast)
+      if (pl->large)
+        e = launch_ring_forward_large<T>(large_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      else if (pl->fast)
         e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
       else
         e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
@@ -314,7 +343,10 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
-      if (pl->fast)
+      if (pl->large)
+        e = launch_ring_inverse_large<T>(large_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
+                                         (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+      else if (pl->fast)
         e = launch_ring_inverse_fast<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
                                         (cpx<T>*)out, s);
       else

@@ -95,6 +95,18 @@ struct FastRingParams {
   const long long* soff;  // per signal sample offsets, or null
 };
 
+// Parameters of the two-pass ring kernels (N = 256): the register-resident
+// kernels' parameters plus the pair range of every block of gamma frequencies
+// and the intermediate buffer of a chunk of rings.
+template <class T>
+struct LargeRingParams {
+  FastRingParams<T> f;
+  const int* qrange;  // [2 * block]: begin, end of the retained pairs of q in [32 block, 32 block + 32)
+  cpx<T>* G;          // chunk * N * N complex values
+  int chunk;          // rings per chunk
+  int ring0;          // first ring (signal * N + node) of the chunk being processed
+};
+
 // Parameters of the beta contraction kernels.
 template <class T>
 struct BetaParams {
@@ -158,6 +170,14 @@ template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
 template <class T>
 hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s);
+
+bool large_ring_supported(int N);
+int large_ring_block();           // gamma frequencies per block (pair ranges are given per block)
+int large_ring_slice_capacity();  // pairs of one block the kernels can stage in LDS
+template <class T>
+hipError_t launch_ring_forward_large(const LargeRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
+template <class T>
+hipError_t launch_ring_inverse_large(const LargeRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s);
 
 // d-table generation: FP64 three-term recurrence in l, one thread per (pair, k).
 hipError_t launch_dtable(int B, int N, int npairs, const PairInfo* pairs, const double* beta, double* tab64,

@@ -29,6 +29,7 @@
 
 #include "su2fft_ring.hip"
 #include "su2fft_ring_fast.hip"
+#include "su2fft_ring_large.hip"
 #include "su2fft_beta.hip"
 #include "su2fft_beta_bf16.hip"
 #include "su2fft_plan.h"
@@ -621,6 +622,7 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
     gp->B = kv.first;
     gp->batch = (int)kv.second.size();
     gp->dtype = dtype;
+    gp->allow_large = false;  // the work lists run the generic kernels for N = 256
     std::vector<long long> so, co;
     for (int s : kv.second) { so.push_back(soff[s]); co.push_back(coff[s]); }
     long long *dso = nullptr, *dco = nullptr;

@@ -34,6 +34,12 @@ struct su2_plan_s {
   int* d_bins = nullptr;
   bool fast = false;
   int rbeg[FAST_ROUNDS] = {0}, rend[FAST_ROUNDS] = {0};
+  // two-pass ring kernels (N = 256): pair ranges per q block, intermediate
+  bool large = false;
+  bool allow_large = true;  // mixed-plan groups use the generic kernels instead
+  int* d_qrange = nullptr;
+  void* d_G = nullptr;
+  int large_chunk = 0;
   void* d_rho = nullptr;
   void* d_tw = nullptr;
   void* d_W = nullptr;
@@ -99,6 +105,17 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   r.adjoint = adjoint;
   for (int i = 0; i < FAST_ROUNDS; i++) { r.rbeg[i] = pl->rbeg[i]; r.rend[i] = pl->rend[i]; }
   r.soff = pl->d_soff;
+  return r;
+}
+
+template <class T>
+LargeRingParams<T> large_params(const su2_plan_s* pl, int adjoint) {
+  LargeRingParams<T> r;
+  memset(&r, 0, sizeof(r));
+  r.f = fast_params<T>(pl, adjoint);
+  r.qrange = pl->d_qrange;
+  r.G = (cpx<T>*)pl->d_G;
+  r.chunk = pl->large_chunk;
   return r;
 }
 

@@ -173,7 +173,9 @@ def test_full_size_b64_batch32_sampled(dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_max_bandlimit_b128_sampled(dtype):
-    """B = 128 (largest supported; 256^3 grid, rings split into gamma classes)."""
+    """B = 128 (largest supported; 256^3 grid, two-pass ring transforms over
+    several chunks of rings): round trip, sampled forward of non-bandlimited
+    samples, sampled inverse and adjoint points, all against the oracle."""
     B, batch = 128, 2
     rng = np.random.default_rng(128)
     plan = su2.Plan(B, batch, dtype)
@@ -183,9 +185,18 @@ def test_max_bandlimit_b128_sampled(dtype):
     tol_rt = 1e-11 if dtype == "c128" else 1e-4
     _check(back, c, tol_rt, f"round trip B=128 {dtype}")
     xs = _host(x)
+    del x
     N = 2 * B
     pts = rng.choice(N ** 3, 24, replace=False)
     _check(xs[1].reshape(-1)[pts], oracle.inverse(B, c[1], pts), TOL[dtype], f"inverse B=128 {dtype}")
+    del xs
+    xa = _host(plan.adjoint(_dev(c)))
+    _check(xa[0].reshape(-1)[pts], oracle.adjoint(B, c[0], pts), TOL[dtype], f"adjoint B=128 {dtype}")
+    del xa
+    xu = synth.samples_uniform(B, batch, seed=12, dtype=NPDT[dtype])
+    fu = _host(plan.forward(_dev(xu)))
+    sel = rng.choice(oracle.num_coeffs(B), 12, replace=False)
+    _check(fu[1][sel], oracle.forward(B, xu[1], sel), TOL[dtype], f"forward B=128 {dtype}")
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
