@@ -74,10 +74,15 @@ def useful_flops(stage: str, B: int, batch: int) -> float:
     return 4.0 * N * C * batch if stage.startswith("beta") else 0.0
 
 
+# sources of the kernels the B = 64 chain launches (the counter summaries in
+# profiles/ are valid only for the digest they were taken at)
+MEASURED_SOURCES = ["su2fft_internal.h", "su2fft_ring_fast.hip", "su2fft_beta.hip", "su2fft_beta_bf16.hip"]
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2605_23923_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
+    for fn in MEASURED_SOURCES:
         with open(os.path.join(csrc, fn), "rb") as fh:
             h.update(fn.encode() + fh.read())
     return h.hexdigest()[:16]
