@@ -33,14 +33,24 @@ HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
+# a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf":
+# Wigner-d values generated inside the contraction kernels instead of stored
+
+
+def base_mode(mode: str) -> str:
+    return mode[:-4] if mode.endswith("_otf") else mode
+
+
 def kernel_name(stage: str, mode: str) -> str:
     """Name of the kernel that runs `stage` at B=64, as rocprofv3 lists it (template type kept)."""
-    t = "double" if mode == "c128" else "float"
+    t = "double" if base_mode(mode) == "c128" else "float"
     if stage.startswith("ring"):
         return f"ring_{'forward' if stage == 'ring_forward' else 'inverse'}_fast<{t}>"
     kind = "forward" if stage == "beta_forward" else "inverse"
     if mode == "c64_bf16x3":
         return f"beta_{kind}_bf16x3_kernel"
+    if mode.endswith("_otf"):
+        return f"beta_{kind}_otf_kernel<{t}>"
     return f"beta_{kind}_kernel<{t}>"
 
 
@@ -49,7 +59,12 @@ def retained_pairs(B: int) -> int:
 
 
 def table_bytes(B: int, mode: str) -> int:
+    """Table bytes a contraction launch reads: the stored table, or the
+    scalars of the generated one (3 recurrence coefficients per degree, a
+    seed constant per pair, 3 values per node, all FP64)."""
     C = B * (B + 1) * (2 * B + 1) // 6
+    if mode.endswith("_otf"):
+        return 8 * (3 * C + retained_pairs(B) + 3 * 2 * B)
     es = {"c128": 8, "c64": 4, "c64_bf16x3": 4}[mode]
     return C * 2 * B * es
 
@@ -57,7 +72,7 @@ def table_bytes(B: int, mode: str) -> int:
 def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     """Compulsory HBM bytes of one launch: inputs read once, outputs written once."""
     N = 2 * B
-    cb = 16 if mode == "c128" else 8
+    cb = 16 if base_mode(mode) == "c128" else 8
     C = B * (B + 1) * (2 * B + 1) // 6
     ring = N ** 3 * cb                       # one signal's samples
     spec = retained_pairs(B) * N * cb        # one signal's retained ring spectra
@@ -108,8 +123,8 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
     import paper_2605_23923_amd as su2
     import synth
 
-    plan = su2.Plan(B, batch, mode)
-    np_dt = "complex128" if mode == "c128" else "complex64"
+    plan = su2.Plan(B, batch, base_mode(mode), tables="on_the_fly" if mode.endswith("_otf") else "stored")
+    np_dt = "complex128" if base_mode(mode) == "c128" else "complex64"
     c_host = synth.coeffs(B, batch, seed=2, spectrum="decay").astype(np_dt)
     coeffs = torch.from_numpy(c_host).to("cuda")
     samples = plan.inverse(coeffs)                       # input synthesis, not timed
@@ -151,7 +166,7 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_hbm_frac": {k: round(algorithmic_bytes(k, B, batch, mode) / (v * 1e-3) / HBM_PEAK, 4)
                            for k, v in stage_ms.items()},
-        "beta_mfma_useful_frac": {k: round(useful_flops(k, B, batch) / (stage_ms[k] * 1e-3) / MFMA_PEAK[mode], 5)
+        "beta_mfma_useful_frac": {k: round(useful_flops(k, B, batch) / (stage_ms[k] * 1e-3) / MFMA_PEAK[base_mode(mode)], 5)
                                   for k in STAGES if k.startswith("beta")},
     }
     plan.close()
@@ -216,6 +231,8 @@ def secondary_configs(steps: int, warmup: int):
     c = torch.from_numpy(synth.coeffs(B, batch, seed=4, dtype=np.complex64)).to("cuda")
     out["b128_batch16_c64_bf16x3"] = run_whole(lambda: su2.Plan(B, batch, "c64_bf16x3"), x, c, max(2, steps // 5),
                                                1, batch)
+    out["b128_batch16_c64_tables_on_the_fly"] = run_whole(lambda: su2.Plan(B, batch, "c64", tables="on_the_fly"),
+                                                         x, c, max(2, steps // 5), 1, batch)
     del x, c
     torch.cuda.empty_cache()
     return out
@@ -275,8 +292,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="c64", choices=["c128", "c64", "c64_bf16x3"],
                     help="precision mode of the headline number")
-    ap.add_argument("--other-modes", default="c128",
-                    help="comma-separated modes also timed and reported under 'modes' ('' for none)")
+    ap.add_argument("--other-modes", default="c128,c64_otf",
+                    help="comma-separated modes also timed and reported under 'modes' ('' for none); "
+                         "'_otf' = Wigner-d values generated inside the contraction kernels")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
@@ -330,7 +348,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE_NAME[args.mode], "data": "synthetic",
+        "dtype": DTYPE_NAME[base_mode(args.mode)], "data": "synthetic",
         "config": {"workload": "SU(2) transform chain (forward + inverse + adjoint), B=64 (2l<64), "
                                "128^3 Euler grid, batch 32, bandlimited Gaussian coefficients var (2l+1)^-2",
                    "B": B, "batch": batch, "grid": "128x128x128", "mode": args.mode,

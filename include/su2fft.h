@@ -80,6 +80,22 @@ typedef struct su2_plan_s* su2_plan_t;
  * *out receives the plan (NULL on error). */
 su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_plan_t* out);
 
+/* Plan options (bit flags) for su2_plan_create_ex. */
+enum {
+  /* Generate the Wigner-d values inside the beta-contraction kernels instead of
+   * storing the table: the FP64 three-term recurrence in l (Section 4; Lemma 4.3
+   * is its m = n = 0 case) runs per (pair, node) from its single-term seed in
+   * every call, and only per-pair and per-node scalars are kept (about 3 C(B)
+   * doubles instead of C(B) * 2B table values: 724 MB of FP32 at B = 128).
+   * Same results as the stored table up to rounding.  SU2_C128 and SU2_C64
+   * only (SU2_ERR_UNSUPPORTED for SU2_C64_BF16X3). */
+  SU2_PLAN_TABLES_ON_THE_FLY = 1u
+};
+
+/* su2_plan_create with options: `flags` is a bitwise or of SU2_PLAN_* values
+ * (0 gives su2_plan_create's plan).  Unknown bits: SU2_ERR_INVALID_VALUE. */
+su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uint32_t flags, su2_plan_t* out);
+
 /* Plan for a batch of signals with individual bandlimits B_per_signal[0..batch-1]
  * (each 1..128, N = 2B of the form 2^a 3^b).  Signals are concatenated in order
  * in the sample and coefficient buffers: signal s starts at the prefix sum of
@@ -162,7 +178,8 @@ su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t*
  * for the pair (m, n) (doubled indices): host_out[k * L + i] = d^{l0+i}_{nm}(beta_k),
  * l0 = max(|m|, |n|), k = 0..2B-1, with *L = number of degrees l (may be NULL
  * to query L only when host_out is NULL).  SU2_ERR_INVALID_VALUE if the pair is
- * not retained (|2m|, |2n| > B-1 or 2m, 2n of different parity).  Synchronous. */
+ * not retained (|2m|, |2n| > B-1 or 2m, 2n of different parity);
+ * SU2_ERR_UNSUPPORTED for a plan without a stored table.  Synchronous. */
 su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L);
 
 const char* su2_status_string(su2_status_t status);

@@ -60,6 +60,8 @@ def _load():
     dp = ctypes.POINTER(ctypes.c_double)
     lib.su2_plan_create.argtypes = [i32, i32, i32, ctypes.POINTER(vp)]
     lib.su2_plan_create.restype = i32
+    lib.su2_plan_create_ex.argtypes = [i32, i32, i32, ctypes.c_uint32, ctypes.POINTER(vp)]
+    lib.su2_plan_create_ex.restype = i32
     lib.su2_plan_create_mixed.argtypes = [ctypes.POINTER(i32), i32, i32, ctypes.POINTER(vp)]
     lib.su2_plan_create_mixed.restype = i32
     lib.su2_plan_destroy.argtypes = [vp]
@@ -208,10 +210,21 @@ class _PlanBase:
             pass
 
 
-class Plan(_PlanBase):
-    """Transform plan for `batch` signals of bandlimit B (2l < B)."""
+PLAN_TABLES_ON_THE_FLY = 1  # SU2_PLAN_TABLES_ON_THE_FLY
 
-    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None):
+
+class Plan(_PlanBase):
+    """Transform plan for `batch` signals of bandlimit B (2l < B).
+
+    tables: "stored" keeps the Wigner-d table in device memory (generated once
+    at plan creation); "on_the_fly" generates the values inside the
+    contraction kernels on every call (c128 and c64 only)."""
+
+    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored"):
+        if tables not in ("stored", "on_the_fly"):
+            raise ValueError(f"tables must be 'stored' or 'on_the_fly', got {tables!r}")
+        flags = PLAN_TABLES_ON_THE_FLY if tables == "on_the_fly" else 0
+        self.tables = tables
         lib = _load()
         self.B, self.batch = int(B), int(batch)
         self.dtype = _DTYPES[dtype]
@@ -222,7 +235,8 @@ class Plan(_PlanBase):
         self.ncoef = num_coeffs(self.B) if self.B >= 1 else 0
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.su2_plan_create(self.B, self.batch, self.dtype, ctypes.byref(h)), "su2_plan_create")
+            _check(lib.su2_plan_create_ex(self.B, self.batch, self.dtype, flags, ctypes.byref(h)),
+                   "su2_plan_create_ex")
         self._handle = h
         self.sample_shape = (self.batch, self.N, self.N, self.N)
         self.coeff_shape = (self.batch, self.ncoef)

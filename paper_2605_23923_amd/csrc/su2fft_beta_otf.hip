@@ -1,0 +1,457 @@
+// Beta contraction with the Wigner-d values generated inside the kernels
+// (no stored table): the same products as the table kernels of
+// su2fft_beta.hip, with d^l_{nm}(beta_k) produced by the FP64 three-term
+// recurrence in l (Section 4: Lemma 4.3 is its m = n = 0 case, extended at the
+// end of the section to general (m, n)) from its single-term seed, and
+// rounded to the contraction's type where it is consumed.  Only per-pair and
+// per-node scalars are read (OtfParams), so the table bytes of a launch
+// (C(B) N values) drop to about 3 C(B) + P doubles.
+//
+// Forward: a workgroup generates the table rows of its 16 pairs for GK nodes
+// at a time into LDS (one recurrence chain per (pair, node) and thread), then
+// runs the KC-node chunks of S through the matrix cores as the table kernel
+// does.  Inverse: every lane generates the A operands it needs for its node
+// (one chain per pair and lane, keeping the degrees l = lk mod 4 it feeds to
+// the matrix cores), so no LDS is needed for the table.
+#include "su2fft_internal.h"
+
+namespace su2 {
+
+// x^n for an integer n >= 0 by repeated squaring (n <= 128 here)
+__device__ __forceinline__ double powi_d(double x, int n) {
+  double r = 1.0;
+  while (n) {
+    if (n & 1) r *= x;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
+// seed d^{l0}_{nm}(beta_k) of a pair (a = n, b = m, doubled indices)
+template <class T>
+__device__ __forceinline__ double otf_seed(const OtfParams<T>& p, const PairInfo& q, int pidx, int k) {
+  int top, pc, ps, neg;
+  wigner_seed_form(q.tl0, q.tn, q.tm, &top, &pc, &ps, &neg);
+  return p.seedc[pidx] * powi_d(p.ck[k], pc) * powi_d(p.sk[k], ps);
+}
+
+template <class T, int RTMAX>
+struct OtfFwd {
+  static constexpr int BT = BetaCfg<T>::BT;
+  static constexpr int KC = 8;                 // nodes per S chunk
+  static constexpr int PB = 2 * PT + 2;
+  static constexpr int PK = BT * PB + 16;
+  static constexpr int TMAX = PT * 16 * RTMAX;  // longest tile row (sum of L)
+  static constexpr int GK0 = (65536 / (int)sizeof(T)) / TMAX;
+  static constexpr int GK = GK0 >= 32 ? 32 : GK0;   // nodes generated at a time (64 KB of rows)
+  static_assert(GK % KC == 0 && PT * GK <= FWD_THREADS, "generation geometry");
+  // S chunk, GK table rows, then the tile's recurrence coefficients (3 doubles per row element)
+  static constexpr size_t SMEM_C = (size_t)KC * PK * sizeof(T) + (size_t)GK * TMAX * sizeof(T);
+  static constexpr size_t SMEM = SMEM_C + (size_t)TMAX * 3 * sizeof(double);
+};
+
+// the tile's recurrence coefficients (rows row0 .. row0 + lsum - 1) into LDS
+__device__ __forceinline__ void otf_load_coeffs(double* sC, const double* rcoef, long long row0, int lsum, int tid,
+                                                int nthreads) {
+  for (int j = tid; j < 3 * lsum; j += nthreads) sC[j] = rcoef[3 * row0 + j];
+}
+
+template <class T, int RTMAX>
+__device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
+                                                      const OtfParams<T>& op, int tile, int bt, unsigned char* smem,
+                                                      int tid) {
+  typedef OtfFwd<T, RTMAX> G;
+  typedef typename acc4<T>::type accT;
+  const BetaParams<T>& p = op.b;
+  constexpr int BT = G::BT, CT = 2 * BT / 16, KC = G::KC, PB = G::PB, PK = G::PK, GK = G::GK;
+  constexpr int VC = 16 / (int)sizeof(cpx<T>);
+  constexpr int SV = KC * BT * PT / VC;
+  constexpr int SPT = SV / FWD_THREADS;
+  static_assert(SV % FWD_THREADS == 0, "chunk split");
+  T* sS = reinterpret_cast<T*>(smem);
+  T* sT = sS + KC * PK;  // GK node rows of lsum values
+  double* sC = reinterpret_cast<double*>(smem + G::SMEM_C);
+
+  const int b0 = bt * BT;
+  const int nb = min(BT, p.batch - b0);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const int N = p.N;
+  const PairInfo p0 = p.pairs[tile * PT];
+  const int lsum = p0.lsum;
+  const long long row0 = p0.tab / N;  // first recurrence-coefficient row of the tile
+
+  PairInfo pi[2];
+#pragma unroll
+  for (int i = 0; i < 2; i++) pi[i] = p.pairs[tile * PT + wave + 8 * i];
+
+  accT acc[2][RTMAX][CT];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int rt = 0; rt < RTMAX; rt++)
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[i][rt][ct][r] = T(0);
+
+  // table rows of nodes g0 .. g0 + GK - 1: thread (pair gi, node gk) runs one chain
+  auto generate = [&](int g0) {
+    const int gi = tid / GK, gk = tid - gi * GK;
+    const int k = g0 + gk;
+    if (gi < PT && k < N) {
+      const PairInfo q = p.pairs[tile * PT + gi];
+      if (q.L > 0) {
+        T* out = sT + gk * lsum + q.coff;
+        double d = otf_seed(op, q, tile * PT + gi, k), dm1 = 0.0;
+        const double x = op.xk[k];
+        const double* rc = sC + 3 * q.coff;
+        out[0] = (T)d;
+        for (int i = 1; i < q.L; i++) {
+          const double dn = (rc[3 * i] * x - rc[3 * i + 1]) * d - rc[3 * i + 2] * dm1;
+          dm1 = d;
+          d = dn;
+          out[i] = (T)d;
+        }
+      }
+    }
+  };
+
+  typedef T vec16 __attribute__((ext_vector_type(16 / sizeof(T))));
+  vec16 sreg[SPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+      const int v = tid + FWD_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+      const int k = k0 + kk;
+      if (k < N && bb < nb)
+        sreg[i] = *reinterpret_cast<const vec16*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
+      else
+        sreg[i] = vec16(T(0));
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int i = 0; i < SPT; i++) {
+      const int v = tid + FWD_THREADS * i;
+      const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
+      const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
+#pragma unroll
+      for (int q = 0; q < 2 * VC; q++) sS[kk * PK + bb * PB + 2 * pv * VC + q] = sreg[i][q];
+    }
+  };
+
+  const int nchunk = (N + KC - 1) / KC;
+  otf_load_coeffs(sC, op.rcoef, row0, lsum, tid, FWD_THREADS);
+  fetch(0);
+  commit();
+  int g0 = 0;
+  for (int c = 0; c < nchunk; c++) {
+    __syncthreads();
+    if (c + 1 < nchunk) fetch((c + 1) * KC);
+    if ((c * KC) % GK == 0) {  // the next GK nodes' table rows
+      g0 = c * KC;
+      generate(g0);
+      __syncthreads();
+    }
+    const int toff = (c * KC - g0) * lsum;
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      const int L = pi[i].L;
+      if (L == 0) continue;
+      const int pp = wave + 8 * i;
+      const int coff = pi[i].coff;
+#pragma unroll
+      for (int ks = 0; ks < KC; ks += 4) {
+        const int kk = ks + lk;
+        const bool kin = c * KC + kk < N;
+        T bop[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++) {
+          const int cc = ct * 16 + lrow;
+          bop[ct] = sS[kk * PK + (cc >> 1) * PB + 2 * pp + (cc & 1)];
+        }
+#pragma unroll
+        for (int rt = 0; rt < RTMAX; rt++) {
+          if (rt * 16 < L) {
+            const int l = rt * 16 + lrow;
+            const T a = (l < L && kin) ? sT[toff + kk * lsum + coff + l] : T(0);
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = mfma16x16x4(a, bop[ct], acc[i][rt][ct]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nchunk) commit();
+  }
+
+  T* out = reinterpret_cast<T*>(coeffs);
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int L = pi[i].L;
+    if (L == 0) continue;
+#pragma unroll
+    for (int rt = 0; rt < RTMAX; rt++) {
+      if (rt * 16 >= L) continue;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+        if (bb >= nb) continue;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int l = rt * 16 + acc_row<T>(lane, r);
+          if (l < L) {
+            const long long idx = coeff_index(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
+            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class T, int RTMAX>
+__global__ __launch_bounds__(FWD_THREADS) void beta_forward_otf_kernel(const cpx<T>* __restrict__ S,
+                                                                       cpx<T>* __restrict__ coeffs, OtfParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_forward_otf_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+}
+
+// Inverse: as beta_inverse_body, with the A operands (node k = k0 + lrow,
+// degree l = 4 s + lk) generated per lane.
+template <class T, int LQ, bool GEN_LDS>
+__device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
+                                                      const OtfParams<T>& op, int tile, int bt, unsigned char* smem,
+                                                      int tid) {
+  typedef typename acc4<T>::type accT;
+  const BetaParams<T>& p = op.b;
+  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int PB = InvStage<T>::PB, NRS = InvStage<T>::NRS;
+  T* stage = reinterpret_cast<T*>(smem);
+  double* sC = reinterpret_cast<double*>(smem + inverse_smem<T>());  // the tile's recurrence coefficients
+  T* sT = reinterpret_cast<T*>(sC + (size_t)PT * 4 * LQ * 3);          // GEN_LDS: 16 node rows of lsum values
+  const int b0 = bt * BT;
+  const int nb = min(BT, p.batch - b0);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const int N = p.N;
+  const T* cin = reinterpret_cast<const T*>(coeffs);
+  const PairInfo p0 = p.pairs[tile * PT];
+  const long long row0 = p0.tab / N;
+  otf_load_coeffs(sC, op.rcoef, row0, p0.lsum, tid, INV_THREADS);
+
+  PairInfo pi[2];
+  T bop[2][LQ][CT];
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    pi[q] = p.pairs[tile * PT + wave + 8 * q];
+#pragma unroll
+    for (int s = 0; s < LQ; s++) {
+      const int l = 4 * s + lk;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+        T v = T(0);
+        if (l < pi[q].L && bb < nb) {
+          const int tl = pi[q].tl0 + 2 * l;
+          const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
+          const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
+          v = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim];
+        }
+        bop[q][s][ct] = v;
+      }
+    }
+  }
+
+  __syncthreads();
+  for (int k0 = 0; k0 < N; k0 += 16) {
+    const int k = k0 + lrow;
+    const int kc = k < N ? k : N - 1;  // lanes past the last node compute a valid chain and are zeroed
+    T av[2][LQ];
+    if constexpr (GEN_LDS) {
+      // one chain per (pair, node) of the block: threads tid < 16 * PT, then
+      // every lane reads its operands (node kc, degrees l = 4 s + lk)
+      const int lsum = p0.lsum;
+      if (tid < 16 * PT) {
+        const int gi = tid / 16, gk = tid - gi * 16;
+        const int kg = k0 + gk < N ? k0 + gk : N - 1;
+        const PairInfo q = p.pairs[tile * PT + gi];
+        if (q.L > 0) {
+          T* out = sT + gk * lsum + q.coff;
+          double dd = otf_seed(op, q, tile * PT + gi, kg), ddm1 = 0.0;
+          const double xg = op.xk[kg];
+          const double* rc = sC + 3 * q.coff;
+          out[0] = (T)dd;
+          for (int i = 1; i < q.L; i++) {
+            const double dn = (rc[3 * i] * xg - rc[3 * i + 1]) * dd - rc[3 * i + 2] * ddm1;
+            ddm1 = dd;
+            dd = dn;
+            out[i] = (T)dd;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int s = 0; s < LQ; s++) {
+          const int l = 4 * s + lk;
+          av[q][s] = (l < pi[q].L && k < N) ? sT[lrow * lsum + pi[q].coff + l] : T(0);
+        }
+    } else {
+      // this lane's chains for both pairs, advanced together (independent FP64
+      // chains interleave): degrees l0 .. l0 + L - 1 at node kc; keep l = 4 s + lk
+      double d[2], dm1[2];
+      const double x = op.xk[kc];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        d[q] = pi[q].L > 0 ? otf_seed(op, pi[q], tile * PT + wave + 8 * q, kc) : 0.0;
+        dm1[q] = 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+#pragma unroll
+        for (int q = 0; q < 2; q++) av[q][s] = T(0);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int l = 4 * s + j;
+#pragma unroll
+          for (int q = 0; q < 2; q++) {
+            if (l < pi[q].L) {
+              if (l > 0) {
+                const double* rc = sC + 3 * (pi[q].coff + l);
+                const double dn = (rc[0] * x - rc[1]) * d[q] - rc[2] * dm1[q];
+                dm1[q] = d[q];
+                d[q] = dn;
+              }
+              if (j == lk) av[q][s] = (T)d[q];
+            }
+          }
+        }
+        if (k >= N) {
+#pragma unroll
+          for (int q = 0; q < 2; q++) av[q][s] = T(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int L = pi[q].L;
+      const int pp = wave + 8 * q;
+      accT acc[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[ct][r] = T(0);
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+        if (4 * s < L) {
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++) acc[ct] = mfma16x16x4(av[q][s], bop[q][s][ct], acc[ct]);
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int cc = ct * 16 + lrow;
+        const int bb = cc >> 1, reim = cc & 1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) stage[acc_row<T>(lane, r) * NRS + bb * PB + 2 * pp + reim] = acc[ct][r];
+      }
+    }
+    __syncthreads();
+    constexpr int VC = 16 / (int)sizeof(cpx<T>);
+    for (int v = tid; v < 16 * BT * (PT / VC); v += INV_THREADS) {
+      const int row = v / (PT / VC), pv = v - row * (PT / VC);
+      const int kk = row / BT, bb = row - kk * BT;
+      const int kn = k0 + kk;
+      if (kn < N && bb < nb) {
+        const T* src = stage + kk * NRS + bb * PB + 2 * pv * VC;
+        float4 w;
+        T* wd = reinterpret_cast<T*>(&w);
+#pragma unroll
+        for (int e = 0; e < 2 * VC; e++) wd[e] = src[e];
+        *reinterpret_cast<float4*>(S + (((size_t)tile * N + kn) * p.batch + b0 + bb) * PT + pv * VC) = w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int LQ, bool GEN_LDS>
+__global__ __launch_bounds__(INV_THREADS) void beta_inverse_otf_kernel(const cpx<T>* __restrict__ coeffs,
+                                                                       cpx<T>* __restrict__ S, OtfParams<T> p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  beta_inverse_otf_body<T, LQ, GEN_LDS>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+}
+
+// LDS of the inverse: staging, recurrence coefficients and (GEN_LDS) the
+// generated rows of one block of 16 nodes
+template <class T, int LQ, bool GEN_LDS>
+constexpr size_t inverse_otf_smem() {
+  return inverse_smem<T>() + (size_t)PT * 4 * LQ * 3 * sizeof(double) +
+         (GEN_LDS ? (size_t)16 * PT * 4 * LQ * sizeof(T) : 0);
+}
+// generated rows in LDS where they fit next to the staging buffer (all but
+// FP64 at B = 128, which generates per lane)
+template <class T, int LQ>
+constexpr bool inverse_gen_lds() { return inverse_otf_smem<T, LQ, true>() <= 160 * 1024; }
+
+template <class T>
+hipError_t launch_beta_forward_otf(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
+  constexpr int BT = BetaCfg<T>::BT;
+  const dim3 grid(p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  const int rt = beta_rtmax(p.b.B);
+  hipError_t e;
+#define SU2_OTF_FWD(R)                                                                                    \
+  if (rt == R) {                                                                                          \
+    if ((e = set_smem(beta_forward_otf_kernel<T, R>, OtfFwd<T, R>::SMEM)) != hipSuccess) return e;         \
+    hipLaunchKernelGGL((beta_forward_otf_kernel<T, R>), grid, dim3(FWD_THREADS), (OtfFwd<T, R>::SMEM), s, S, \
+                       coeffs, p);                                                                        \
+    return hipGetLastError();                                                                             \
+  }
+  SU2_OTF_FWD(1)
+  SU2_OTF_FWD(2)
+  SU2_OTF_FWD(4)
+#undef SU2_OTF_FWD
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+hipError_t launch_beta_inverse_otf(const OtfParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
+  constexpr int BT = BetaCfg<T>::BT;
+  const dim3 grid(p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  const int lq = beta_lq(p.b.B);
+  hipError_t e;
+#define SU2_OTF_INV(Q)                                                                                    \
+  if (lq == Q) {                                                                                          \
+    constexpr bool GL = inverse_gen_lds<T, Q>();                                                          \
+    constexpr size_t smem = inverse_otf_smem<T, Q, GL>();                                                 \
+    if ((e = set_smem(beta_inverse_otf_kernel<T, Q, GL>, smem)) != hipSuccess) return e;                  \
+    hipLaunchKernelGGL((beta_inverse_otf_kernel<T, Q, GL>), grid, dim3(INV_THREADS), smem, s, coeffs, S,  \
+                       p);                                                                                \
+    return hipGetLastError();                                                                             \
+  }
+  SU2_OTF_INV(2)
+  SU2_OTF_INV(4)
+  SU2_OTF_INV(8)
+  SU2_OTF_INV(16)
+#undef SU2_OTF_INV
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_beta_forward_otf<float>(const OtfParams<float>&, const cpx<float>*, cpx<float>*,
+                                                   hipStream_t);
+template hipError_t launch_beta_forward_otf<double>(const OtfParams<double>&, const cpx<double>*, cpx<double>*,
+                                                    hipStream_t);
+template hipError_t launch_beta_inverse_otf<float>(const OtfParams<float>&, const cpx<float>*, cpx<float>*,
+                                                   hipStream_t);
+template hipError_t launch_beta_inverse_otf<double>(const OtfParams<double>&, const cpx<double>*, cpx<double>*,
+                                                    hipStream_t);
+
+}  // namespace su2

@@ -133,6 +133,53 @@ hipError_t upload_typed(su2_plan_s* pl, const std::vector<long double>& W, const
 
 namespace su2 {
 
+// Scalars of the on-the-fly tables: per pair the seed constant
+// (-1)^neg sqrt(C(2 l0, top)), per (pair, degree index i >= 1) the three
+// coefficients of the step that produces degree l0 + i from l0 + i - 1 and
+// l0 + i - 2 (tile-major rows, like the table), and per node cos beta,
+// cos beta/2, sin beta/2.  Computed in long double, stored as double.
+hipError_t upload_otf_scalars(su2_plan_s* pl, const std::vector<long double>& beta) {
+  const int N = pl->N;
+  const std::vector<PairInfo>& pairs = pl->h_pairs;
+  std::vector<double> seedc(pl->P_pad, 0.0), rc((size_t)3 * (pl->tab_elems / N + 1), 0.0), nodes(3 * (size_t)N);
+  for (int p = 0; p < pl->P_pad; p++) {
+    const PairInfo& q = pairs[p];
+    if (q.L == 0) continue;
+    int top, pc, ps, neg;
+    wigner_seed_form(q.tl0, q.tn, q.tm, &top, &pc, &ps, &neg);
+    long double lb = lgammal(q.tl0 + 1.0L) - lgammal(top + 1.0L) - lgammal(q.tl0 - top + 1.0L);
+    seedc[p] = (double)((neg ? -1.0L : 1.0L) * expl(0.5L * lb));
+    const long long row = q.tab / N + q.coff;
+    const long double a = 0.5L * q.tn, b = 0.5L * q.tm;
+    for (int i = 1; i < q.L; i++) {
+      const long double l = 0.5L * (q.tl0 + 2 * (i - 1)), lp1 = l + 1.0L;  // step l -> l + 1
+      const long double pre = lp1 * (2.0L * l + 1.0L) / sqrtl((lp1 * lp1 - a * a) * (lp1 * lp1 - b * b));
+      long double c1 = 0.0L, c2 = 0.0L;
+      if (l != 0.0L) {
+        c1 = pre * a * b / (l * lp1);
+        c2 = pre * sqrtl((l * l - a * a) * (l * l - b * b)) / (l * (2.0L * l + 1.0L));
+      }
+      rc[3 * (row + i)] = (double)pre;
+      rc[3 * (row + i) + 1] = (double)c1;
+      rc[3 * (row + i) + 2] = (double)c2;
+    }
+  }
+  for (int k = 0; k < N; k++) {
+    nodes[k] = (double)cosl(beta[k]);
+    nodes[N + k] = (double)cosl(0.5L * beta[k]);
+    nodes[2 * N + k] = (double)sinl(0.5L * beta[k]);
+  }
+  hipError_t e;
+  if ((e = pl->alloc((void**)&pl->d_seedc, sizeof(double) * seedc.size())) != hipSuccess) return e;
+  if ((e = pl->alloc((void**)&pl->d_rcoef, sizeof(double) * rc.size())) != hipSuccess) return e;
+  if ((e = pl->alloc((void**)&pl->d_nodes, sizeof(double) * nodes.size())) != hipSuccess) return e;
+  if ((e = hipMemcpy(pl->d_seedc, seedc.data(), sizeof(double) * seedc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpy(pl->d_rcoef, rc.data(), sizeof(double) * rc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  return hipMemcpy(pl->d_nodes, nodes.data(), sizeof(double) * nodes.size(), hipMemcpyHostToDevice);
+}
+
 su2_status_t build_plan(su2_plan_s* pl) {
   const int B = pl->B, N = 2 * B;
   pl->N = N;
@@ -268,8 +315,6 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
-  // tables are padded by 64 bytes: the contraction kernels read whole 16-byte vectors
-  if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_pairs, pairs.data(), sizeof(PairInfo) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipMemcpy(pl->d_fftpos, fftpos.data(), sizeof(int) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
@@ -284,8 +329,16 @@ su2_status_t build_plan(su2_plan_s* pl) {
     e = upload_typed<float>(pl, W, twr, twi, rho_e);
   if (e != hipSuccess) return hip_fail(e);
 
-  if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
-  if (pl->dtype == SU2_C64) {
+  if (pl->otf) {
+    if ((e = upload_otf_scalars(pl, beta)) != hipSuccess) return hip_fail(e);
+  } else {
+    // tables are padded by 64 bytes: the contraction kernels read whole 16-byte vectors
+    if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
+  }
+  if (pl->otf) {
+    // no stored table
+  } else if (pl->dtype == SU2_C64) {
     if ((e = pl->alloc((void**)&pl->d_tab32, sizeof(float) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_round_table_f32(tab, pl->d_tab64, pl->d_tab32, 0)) != hipSuccess) return hip_fail(e);
   } else if (pl->dtype == SU2_C64_BF16X3) {
@@ -334,12 +387,19 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
         e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
       break;
     case SU2_STAGE_BETA_FORWARD:
-      e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+      if (pl->otf)
+        e = launch_beta_forward_otf<T>(otf_params<T>(pl, 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+      else
+        e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
       break;
     case SU2_STAGE_BETA_INVERSE:
     case SU2_STAGE_BETA_ADJOINT:
-      e = launch_beta_inverse<T>(beta_params<T>(pl, table_of<T>(pl), stage == SU2_STAGE_BETA_ADJOINT),
-                                 (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+      if (pl->otf)
+        e = launch_beta_inverse_otf<T>(otf_params<T>(pl, stage == SU2_STAGE_BETA_ADJOINT), (const cpx<T>*)in,
+                                       (cpx<T>*)pl->d_S, s);
+      else
+        e = launch_beta_inverse<T>(beta_params<T>(pl, table_of<T>(pl), stage == SU2_STAGE_BETA_ADJOINT),
+                                   (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
@@ -432,11 +492,17 @@ su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, dou
 }
 
 su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_plan_t* out) {
+  return su2_plan_create_ex(B, batch, dtype, 0u, out);
+}
+
+su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uint32_t flags, su2_plan_t* out) {
   if (!out) return SU2_ERR_INVALID_VALUE;
   *out = nullptr;
   if (B < 1 || batch < 1) return SU2_ERR_INVALID_VALUE;
   if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
+  if (flags & ~(uint32_t)SU2_PLAN_TABLES_ON_THE_FLY) return SU2_ERR_INVALID_VALUE;
   if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
+  if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) && dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
   su2_status_t st = check_device();
   if (st != SU2_OK) return st;
   su2_plan_s* pl = new (std::nothrow) su2_plan_s();
@@ -444,6 +510,7 @@ su2_status_t su2_plan_create(int32_t B, int32_t batch, su2_dtype_t dtype, su2_pl
   pl->B = B;
   pl->batch = batch;
   pl->dtype = dtype;
+  pl->otf = (flags & SU2_PLAN_TABLES_ON_THE_FLY) != 0;
   st = build_plan(pl);
   if (st != SU2_OK) {
     (void)hipDeviceSynchronize();
@@ -535,6 +602,7 @@ su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, v
 
 su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L) {
   if (!plan || plan->mixed || (!host_out && !L)) return SU2_ERR_INVALID_VALUE;
+  if (plan->otf && host_out) return SU2_ERR_UNSUPPORTED;
   for (int p = 0; p < plan->P; p++) {
     const PairInfo& pi = plan->h_pairs[p];
     if (pi.tm != two_m || pi.tn != two_n) continue;

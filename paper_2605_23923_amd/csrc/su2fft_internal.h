@@ -118,6 +118,39 @@ struct BetaParams {
   const long long* coff;    // per signal: offset of its coefficients (complex values), or null: b * ncoef
 };
 
+// Tables generated inside the contraction kernels ("on the fly"): the FP64
+// three-term recurrence in l runs per (pair, node) from its seed; only
+// per-pair and per-node scalars are stored.
+//   seed:  d^{l0}_{nm}(beta_k) = seedc[pair] cos^{pc}(beta_k / 2) sin^{ps}(beta_k / 2)
+//   step:  d^{l0+i} = (rc[0] x_k - rc[1]) d^{l0+i-1} - rc[2] d^{l0+i-2},  x_k = cos beta_k,
+//          rc = rcoef + 3 (tile_row0 + coff + i), tile_row0 = (tile table offset) / N
+template <class T>
+struct OtfParams {
+  BetaParams<T> b;
+  const double* seedc;  // per pair
+  const double* rcoef;  // 3 per (pair, degree index i >= 1), tile-major like the table rows
+  const double* xk;     // cos(beta_k)
+  const double* ck;     // cos(beta_k / 2)
+  const double* sk;     // sin(beta_k / 2)
+};
+
+// Exponents of the single surviving term of Wigner's sum at l0 = max(|a|, |b|)
+// (doubled indices t0, ta, tb): d^{l0}_{ab} = (-1)^neg sqrt(C(t0, top)) cos^pc sin^ps.
+__host__ __device__ inline void wigner_seed_form(int t0, int ta, int tb, int* top, int* pc, int* ps, int* neg) {
+  *neg = 0;
+  if (t0 == ta) {
+    *top = (t0 + tb) / 2; *pc = (t0 + tb) / 2; *ps = (t0 - tb) / 2;
+    *neg = ((t0 - tb) / 2) & 1;
+  } else if (t0 == -ta) {
+    *top = (t0 + tb) / 2; *pc = (t0 - tb) / 2; *ps = (t0 + tb) / 2;
+  } else if (t0 == tb) {
+    *top = (t0 + ta) / 2; *pc = (t0 + ta) / 2; *ps = (t0 - ta) / 2;
+  } else {  // t0 == -tb
+    *top = (t0 + ta) / 2; *pc = (t0 - ta) / 2; *ps = (t0 + ta) / 2;
+    *neg = ((t0 + ta) / 2) & 1;
+  }
+}
+
 __host__ __device__ inline size_t coef_offset(const long long* coff, int b, long long ncoef) {
   return coff ? (size_t)coff[b] : (size_t)b * ncoef;
 }
@@ -136,6 +169,10 @@ template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s);
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s);
+template <class T>
+hipError_t launch_beta_forward_otf(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s);
+template <class T>
+hipError_t launch_beta_inverse_otf(const OtfParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s);
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s);
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,

@@ -35,6 +35,12 @@ struct su2_plan_s {
   bool fast = false;
   int rbeg[FAST_ROUNDS] = {0}, rend[FAST_ROUNDS] = {0};
   // two-pass ring kernels (N = 256): pair ranges per q block, intermediate
+  // tables generated inside the contraction kernels: per-pair seed constants,
+  // recurrence coefficients, node values
+  bool otf = false;
+  double* d_seedc = nullptr;
+  double* d_rcoef = nullptr;
+  double* d_nodes = nullptr;  // [3][N]: cos(beta_k), cos(beta_k / 2), sin(beta_k / 2)
   bool large = false;
   bool allow_large = true;  // mixed-plan groups use the generic kernels instead
   int* d_qrange = nullptr;
@@ -116,6 +122,22 @@ LargeRingParams<T> large_params(const su2_plan_s* pl, int adjoint) {
   r.qrange = pl->d_qrange;
   r.G = (cpx<T>*)pl->d_G;
   r.chunk = pl->large_chunk;
+  return r;
+}
+
+template <class T>
+BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode);
+
+template <class T>
+OtfParams<T> otf_params(const su2_plan_s* pl, int scale_mode) {
+  OtfParams<T> r;
+  memset(&r, 0, sizeof(r));
+  r.b = beta_params<T>(pl, nullptr, scale_mode);
+  r.seedc = pl->d_seedc;
+  r.rcoef = pl->d_rcoef;
+  r.xk = pl->d_nodes;
+  r.ck = pl->d_nodes + pl->N;
+  r.sk = pl->d_nodes + 2 * pl->N;
   return r;
 }
 

@@ -42,20 +42,9 @@ __global__ void dtable_kernel(int B, int N, int npairs, const PairInfo* __restri
   const double bk = beta[k];
   const double ch = cos(0.5 * bk), sh = sin(0.5 * bk), x = cos(bk);
   // seed (all exponents are integers: t0 +- ta, t0 +- tb are even)
-  int pc, ps, top;
-  double sgn = 1.0;
-  if (t0 == ta) {
-    top = (t0 + tb) / 2; pc = (t0 + tb) / 2; ps = (t0 - tb) / 2;
-    if (((t0 - tb) / 2) & 1) sgn = -1.0;
-  } else if (t0 == -ta) {
-    top = (t0 + tb) / 2; pc = (t0 - tb) / 2; ps = (t0 + tb) / 2;
-  } else if (t0 == tb) {
-    top = (t0 + ta) / 2; pc = (t0 + ta) / 2; ps = (t0 - ta) / 2;
-  } else {  // t0 == -tb
-    top = (t0 + ta) / 2; pc = (t0 - ta) / 2; ps = (t0 + ta) / 2;
-    if (((t0 + ta) / 2) & 1) sgn = -1.0;
-  }
-  double dl = sgn * sqrt(binom_d(t0, top)) * pow(ch, (double)pc) * pow(sh, (double)ps);
+  int pc, ps, top, neg;
+  wigner_seed_form(t0, ta, tb, &top, &pc, &ps, &neg);
+  double dl = (neg ? -1.0 : 1.0) * sqrt(binom_d(t0, top)) * pow(ch, (double)pc) * pow(sh, (double)ps);
   double dlm1 = 0.0;
   double* out = tab + pi.tab + (long long)k * pi.lsum + pi.coff;
   out[0] = dl;

@@ -85,6 +85,13 @@ def test_argument_validation_before_any_device_call():
     assert lib.su2_plan_create_mixed(bs, 2, 1, ctypes.byref(h)) == 1
     assert lib.su2_grid(0, None, None, None, None) == 1
     assert lib.su2_status_string(2).startswith(b"SU2_ERR_UNSUPPORTED")
+    # plan options: unknown bits, and on-the-fly tables with the split-BF16 mode
+    lib.su2_plan_create_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.su2_plan_create_ex(8, 1, 1, 2, ctypes.byref(h)) == 1
+    assert lib.su2_plan_create_ex(8, 1, 1, 0x80000000, ctypes.byref(h)) == 1
+    assert lib.su2_plan_create_ex(8, 1, 2, 1, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(0, 1, 1, 1, ctypes.byref(h)) == 1
 
 
 def test_valid_plan_without_device_reports_no_device():
