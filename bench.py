@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+FP64_VALU_PEAK = 78.6e12     # flop/s, FP64 vector (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
@@ -204,6 +205,46 @@ def run_whole(make_plan, x, c, steps: int, warmup: int, batch: int):
     return info
 
 
+def shifted_forms(steps: int):
+    """The forward contraction at B=64 batch 32 (c64 plan) in its three forms:
+    the table contraction on the matrix cores, and the shifted-recurrence
+    (divide-and-conquer) form at depth 1 and depth 2 (coarse step 4), which
+    run on the FP64 vector ALUs.  Executed FP64 flops of the shifted forms:
+    16 per (coefficient, node, signal) (two recurrence chains and two complex
+    accumulations), priced against the FP64 vector peak."""
+    import numpy as np
+    import torch
+
+    import paper_2605_23923_amd as su2
+    import synth
+
+    B, batch = 64, 32
+    plan = su2.Plan(B, batch, "c64")
+    x = torch.from_numpy(synth.samples_uniform(B, batch, seed=1, dtype=np.complex64)).to("cuda")
+    out = torch.empty(plan.coeff_shape, dtype=plan.torch_dtype, device="cuda")
+    plan.run_stage("ring_forward", x, None)
+    res = {}
+    for name, fn in (("table_ms", lambda: plan.run_stage("beta_forward", None, out)),
+                     ("shifted_depth1_ms", lambda: plan.beta_forward_shifted(out, 1, 4)),
+                     ("shifted_depth2_block4_ms", lambda: plan.beta_forward_shifted(out, 2, 4))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(max(3, steps // 5)):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / max(3, steps // 5), 4)
+    C = B * (B + 1) * (2 * B + 1) // 6
+    flops = 16.0 * C * 2 * B * batch
+    ach = flops / (res["shifted_depth1_ms"] * 1e-3)
+    res["roofline_depth1"] = {"bound": "alu", "achieved": round(ach / 1e12, 3), "peak": FP64_VALU_PEAK / 1e12,
+                              "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_PEAK, 4)}
+    plan.close()
+    return res
+
+
 def secondary_configs(steps: int, warmup: int):
     """The other workload shapes, timed through the public calls."""
     import numpy as np
@@ -224,6 +265,7 @@ def secondary_configs(steps: int, warmup: int):
     out["mixed_320_signals_c64"]["signals"] = "256 x B=32 + 64 x B in {16,24,32,48,64} (seed 33)"
     del x, c
     torch.cuda.empty_cache()
+    out["b64_batch32_beta_forward_shifted_c64"] = shifted_forms(steps)
     # B = 128, batch 16, split-BF16 contraction
     B, batch = 128, 16
     N = 2 * B

@@ -174,6 +174,27 @@ su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu);
 su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype,
                            int64_t* device_bytes);
 
+/* The contraction stage of the forward transform in the divide-and-conquer
+ * form of Section 4 (the shifted three-term recurrence: the matrix-recurrence
+ * and composition-rule propositions, Theorem 4.7, and its worked example for
+ * depth 2), generalised from the Legendre case to the Wigner-d recurrence of
+ * every (m, n) pair, instead of against the stored table.  For a pair with
+ * degrees l0 .. l0+L-1 and base level Lb = l0 + 1 it forms the stored products
+ * s^{Lb} = S d^{l0+1}, s^{Lb-1} = S d^{l0} of the pair's ring spectrum S and
+ *   depth 1:  fhat(l0+1+r) = <s^{Lb}, A_r^{Lb}> + <s^{Lb-1}, B_r^{Lb}>,
+ *   depth 2:  r = n1 + n2 with n1 a multiple of `block` (2, 4 or 8; ignored at
+ *             depth 1) and the four terms <s^{Lb}, A_{n2}^{Lb+n1} A_{n1}^{Lb}> +
+ *             <s^{Lb}, B_{n2}^{Lb+n1} A_{n1-1}^{Lb}> + <s^{Lb-1}, A_{n2}^{Lb+n1} B_{n1}^{Lb}> +
+ *             <s^{Lb-1}, B_{n2}^{Lb+n1} B_{n1-1}^{Lb}>,
+ * with the shifted polynomials A, B generated per node in FP64.  Reads the
+ * ring spectra that su2_run_stage(SU2_STAGE_RING_FORWARD) left in the plan and
+ * writes d_coeffs exactly like su2_run_stage(SU2_STAGE_BETA_FORWARD) (same
+ * values up to rounding).  Arithmetic in FP64 for every dtype (the method's
+ * stored products leave the FP32 range near the poles).  Single-B plans with
+ * B <= 64 (SU2_ERR_UNSUPPORTED above); SU2_ERR_INVALID_VALUE for bad depth or
+ * block, mixed plans or null pointers. */
+su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream);
+
 /* Diagnostic: copy to host the FP64 Wigner-d table a single-B plan generated
  * for the pair (m, n) (doubled indices): host_out[k * L + i] = d^{l0+i}_{nm}(beta_k),
  * l0 = max(|m|, |n|), k = 0..2B-1, with *L = number of degrees l (may be NULL

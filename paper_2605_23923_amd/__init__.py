@@ -71,6 +71,8 @@ def _load():
         f.argtypes = [vp, vp, vp, vp]
         f.restype = i32
     lib.su2_run_stage.argtypes = [vp, i32, vp, vp, vp]
+    lib.su2_beta_forward_shifted.argtypes = [vp, i32, i32, vp, vp]
+    lib.su2_beta_forward_shifted.restype = i32
     lib.su2_run_stage.restype = i32
     lib.su2_num_samples.argtypes = [i32]
     lib.su2_num_samples.restype = i64
@@ -178,6 +180,17 @@ class _PlanBase:
         pin = ctypes.c_void_p(inp.data_ptr()) if inp is not None else ctypes.c_void_p()
         pout = ctypes.c_void_p(out.data_ptr()) if out is not None else ctypes.c_void_p()
         _check(_load().su2_run_stage(self._handle, code, pin, pout, _stream_handle(self.device)), "su2_run_stage")
+
+    def beta_forward_shifted(self, out: torch.Tensor | None = None, depth: int = 1, block: int = 4) -> torch.Tensor:
+        """The forward contraction stage in the shifted-recurrence
+        (divide-and-conquer) form, from the ring spectra a preceding
+        run_stage("ring_forward") left in the plan (see su2_beta_forward_shifted)."""
+        if out is None:
+            out = torch.empty(self.coeff_shape, dtype=self.torch_dtype, device=self.device)
+        self._check_tensor(out, self.total_coeffs, "out")
+        _check(_load().su2_beta_forward_shifted(self._handle, int(depth), int(block), ctypes.c_void_p(out.data_ptr()),
+                                                _stream_handle(self.device)), "su2_beta_forward_shifted")
+        return out
 
     def dtable(self, two_m: int, two_n: int):
         """The plan's FP64 Wigner-d table of pair (m, n) as a list of rows

@@ -329,9 +329,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
     e = upload_typed<float>(pl, W, twr, twi, rho_e);
   if (e != hipSuccess) return hip_fail(e);
 
-  if (pl->otf) {
-    if ((e = upload_otf_scalars(pl, beta)) != hipSuccess) return hip_fail(e);
-  } else {
+  // per-pair and per-node recurrence scalars: the on-the-fly tables and the
+  // shifted-recurrence contraction use them (a few MB)
+  if ((e = upload_otf_scalars(pl, beta)) != hipSuccess) return hip_fail(e);
+  if (!pl->otf) {
     // tables are padded by 64 bytes: the contraction kernels read whole 16-byte vectors
     if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
@@ -618,6 +619,21 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
     return SU2_OK;
   }
   return SU2_ERR_INVALID_VALUE;
+}
+
+su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream) {
+  if (!plan || plan->mixed || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (depth != 1 && depth != 2) return SU2_ERR_INVALID_VALUE;
+  if (depth == 2 && block != 2 && block != 4 && block != 8) return SU2_ERR_INVALID_VALUE;
+  if (!shifted_supported(plan->B)) return SU2_ERR_UNSUPPORTED;
+  hipError_t e;
+  if (plan->dtype == SU2_C128)
+    e = launch_beta_forward_shifted<double>(otf_params<double>(plan, 0), (const cpx<double>*)plan->d_S,
+                                            (cpx<double>*)d_coeffs, depth, block, (hipStream_t)stream);
+  else
+    e = launch_beta_forward_shifted<float>(otf_params<float>(plan, 0), (const cpx<float>*)plan->d_S,
+                                           (cpx<float>*)d_coeffs, depth, block, (hipStream_t)stream);
+  return e == hipSuccess ? SU2_OK : hip_fail(e);
 }
 
 const char* su2_status_string(su2_status_t status) {

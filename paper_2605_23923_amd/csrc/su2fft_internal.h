@@ -173,6 +173,12 @@ template <class T>
 hipError_t launch_beta_forward_otf(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s);
 template <class T>
 hipError_t launch_beta_inverse_otf(const OtfParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s);
+// forward contraction in the shifted-recurrence (divide-and-conquer) form;
+// depth 1 or 2 (coarse step blk in {2, 4, 8}); B <= 64
+bool shifted_supported(int B);
+template <class T>
+hipError_t launch_beta_forward_shifted(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, int depth, int blk,
+                                       hipStream_t s);
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s);
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,

@@ -33,6 +33,7 @@
 #include "su2fft_beta.hip"
 #include "su2fft_beta_bf16.hip"
 #include "su2fft_beta_otf.hip"
+#include "su2fft_beta_shifted.hip"
 #include "su2fft_plan.h"
 
 namespace su2 {
