@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="c64", choices=["c128", "c64", "c64_bf16x3"],
                     help="precision mode of the headline number")
-    ap.add_argument("--other-modes", default="c128,c64_otf",
+    ap.add_argument("--other-modes", default="c128,c64_bf16x3,c64_otf",
                     help="comma-separated modes also timed and reported under 'modes' ('' for none); "
                          "'_otf' = Wigner-d values generated inside the contraction kernels")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
