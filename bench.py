@@ -34,12 +34,16 @@ FP64_VALU_PEAK = 78.6e12     # flop/s, FP64 vector (256 CUs x 4 SIMDs x 16 lanes
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
-# a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf":
-# Wigner-d values generated inside the contraction kernels instead of stored
+# a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf"
+# (Wigner-d values generated inside the contraction kernels instead of stored)
+# or "_real" (real signals: real samples, half of the pairs contracted)
 
 
 def base_mode(mode: str) -> str:
-    return mode[:-4] if mode.endswith("_otf") else mode
+    for suffix in ("_otf", "_real"):
+        if mode.endswith(suffix):
+            return mode[: -len(suffix)]
+    return mode
 
 
 def kernel_name(stage: str, mode: str) -> str:
@@ -78,6 +82,15 @@ def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     ring = N ** 3 * cb                       # one signal's samples
     spec = retained_pairs(B) * N * cb        # one signal's retained ring spectra
     coef = C * cb
+    if mode.endswith("_real"):
+        # real samples; spectra of the (P + 1) / 2 pairs with 2m >= 0 (mirrors
+        # excluded); every coefficient written (forward) or read (inverse);
+        # the table rows of those pairs
+        ring = N ** 3 * cb // 2
+        spec = (retained_pairs(B) + 1) // 2 * N * cb
+        if stage.startswith("ring"):
+            return batch * (ring + spec)
+        return batch * (spec + coef) + table_bytes(B, base_mode(mode)) // 2
     if stage.startswith("ring"):
         return batch * (ring + spec)
     return batch * (spec + coef) + table_bytes(B, mode)
@@ -124,7 +137,8 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
     import paper_2605_23923_amd as su2
     import synth
 
-    plan = su2.Plan(B, batch, base_mode(mode), tables="on_the_fly" if mode.endswith("_otf") else "stored")
+    plan = su2.Plan(B, batch, base_mode(mode), tables="on_the_fly" if mode.endswith("_otf") else "stored",
+                    real=mode.endswith("_real"))
     np_dt = "complex128" if base_mode(mode) == "c128" else "complex64"
     c_host = synth.coeffs(B, batch, seed=2, spectrum="decay").astype(np_dt)
     coeffs = torch.from_numpy(c_host).to("cuda")
@@ -334,9 +348,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="c64", choices=["c128", "c64", "c64_bf16x3"],
                     help="precision mode of the headline number")
-    ap.add_argument("--other-modes", default="c128,c64_bf16x3,c64_otf",
+    ap.add_argument("--other-modes", default="c128,c64_bf16x3,c64_otf,c64_real",
                     help="comma-separated modes also timed and reported under 'modes' ('' for none); "
-                         "'_otf' = Wigner-d values generated inside the contraction kernels")
+                         "'_otf' = Wigner-d values generated inside the contraction kernels, "
+                         "'_real' = real-signal plan")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",

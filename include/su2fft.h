@@ -89,7 +89,20 @@ enum {
    * doubles instead of C(B) * 2B table values: 724 MB of FP32 at B = 128).
    * Same results as the stored table up to rounding.  SU2_C128 and SU2_C64
    * only (SU2_ERR_UNSUPPORTED for SU2_C64_BF16X3). */
-  SU2_PLAN_TABLES_ON_THE_FLY = 1u
+  SU2_PLAN_TABLES_ON_THE_FLY = 1u,
+  /* Real signals.  The samples are real (double for SU2_C128, float for
+   * SU2_C64; N^3 values per signal, same order), the coefficients complex as
+   * usual.  A real f has fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
+   * (Definition 3.4 with conj(t^l_{nm}) = (-1)^{m-n} t^l_{-n,-m}), so both
+   * stages run only for the pairs with 2m > 0, or 2m = 0 and 2n >= 0:
+   * su2_forward writes every coefficient (the others by the symmetry);
+   * su2_inverse and su2_adjoint return the real part of the complex result,
+   * i.e. they read the Hermitian part (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
+   * of the coefficients (the adjoint is then the adjoint of the real-input
+   * forward map).  SU2_C128 and SU2_C64 with B in {8, 16, 32, 64}, without
+   * SU2_PLAN_TABLES_ON_THE_FLY; SU2_ERR_UNSUPPORTED otherwise.
+   * su2_beta_forward_shifted does not accept real-signal plans. */
+  SU2_PLAN_REAL_SIGNALS = 2u
 };
 
 /* su2_plan_create with options: `flags` is a bitwise or of SU2_PLAN_* values

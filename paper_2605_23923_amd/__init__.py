@@ -129,11 +129,12 @@ def _stream_handle(device) -> ctypes.c_void_p:
 class _PlanBase:
     _handle = None
 
-    def _check_tensor(self, t: torch.Tensor, numel: int, what: str):
+    def _check_tensor(self, t: torch.Tensor, numel: int, what: str, dtype=None):
+        dtype = self.torch_dtype if dtype is None else dtype
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError(f"{what} must be a CUDA (HIP) tensor")
-        if t.dtype != self.torch_dtype:
-            raise TypeError(f"{what} must be {self.torch_dtype}, got {t.dtype}")
+        if t.dtype != dtype:
+            raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
         if not t.is_contiguous():
             raise ValueError(f"{what} must be contiguous")
         if t.numel() != numel:
@@ -146,8 +147,13 @@ class _PlanBase:
                                       ctypes.c_void_p(dst.data_ptr()), _stream_handle(self.device))
         _check(status, fn)
 
+    @property
+    def sample_dtype(self):
+        """torch dtype of the samples: complex, or real for real-signal plans."""
+        return getattr(self, "_sample_dtype", self.torch_dtype)
+
     def forward(self, samples: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        self._check_tensor(samples, self.total_samples, "samples")
+        self._check_tensor(samples, self.total_samples, "samples", self.sample_dtype)
         if out is None:
             out = torch.empty(self.coeff_shape, dtype=self.torch_dtype, device=self.device)
         self._check_tensor(out, self.total_coeffs, "out")
@@ -157,16 +163,16 @@ class _PlanBase:
     def inverse(self, coeffs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check_tensor(coeffs, self.total_coeffs, "coeffs")
         if out is None:
-            out = torch.empty(self.sample_shape, dtype=self.torch_dtype, device=self.device)
-        self._check_tensor(out, self.total_samples, "out")
+            out = torch.empty(self.sample_shape, dtype=self.sample_dtype, device=self.device)
+        self._check_tensor(out, self.total_samples, "out", self.sample_dtype)
         self._call("su2_inverse", coeffs, out)
         return out
 
     def adjoint(self, coeffs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check_tensor(coeffs, self.total_coeffs, "coeffs")
         if out is None:
-            out = torch.empty(self.sample_shape, dtype=self.torch_dtype, device=self.device)
-        self._check_tensor(out, self.total_samples, "out")
+            out = torch.empty(self.sample_shape, dtype=self.sample_dtype, device=self.device)
+        self._check_tensor(out, self.total_samples, "out", self.sample_dtype)
         self._call("su2_adjoint", coeffs, out)
         return out
 
@@ -224,6 +230,7 @@ class _PlanBase:
 
 
 PLAN_TABLES_ON_THE_FLY = 1  # SU2_PLAN_TABLES_ON_THE_FLY
+PLAN_REAL_SIGNALS = 2       # SU2_PLAN_REAL_SIGNALS
 
 
 class Plan(_PlanBase):
@@ -231,17 +238,25 @@ class Plan(_PlanBase):
 
     tables: "stored" keeps the Wigner-d table in device memory (generated once
     at plan creation); "on_the_fly" generates the values inside the
-    contraction kernels on every call (c128 and c64 only)."""
+    contraction kernels on every call (c128 and c64 only).
 
-    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored"):
+    real: real-signal plan (c128 / c64, B in {8, 16, 32, 64}): samples are
+    float64 / float32 tensors; forward returns every coefficient, inverse and
+    adjoint return the real part of the complex result (see
+    SU2_PLAN_REAL_SIGNALS)."""
+
+    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored", real=False):
         if tables not in ("stored", "on_the_fly"):
             raise ValueError(f"tables must be 'stored' or 'on_the_fly', got {tables!r}")
-        flags = PLAN_TABLES_ON_THE_FLY if tables == "on_the_fly" else 0
+        flags = (PLAN_TABLES_ON_THE_FLY if tables == "on_the_fly" else 0) | (PLAN_REAL_SIGNALS if real else 0)
         self.tables = tables
+        self.real = bool(real)
         lib = _load()
         self.B, self.batch = int(B), int(batch)
         self.dtype = _DTYPES[dtype]
         self.torch_dtype = _TORCH_DTYPE[self.dtype]
+        if self.real:
+            self._sample_dtype = torch.float64 if self.torch_dtype == torch.complex128 else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.N = 2 * self.B

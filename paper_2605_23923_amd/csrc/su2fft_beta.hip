@@ -113,7 +113,10 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
 
   PairInfo pi[2];
 #pragma unroll
-  for (int i = 0; i < 2; i++) pi[i] = p.pairs[tile * PT + wave + 8 * i];
+  for (int i = 0; i < 2; i++) {
+    pi[i] = p.pairs[tile * PT + wave + 8 * i];
+    if (p.real && mirrored_pair(pi[i].tm, pi[i].tn)) pi[i].L = 0;
+  }
 
   accT acc[2][RTMAX][CT];
 #pragma unroll
@@ -227,8 +230,15 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
         for (int r = 0; r < 4; r++) {
           const int l = rt * 16 + acc_row<T>(lane, r);
           if (l < L) {
+            const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
             const long long idx = coeff_index(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
-            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
+            out[(cb0 + idx) * 2 + reim] = acc[i][rt][ct][r];
+            if (p.real && (pi[i].tm != 0 || pi[i].tn != 0)) {
+              // mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
+              const T sg = (((pi[i].tm - pi[i].tn) / 2) & 1) ? T(-1) : T(1);
+              const long long mdx = coeff_index(pi[i].tl0 + 2 * l, -pi[i].tm, -pi[i].tn);
+              out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
+            }
           }
         }
       }
@@ -240,7 +250,7 @@ template <class T, int RTMAX>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_forward_body<T, RTMAX>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
@@ -285,6 +295,7 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     pi[q] = p.pairs[tile * PT + wave + 8 * q];
+    if (p.real && mirrored_pair(pi[q].tm, pi[q].tn)) pi[q].L = 0;
 #pragma unroll
     for (int s = 0; s < LQ; s++) {
       const int l = 4 * s + lk;
@@ -295,9 +306,18 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
         T v = T(0);
         if (l < pi[q].L && bb < nb) {
           const int tl = pi[q].tl0 + 2 * l;
+          const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
           const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
           const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
-          v = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim];
+          v = cin[(cb0 + idx) * 2 + reim];
+          if (p.real) {
+            // Hermitian part: (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
+            const T sg = (((pi[q].tm - pi[q].tn) / 2) & 1) ? T(-1) : T(1);
+            const long long mdx = coeff_index(tl, -pi[q].tm, -pi[q].tn);
+            const T w = cin[(cb0 + mdx) * 2 + reim];
+            v = T(0.5) * (v + (reim ? -sg : sg) * w);
+          }
+          v *= sc;
         }
         bop[q][s][ct] = v;
       }
@@ -370,7 +390,7 @@ template <class T, int LQ>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
                                                                    cpx<T>* __restrict__ S, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_body<T, LQ>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_inverse_body<T, LQ>(coeffs, S, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)
@@ -382,7 +402,7 @@ static hipError_t set_smem(K kern, size_t smem) {
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
   constexpr int BT = BetaCfg<T>::BT;
-  dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
+  dim3 grid(p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
   const int rt = beta_rtmax(p.B);
   hipError_t e;
   if (rt == 1) {
@@ -404,7 +424,7 @@ hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* 
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
   constexpr int BT = BetaCfg<T>::BT;
-  dim3 grid(p.ntiles, (p.batch + BT - 1) / BT);
+  dim3 grid(p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);
   hipError_t e;

@@ -274,6 +274,24 @@ su2_status_t build_plan(su2_plan_s* pl) {
     pl->rbeg[r] = pidx < pl->rbeg[r] ? pidx : pl->rbeg[r];
     pl->rend[r] = pidx + 1 > pl->rend[r] ? pidx + 1 : pl->rend[r];
   }
+  // real signals: every bin's source pair (its own, or the mirror (-m, -n)
+  // with a conjugate) for the inverse ring kernel
+  std::vector<int> bins_real;
+  if (pl->real) {
+    std::vector<int> at((size_t)(2 * B - 1) * (2 * B - 1), -1);
+    for (int pidx = 0; pidx < pl->P; pidx++)
+      at[(size_t)(pairs[pidx].tm + B - 1) * (2 * B - 1) + pairs[pidx].tn + B - 1] = pidx;
+    bins_real.assign((size_t)N * N, -1);
+    for (int pidx = 0; pidx < pl->P; pidx++) {
+      const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
+      const int q = imod(tm, N);
+      const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
+      const bool mir = mirrored_pair(tm, tn);
+      const int src = mir ? at[(size_t)(-tm + B - 1) * (2 * B - 1) + (-tn + B - 1)] : pidx;
+      if (src < 0) return SU2_ERR_UNSUPPORTED;
+      bins_real[(size_t)q * N + palpha] = (src << 3) | ((mir ? 1 : 0) << 2) | rho_e[pidx];
+    }
+  }
   for (int r = 0; r < FAST_ROUNDS; r++) {
     if (pl->rend[r] < pl->rbeg[r]) pl->rbeg[r] = pl->rend[r] = 0;
     const int cap = pl->dtype == SU2_C128 ? fast_ring_slice_capacity<double>(N) : fast_ring_slice_capacity<float>(N);
@@ -315,6 +333,12 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
+  if (pl->real) {
+    if ((e = pl->alloc((void**)&pl->d_bins_real, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpy(pl->d_bins_real, bins_real.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
   if ((e = hipMemcpy(pl->d_pairs, pairs.data(), sizeof(PairInfo) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
   if ((e = hipMemcpy(pl->d_fftpos, fftpos.data(), sizeof(int) * pl->P_pad, hipMemcpyHostToDevice)) != hipSuccess)
@@ -380,7 +404,9 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
   hipError_t e = hipSuccess;
   switch (stage) {
     case SU2_STAGE_RING_FORWARD:
-      if (pl->large)
+      if (pl->real)
+        e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)pl->d_S, s);
+      else if (pl->large)
         e = launch_ring_forward_large<T>(large_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
       else if (pl->fast)
         e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
@@ -404,7 +430,10 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
-      if (pl->large)
+      if (pl->real)
+        e = launch_ring_inverse_fast_real<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
+                                             (const cpx<T>*)pl->d_S, (T*)out, s);
+      else if (pl->large)
         e = launch_ring_inverse_large<T>(large_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
                                          (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
       else if (pl->fast)
@@ -501,9 +530,12 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   *out = nullptr;
   if (B < 1 || batch < 1) return SU2_ERR_INVALID_VALUE;
   if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
-  if (flags & ~(uint32_t)SU2_PLAN_TABLES_ON_THE_FLY) return SU2_ERR_INVALID_VALUE;
+  if (flags & ~(uint32_t)(SU2_PLAN_TABLES_ON_THE_FLY | SU2_PLAN_REAL_SIGNALS)) return SU2_ERR_INVALID_VALUE;
   if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
   if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) && dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
+  if ((flags & SU2_PLAN_REAL_SIGNALS) &&
+      (dtype == SU2_C64_BF16X3 || (flags & SU2_PLAN_TABLES_ON_THE_FLY) || (B != 8 && B != 16 && B != 32 && B != 64)))
+    return SU2_ERR_UNSUPPORTED;
   su2_status_t st = check_device();
   if (st != SU2_OK) return st;
   su2_plan_s* pl = new (std::nothrow) su2_plan_s();
@@ -512,6 +544,7 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   pl->batch = batch;
   pl->dtype = dtype;
   pl->otf = (flags & SU2_PLAN_TABLES_ON_THE_FLY) != 0;
+  pl->real = (flags & SU2_PLAN_REAL_SIGNALS) != 0;
   st = build_plan(pl);
   if (st != SU2_OK) {
     (void)hipDeviceSynchronize();
@@ -622,7 +655,7 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
 }
 
 su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream) {
-  if (!plan || plan->mixed || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (!plan || plan->mixed || plan->real || !d_coeffs) return SU2_ERR_INVALID_VALUE;
   if (depth != 1 && depth != 2) return SU2_ERR_INVALID_VALUE;
   if (depth == 2 && block != 2 && block != 4 && block != 8) return SU2_ERR_INVALID_VALUE;
   if (!shifted_supported(plan->B)) return SU2_ERR_UNSUPPORTED;

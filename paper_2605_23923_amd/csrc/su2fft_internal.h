@@ -1,6 +1,8 @@
 // Internal declarations shared by the su2fft host code and its HIP kernels.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -93,6 +95,9 @@ struct FastRingParams {
   int adjoint;        // inverse chain: 0 -> plain, 1 -> multiply by W_k
   int rbeg[FAST_ROUNDS], rend[FAST_ROUNDS];
   const long long* soff;  // per signal sample offsets, or null
+  // real signals (inverse): [q * N + p]: (source pair << 3) | (conjugate << 2) | e,
+  // the source being the bin's own pair (2m >= 0) or its mirror (-m, -n)
+  const int* bins_real;
 };
 
 // Parameters of the two-pass ring kernels (N = 256): the register-resident
@@ -116,7 +121,15 @@ struct BetaParams {
   const T* tab;             // Wigner-d table, tile-major (see PairInfo)
   int scale_mode;           // inverse: 0 -> (2l+1) weights, 1 -> none (adjoint)
   const long long* coff;    // per signal: offset of its coefficients (complex values), or null: b * ncoef
+  // real signals: only pairs with 2m > 0, or 2m = 0 and 2n >= 0, are contracted;
+  // the forward also writes the mirror coefficient (-1)^{m-n} conj(fhat(l)_{mn})
+  // at (-m, -n), the inverse reads the Hermitian part of the coefficients
+  int real;
+  int tile0;                // first pair tile launched (grid x = ntiles - tile0)
 };
+
+// pair (m, n) of a real-signal plan whose values come from its mirror (-m, -n)
+__host__ __device__ inline bool mirrored_pair(int tm, int tn) { return tm < 0 || (tm == 0 && tn < 0); }
 
 // Tables generated inside the contraction kernels ("on the fly"): the FP64
 // three-term recurrence in l runs per (pair, node) from its seed; only
@@ -213,6 +226,11 @@ template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s);
 template <class T>
 hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s);
+// real signals: real samples in or out; only the pairs with 2m >= 0 carry spectra
+template <class T>
+hipError_t launch_ring_forward_fast_real(const FastRingParams<T>& p, const T* samples, cpx<T>* S, hipStream_t s);
+template <class T>
+hipError_t launch_ring_inverse_fast_real(const FastRingParams<T>& p, const cpx<T>* S, T* samples, hipStream_t s);
 
 bool large_ring_supported(int N);
 int large_ring_block();           // gamma frequencies per block (pair ranges are given per block)

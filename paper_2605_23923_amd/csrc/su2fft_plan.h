@@ -38,6 +38,8 @@ struct su2_plan_s {
   // tables generated inside the contraction kernels: per-pair seed constants,
   // recurrence coefficients, node values
   bool otf = false;
+  bool real = false;            // real-signal plan (pairs with 2m >= 0 carry the spectra)
+  int* d_bins_real = nullptr;
   double* d_seedc = nullptr;
   double* d_rcoef = nullptr;
   double* d_nodes = nullptr;  // [3][N]: cos(beta_k), cos(beta_k / 2), sin(beta_k / 2)
@@ -111,6 +113,7 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   r.adjoint = adjoint;
   for (int i = 0; i < FAST_ROUNDS; i++) { r.rbeg[i] = pl->rbeg[i]; r.rend[i] = pl->rend[i]; }
   r.soff = pl->d_soff;
+  r.bins_real = pl->d_bins_real;
   return r;
 }
 
@@ -151,6 +154,8 @@ BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
   b.tab = tab;
   b.scale_mode = scale_mode;
   b.coff = pl->d_coff;
+  b.real = pl->real ? 1 : 0;
+  b.tile0 = pl->real ? pl->rbeg[0] / PT : 0;
   return b;
 }
 

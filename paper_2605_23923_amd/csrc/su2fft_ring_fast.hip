@@ -154,14 +154,17 @@ __device__ __forceinline__ cpx<T> halfbin(cpx<T> a) {
   return rot16<T, J * (16 / (2 * N2)), SIGN>(a);
 }
 
-// One ring (signal b, node k); x is the ring's N x N input block, t the
-// thread's index in the workgroup.
-template <class T, int N1, int N2, int NT, int ROUNDS>
-__device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ S,
+// One ring (signal b, node k); xv is the ring's N x N input block (complex,
+// or real for REAL), t the thread's index in the workgroup.  REAL: a real ring
+// has a Hermitian spectrum, so only the first q slice (2m >= 0) is formed and
+// written; the contraction and the inverse take the rest from the symmetry.
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL = false>
+__device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ xv, cpx<T>* __restrict__ S,
                                                        const FastRingParams<T>& p, int b, int k,
                                                        unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
   constexpr int N = G::N;
+  constexpr int RR = REAL ? 1 : ROUNDS;  // q slices formed after the gamma transform
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = buf + G::BUF;  // e^{i pi t / N}, t = 0..2N-1
@@ -174,7 +177,12 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
   for (int s = 0; s < G::I1; s++) {
     const int j = t / N1 + (NT / N1) * s;
 #pragma unroll
-    for (int l2 = 0; l2 < N2; l2++) a[s][l2] = ld_stream(x + j * N + l1 + N1 * l2);
+    for (int l2 = 0; l2 < N2; l2++) {
+      if constexpr (REAL)
+        a[s][l2] = {__builtin_nontemporal_load(reinterpret_cast<const T*>(xv) + j * N + l1 + N1 * l2), T(0)};
+      else
+        a[s][l2] = ld_stream(reinterpret_cast<const cpx<T>*>(xv) + j * N + l1 + N1 * l2);
+    }
   }
   __syncthreads();
   cpx<T> tw1[N2];  // w^{q2 l1}: this thread's l1 is the same in every instance
@@ -219,7 +227,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
 #pragma unroll
   for (int p2 = 0; p2 < N2; p2++) tw3[p2] = tw[((2 * p2 + odd) * j1) % (2 * N)];
 #pragma unroll
-  for (int r = 0; r < ROUNDS; r++) {
+  for (int r = 0; r < RR; r++) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < G::I2; s++) {
@@ -238,7 +246,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
     }
   }
 #pragma unroll
-  for (int s = 0; s < G::I1; s++) {
+  for (int s = 0; s < RR * (G::I1 / ROUNDS); s++) {
     if (odd) {
       a[s][1] = halfbin<T, N2, 1, 1>(a[s][1]);
       if constexpr (N2 > 2) {
@@ -262,7 +270,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
   const int p2 = t % N2;
   const T Wk = p.W[k];
 #pragma unroll
-  for (int r = 0; r < ROUNDS; r++) {
+  for (int r = 0; r < RR; r++) {
     static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
     const int q = t / N2 + (NT / N2) * r;
     // this thread's bin entries for the round, fetched before the exchange so
@@ -296,8 +304,11 @@ __device__ __forceinline__ void ring_forward_fast_body(const cpx<T>* __restrict_
   }
 }
 
-template <class T, int N1, int N2, int NT, int ROUNDS>
-__device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xo,
+// REAL: the output ring is real.  Only the first q slice's pairs (2m >= 0)
+// hold spectra; every bin reads its pair's value or the conjugate of its
+// mirror pair's (bins_real), and only the real part is written.
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL = false>
+__device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, void* __restrict__ xov,
                                                        const FastRingParams<T>& p, int b, int k,
                                                        unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
@@ -313,9 +324,10 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
   //      latency per ring); then per round: stage the slice in LDS, gather,
   //      phase 4' (radix-N1 over p1 -> j1), exchange 3' (write)
   constexpr int SPR = G::SLICE_PER_THREAD;
-  cpx<T> sv[ROUNDS][SPR];
+  constexpr int SR = REAL ? 1 : ROUNDS;  // distinct slices held (REAL: both rounds read the first)
+  cpx<T> sv[SR][SPR];
 #pragma unroll
-  for (int r = 0; r < ROUNDS; r++) {
+  for (int r = 0; r < SR; r++) {
     const int pb = p.rbeg[r], pe = p.rend[r];
 #pragma unroll
     for (int i = 0; i < SPR; i++) {
@@ -327,16 +339,18 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
   cpx<T> a[G::I1][N2];
 #pragma unroll
   for (int r = 0; r < ROUNDS; r++) {
-    const int pb = p.rbeg[r], pe = p.rend[r];
+    const int rs = REAL ? 0 : r;  // slice staged in this round
+    const int pb = p.rbeg[rs], pe = p.rend[rs];
     static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
     const int q = t / N2 + (NT / N2) * r;
     int ent[N1 / 2];
+    const int* bins = REAL ? p.bins_real : p.bins;
 #pragma unroll
-    for (int i = 0; i < N1 / 2; i++) ent[i] = p.bins[q * N + p2 + N2 * kept_row<N1>(i)];
+    for (int i = 0; i < N1 / 2; i++) ent[i] = bins[q * N + p2 + N2 * kept_row<N1>(i)];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SPR; i++)
-      if (pb + t + NT * i < pe) buf[t + NT * i] = sv[r][i];
+      if (pb + t + NT * i < pe) buf[t + NT * i] = sv[REAL ? 0 : r][i];
     __syncthreads();
     cpx<T> h[N1];
 #pragma unroll
@@ -345,7 +359,14 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     for (int i = 0; i < N1 / 2; i++) {
       // every lane reads a valid slot; bins that are not retained are zeroed
       const int e = ent[i];
-      const cpx<T> v = ipow_scale(buf[e >= 0 ? (e >> 2) - pb : 0], (4 - (e & 3)) & 3, scale);
+      cpx<T> v;
+      if constexpr (REAL) {  // (source pair << 3) | (conjugate << 2) | phase
+        v = buf[e >= 0 ? (e >> 3) - pb : 0];
+        if ((e >> 2) & 1) v.im = -v.im;
+      } else {
+        v = buf[e >= 0 ? (e >> 2) - pb : 0];
+      }
+      v = ipow_scale(v, (4 - (e & 3)) & 3, scale);
       h[kept_row<N1>(i)] = e >= 0 ? v : cpx<T>{T(0), T(0)};
     }
     dftr<T, N1, -1>(h);
@@ -441,7 +462,12 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmulc(a[s][q2], tw1[q2]);
     dftr<T, N2, -1>(a[s]);
 #pragma unroll
-    for (int l2 = 0; l2 < N2; l2++) st_stream(xo + j * N + l1 + N1 * l2, a[s][l2]);
+    for (int l2 = 0; l2 < N2; l2++) {
+      if constexpr (REAL)
+        __builtin_nontemporal_store(a[s][l2].re, reinterpret_cast<T*>(xov) + j * N + l1 + N1 * l2);
+      else
+        st_stream(reinterpret_cast<cpx<T>*>(xov) + j * N + l1 + N1 * l2, a[s][l2]);
+    }
   }
 }
 
@@ -478,44 +504,46 @@ struct FastRing {
 
 // The workgroup's RPW rings (signal b, nodes k0 .. k0 + RPW - 1); t is the
 // thread's index in the workgroup.
-template <class T, int N>
-__device__ __forceinline__ void ring_forward_fast_group(const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S,
+template <class T, int N, bool REAL = false>
+__device__ __forceinline__ void ring_forward_fast_group(const void* __restrict__ samples, cpx<T>* __restrict__ S,
                                                         const FastRingParams<T>& p, int b, int k0,
                                                         unsigned char* smem, int t) {
   typedef FastRing<T, N> R;
+  typedef typename std::conditional<REAL, T, cpx<T>>::type E;  // sample element
   const int sub = R::RPW == 1 ? 0 : t / R::C::NTR, k = k0 + sub;
-  ring_forward_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS>(
-      samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, S, p, b, k, smem + sub * R::RING_SMEM,
-      R::RPW == 1 ? t : t - sub * R::C::NTR);
+  ring_forward_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS, REAL>(
+      reinterpret_cast<const E*>(samples) + ring_offset(p.soff, b, N) + (size_t)k * N * N, S, p, b, k,
+      smem + sub * R::RING_SMEM, R::RPW == 1 ? t : t - sub * R::C::NTR);
 }
 
-template <class T, int N>
-__device__ __forceinline__ void ring_inverse_fast_group(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples,
+template <class T, int N, bool REAL = false>
+__device__ __forceinline__ void ring_inverse_fast_group(const cpx<T>* __restrict__ S, void* __restrict__ samples,
                                                         const FastRingParams<T>& p, int b, int k0,
                                                         unsigned char* smem, int t) {
   typedef FastRing<T, N> R;
+  typedef typename std::conditional<REAL, T, cpx<T>>::type E;
   const int sub = R::RPW == 1 ? 0 : t / R::C::NTR, k = k0 + sub;
-  ring_inverse_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS>(
-      S, samples + ring_offset(p.soff, b, N) + (size_t)k * N * N, p, b, k, smem + sub * R::RING_SMEM,
-      R::RPW == 1 ? t : t - sub * R::C::NTR);
+  ring_inverse_fast_body<T, R::C::N1, R::C::N2, R::C::NTR, FAST_ROUNDS, REAL>(
+      S, reinterpret_cast<E*>(samples) + ring_offset(p.soff, b, N) + (size_t)k * N * N, p, b, k,
+      smem + sub * R::RING_SMEM, R::RPW == 1 ? t : t - sub * R::C::NTR);
 }
 
-template <class T, int N>
+template <class T, int N, bool REAL>
 __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_forward_fast(
-    const cpx<T>* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
+    const void* __restrict__ samples, cpx<T>* __restrict__ S, FastRingParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring0 = blockIdx.x * FastRing<T, N>::RPW;
   const int b = ring0 / N;
-  ring_forward_fast_group<T, N>(samples, S, p, b, ring0 - b * N, smem_raw, threadIdx.x);
+  ring_forward_fast_group<T, N, REAL>(samples, S, p, b, ring0 - b * N, smem_raw, threadIdx.x);
 }
 
-template <class T, int N>
+template <class T, int N, bool REAL>
 __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_inverse_fast(
-    const cpx<T>* __restrict__ S, cpx<T>* __restrict__ samples, FastRingParams<T> p) {
+    const cpx<T>* __restrict__ S, void* __restrict__ samples, FastRingParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring0 = blockIdx.x * FastRing<T, N>::RPW;
   const int b = ring0 / N;
-  ring_inverse_fast_group<T, N>(S, samples, p, b, ring0 - b * N, smem_raw, threadIdx.x);
+  ring_inverse_fast_group<T, N, REAL>(S, samples, p, b, ring0 - b * N, smem_raw, threadIdx.x);
 }
 
 template <class T>
@@ -556,6 +584,7 @@ int fast_rings_per_group(int N) {
 }
 
 // the epilogue / prologue stage a slice's pair range in the ring's exchange buffer
+
 template <class T, int N>
 static bool slices_fit(const FastRingParams<T>& p) {
   for (int r = 0; r < FAST_ROUNDS; r++)
@@ -564,41 +593,51 @@ static bool slices_fit(const FastRingParams<T>& p) {
 }
 
 template <class T, int N>
-static hipError_t launch_fast(bool forward, const FastRingParams<T>& p, const cpx<T>* in, cpx<T>* out,
+static hipError_t launch_fast(bool forward, bool real, const FastRingParams<T>& p, const void* in, void* out,
                               hipStream_t s) {
   typedef FastRing<T, N> R;
-  if (!slices_fit<T, N>(p)) return hipErrorInvalidValue;
-  const void* kern = forward ? (const void*)ring_forward_fast<T, N> : (const void*)ring_inverse_fast<T, N>;
+  if (!slices_fit<T, N>(p) || (real && !p.bins_real)) return hipErrorInvalidValue;
+  const void* kern =
+      forward ? (real ? (const void*)ring_forward_fast<T, N, true> : (const void*)ring_forward_fast<T, N, false>)
+              : (real ? (const void*)ring_inverse_fast<T, N, true> : (const void*)ring_inverse_fast<T, N, false>);
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)R::SMEM);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((long long)p.batch * N / R::RPW));
-  if (forward)
-    hipLaunchKernelGGL((ring_forward_fast<T, N>), grid, dim3(FAST_NT), R::SMEM, s, in, out, p);
-  else
-    hipLaunchKernelGGL((ring_inverse_fast<T, N>), grid, dim3(FAST_NT), R::SMEM, s, in, out, p);
-  return hipGetLastError();
+  FastRingParams<T> pp = p;
+  void* args[] = {(void*)&in, (void*)&out, (void*)&pp};
+  return hipLaunchKernel(kern, grid, dim3(FAST_NT), args, R::SMEM, s);
 }
 
 template <class T>
-static hipError_t launch_fast_any(bool forward, const FastRingParams<T>& p, const cpx<T>* in, cpx<T>* out,
+static hipError_t launch_fast_any(bool forward, bool real, const FastRingParams<T>& p, const void* in, void* out,
                                   hipStream_t s) {
   switch (p.N) {
-    case 16: return launch_fast<T, 16>(forward, p, in, out, s);
-    case 32: return launch_fast<T, 32>(forward, p, in, out, s);
-    case 64: return launch_fast<T, 64>(forward, p, in, out, s);
-    case 128: return launch_fast<T, 128>(forward, p, in, out, s);
+    case 16: return launch_fast<T, 16>(forward, real, p, in, out, s);
+    case 32: return launch_fast<T, 32>(forward, real, p, in, out, s);
+    case 64: return launch_fast<T, 64>(forward, real, p, in, out, s);
+    case 128: return launch_fast<T, 128>(forward, real, p, in, out, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class T>
 hipError_t launch_ring_forward_fast(const FastRingParams<T>& p, const cpx<T>* samples, cpx<T>* S, hipStream_t s) {
-  return launch_fast_any<T>(true, p, samples, S, s);
+  return launch_fast_any<T>(true, false, p, samples, S, s);
 }
 
 template <class T>
 hipError_t launch_ring_inverse_fast(const FastRingParams<T>& p, const cpx<T>* S, cpx<T>* samples, hipStream_t s) {
-  return launch_fast_any<T>(false, p, S, samples, s);
+  return launch_fast_any<T>(false, false, p, S, samples, s);
+}
+
+template <class T>
+hipError_t launch_ring_forward_fast_real(const FastRingParams<T>& p, const T* samples, cpx<T>* S, hipStream_t s) {
+  return launch_fast_any<T>(true, true, p, samples, S, s);
+}
+
+template <class T>
+hipError_t launch_ring_inverse_fast_real(const FastRingParams<T>& p, const cpx<T>* S, T* samples, hipStream_t s) {
+  return launch_fast_any<T>(false, true, p, S, samples, s);
 }
 
 template size_t fast_ring_smem<float>(int);
@@ -615,5 +654,13 @@ template hipError_t launch_ring_inverse_fast<float>(const FastRingParams<float>&
                                                     hipStream_t);
 template hipError_t launch_ring_inverse_fast<double>(const FastRingParams<double>&, const cpx<double>*, cpx<double>*,
                                                      hipStream_t);
+template hipError_t launch_ring_forward_fast_real<float>(const FastRingParams<float>&, const float*, cpx<float>*,
+                                                         hipStream_t);
+template hipError_t launch_ring_forward_fast_real<double>(const FastRingParams<double>&, const double*, cpx<double>*,
+                                                          hipStream_t);
+template hipError_t launch_ring_inverse_fast_real<float>(const FastRingParams<float>&, const cpx<float>*, float*,
+                                                         hipStream_t);
+template hipError_t launch_ring_inverse_fast_real<double>(const FastRingParams<double>&, const cpx<double>*, double*,
+                                                          hipStream_t);
 
 }  // namespace su2

@@ -88,10 +88,15 @@ def test_argument_validation_before_any_device_call():
     # plan options: unknown bits, and on-the-fly tables with the split-BF16 mode
     lib.su2_plan_create_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_void_p)]
-    assert lib.su2_plan_create_ex(8, 1, 1, 2, ctypes.byref(h)) == 1
+    assert lib.su2_plan_create_ex(8, 1, 1, 4, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 1, 1, 0x80000000, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 1, 2, 1, ctypes.byref(h)) == 2
     assert lib.su2_plan_create_ex(0, 1, 1, 1, ctypes.byref(h)) == 1
+    # real signals: not with the split-BF16 mode, not with generated tables, B in {8, 16, 32, 64}
+    assert lib.su2_plan_create_ex(8, 1, 2, 2, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(8, 1, 1, 3, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(24, 1, 1, 2, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(128, 1, 0, 2, ctypes.byref(h)) == 2
 
 
 def test_valid_plan_without_device_reports_no_device():
