@@ -3,8 +3,9 @@
 
 The paper's grid (Definition 4.1) puts both phi and psi on [-pi, pi]; that is
 the group SO(3) = SU(2)/{+-1}, on which only integer l occur.  This module is
-the transform of Definition 3.4 restricted to that case, on a grid of N = B
-nodes per angle (B bounds 2l, as everywhere in this package):
+the transform of Definition 3.4 restricted to that case, on the paper's
+domain with periodic nodes and N = 2B nodes per angle (B bounds 2l, as
+everywhere in this package; the same N as the SU(2) grid):
 
     alpha_j = -pi + 2 pi j / N,  gamma_l = -pi + 2 pi l / N,  beta_k = pi k / (N - 1),
     W_k = w_k / (2 N^2)   (Clenshaw-Curtis w_k on cos beta_k; (2pi/N)^2 w_k / (8 pi^2)),
@@ -16,7 +17,7 @@ nodes per angle (B bounds 2l, as everywhere in this package):
 with the basis values P^l_{nm}(cos beta) taken from the SU(2) oracle
 (``oracle.basis``: i^{m-n} d^l_{nm}, Jacobi form).  The sum is exact for
 bandlimited input: |n - n'| <= B - 1 < N, and d^l d^{l'} has degree
-l + l' <= B - 1 = N - 1 in cos beta, which Clenshaw-Curtis on N nodes integrates.
+l + l' <= B - 1 <= N - 1 in cos beta, which Clenshaw-Curtis on N nodes integrates.
 
 Coefficient layout (integer degrees l = 0 .. (B-1)//2): the block of l starts at
 l (2l-1)(2l+1) / 3 and is row-major over m = -l..l (rows), n = -l..l (columns).
@@ -49,8 +50,8 @@ def triples(B: int):
 
 
 def grid(B: int):
-    """(alpha, beta, gamma, W), N = B nodes per angle."""
-    N = B
+    """(alpha, beta, gamma, W), N = 2B nodes per angle."""
+    N = 2 * B
     j = np.arange(N)
     alpha = -np.pi + 2 * np.pi * j / N
     gamma = -np.pi + 2 * np.pi * j / N
@@ -65,7 +66,7 @@ def _P(B, l, m, n, beta):
 
 def forward(B: int, f: np.ndarray) -> np.ndarray:
     """Coefficients of samples f ([k][j][l'], N^3 complex values)."""
-    N = B
+    N = 2 * B
     alpha, beta, gamma, W = grid(B)
     f = np.asarray(f, dtype=np.complex128).reshape(N, N, N)
     out = np.zeros(num_coeffs(B), dtype=np.complex128)
@@ -78,7 +79,7 @@ def forward(B: int, f: np.ndarray) -> np.ndarray:
 
 
 def _synth(B: int, c: np.ndarray, weights: np.ndarray, scale_2l1: bool) -> np.ndarray:
-    N = B
+    N = 2 * B
     alpha, beta, gamma, _ = grid(B)
     c = np.asarray(c, dtype=np.complex128).reshape(-1)
     out = np.zeros((N, N, N), dtype=np.complex128)
@@ -92,7 +93,7 @@ def _synth(B: int, c: np.ndarray, weights: np.ndarray, scale_2l1: bool) -> np.nd
 
 
 def inverse(B: int, c: np.ndarray) -> np.ndarray:
-    return _synth(B, c, np.ones(B), True)
+    return _synth(B, c, np.ones(2 * B), True)
 
 
 def adjoint(B: int, c: np.ndarray) -> np.ndarray:
