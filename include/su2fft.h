@@ -102,7 +102,18 @@ enum {
    * forward map).  SU2_C128 and SU2_C64 with B in {8, 16, 32, 64}, without
    * SU2_PLAN_TABLES_ON_THE_FLY; SU2_ERR_UNSUPPORTED otherwise.
    * su2_beta_forward_shifted does not accept real-signal plans. */
-  SU2_PLAN_REAL_SIGNALS = 2u
+  SU2_PLAN_REAL_SIGNALS = 2u,
+  /* SO(3) transform: the group the paper's grid (Definition 4.1, phi and psi
+   * both over [-pi, pi]) covers, on which only integer l occur.  Integer
+   * l with 2l < B, N = 2B periodic nodes per angle, alpha_j = -pi + 2 pi j / N,
+   * gamma_l = -pi + 2 pi l / N, beta_k and W_k as for SU(2) (normalisation
+   * 1/(8 pi^2), so W_k = w_k / (2 N^2) again).  Same definitions of forward,
+   * inverse and adjoint with t^l_{nm} for integer l, m, n.  Samples: N^3
+   * complex values as for SU(2); coefficients: blocks of integer l only, the
+   * block of l starting at l(2l-1)(2l+1)/3, row-major over m then n
+   * (su2_so3_num_coeffs, su2_so3_coeff_index).  SU2_C128 and SU2_C64 with B in
+   * {8, 16, 32, 64}, no other flag; SU2_ERR_UNSUPPORTED otherwise. */
+  SU2_PLAN_SO3 = 4u
 };
 
 /* su2_plan_create with options: `flags` is a bitwise or of SU2_PLAN_* values
@@ -168,6 +179,10 @@ su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, v
 int64_t su2_num_samples(int32_t B);                                    /* (2B)^3, or -1 if B < 1 */
 int64_t su2_num_coeffs(int32_t B);                                     /* B(B+1)(2B+1)/6, or -1   */
 int64_t su2_coeff_index(int32_t two_l, int32_t two_m, int32_t two_n);  /* -1 if not a valid triple */
+/* SO(3) plans (SU2_PLAN_SO3): coefficients per signal (integer l, 2l < B), and
+ * the flat index of fhat(l)_{mn} from plain integers l, m, n (-1 if invalid). */
+int64_t su2_so3_num_coeffs(int32_t B);
+int64_t su2_so3_coeff_index(int32_t l, int32_t m, int32_t n);
 
 /* Grid nodes and beta weights of the plan's quadrature (host arrays of 2B
  * doubles each; any pointer may be NULL to skip it).  w_beta receives W_k. */

@@ -64,17 +64,22 @@ def _P(B, l, m, n, beta):
     return np.array([basis(2 * l, 2 * m, 2 * n, b) for b in beta])
 
 
-def forward(B: int, f: np.ndarray) -> np.ndarray:
-    """Coefficients of samples f ([k][j][l'], N^3 complex values)."""
+def forward(B: int, f: np.ndarray, sel=None) -> np.ndarray:
+    """Coefficients of samples f ([k][j][l'], N^3 complex values): all of them,
+    or those at the flat indices `sel`."""
     N = 2 * B
     alpha, beta, gamma, W = grid(B)
     f = np.asarray(f, dtype=np.complex128).reshape(N, N, N)
-    out = np.zeros(num_coeffs(B), dtype=np.complex128)
-    for l, m, n in triples(B):
+    trip = list(triples(B))
+    if sel is not None:
+        by_index = {coeff_index(*t): t for t in trip}
+        trip = [by_index[int(i)] for i in sel]
+    out = np.zeros(len(trip), dtype=np.complex128)
+    for i, (l, m, n) in enumerate(trip):
         Ea = np.exp(1j * n * alpha)          # conj(e^{-i n alpha})
         Eg = np.exp(1j * m * gamma)
         Pc = np.conj(_P(B, l, m, n, beta))
-        out[coeff_index(l, m, n)] = np.sum(W[:, None, None] * Pc[:, None, None] * f * Ea[None, :, None] * Eg[None, None, :])
+        out[i] = np.sum(W[:, None, None] * Pc[:, None, None] * f * Ea[None, :, None] * Eg[None, None, :])
     return out
 
 
@@ -94,6 +99,20 @@ def _synth(B: int, c: np.ndarray, weights: np.ndarray, scale_2l1: bool) -> np.nd
 
 def inverse(B: int, c: np.ndarray) -> np.ndarray:
     return _synth(B, c, np.ones(2 * B), True)
+
+
+def inverse_at(B: int, c: np.ndarray, pts) -> np.ndarray:
+    """The inverse at the flat sample indices `pts` only (direct sum per point)."""
+    N = 2 * B
+    alpha, beta, gamma, _ = grid(B)
+    pts = np.asarray(pts)
+    k, j, l = pts // (N * N), (pts // N) % N, pts % N
+    c = np.asarray(c, dtype=np.complex128).reshape(-1)
+    out = np.zeros(pts.size, dtype=np.complex128)
+    for lv, m, n in triples(B):
+        P = np.array([basis(2 * lv, 2 * m, 2 * n, b) for b in beta[k]])
+        out += (2 * lv + 1) * c[coeff_index(lv, m, n)] * P * np.exp(-1j * (n * alpha[j] + m * gamma[l]))
+    return out
 
 
 def adjoint(B: int, c: np.ndarray) -> np.ndarray:

@@ -20,7 +20,7 @@ import os
 import torch
 
 __all__ = ["Plan", "MixedPlan", "SU2Transform", "SU2Error", "num_coeffs", "num_samples", "coeff_index",
-           "grid", "library_path", "C128", "C64", "C64_BF16X3"]
+           "so3_num_coeffs", "so3_coeff_index", "grid", "library_path", "C128", "C64", "C64_BF16X3"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsu2fft.so")
@@ -80,6 +80,10 @@ def _load():
     lib.su2_num_coeffs.restype = i64
     lib.su2_coeff_index.argtypes = [i32, i32, i32]
     lib.su2_coeff_index.restype = i64
+    lib.su2_so3_num_coeffs.argtypes = [i32]
+    lib.su2_so3_num_coeffs.restype = i64
+    lib.su2_so3_coeff_index.argtypes = [i32, i32, i32]
+    lib.su2_so3_coeff_index.restype = i64
     lib.su2_grid.argtypes = [i32, dp, dp, dp, dp]
     lib.su2_grid.restype = i32
     lib.su2_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -112,6 +116,16 @@ def num_coeffs(B: int) -> int:
 
 def coeff_index(two_l: int, two_m: int, two_n: int) -> int:
     return int(_load().su2_coeff_index(two_l, two_m, two_n))
+
+
+def so3_num_coeffs(B: int) -> int:
+    """Coefficients per signal of an SO(3) plan: integer l with 2l < B."""
+    return int(_load().su2_so3_num_coeffs(B))
+
+
+def so3_coeff_index(l: int, m: int, n: int) -> int:
+    """Flat index of fhat(l)_{mn} in an SO(3) plan's coefficient vector (plain integers)."""
+    return int(_load().su2_so3_coeff_index(l, m, n))
 
 
 def grid(B: int):
@@ -231,6 +245,7 @@ class _PlanBase:
 
 PLAN_TABLES_ON_THE_FLY = 1  # SU2_PLAN_TABLES_ON_THE_FLY
 PLAN_REAL_SIGNALS = 2       # SU2_PLAN_REAL_SIGNALS
+PLAN_SO3 = 4                # SU2_PLAN_SO3
 
 
 class Plan(_PlanBase):
@@ -243,14 +258,24 @@ class Plan(_PlanBase):
     real: real-signal plan (c128 / c64, B in {8, 16, 32, 64}): samples are
     float64 / float32 tensors; forward returns every coefficient, inverse and
     adjoint return the real part of the complex result (see
-    SU2_PLAN_REAL_SIGNALS)."""
+    SU2_PLAN_REAL_SIGNALS).
 
-    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored", real=False):
+    group: "su2" (default), or "so3" for the transform on SO(3) (c128 / c64,
+    B in {8, 16, 32, 64}, stored tables, complex samples): integer l with
+    2l < B on the same N = 2B grid with gamma over [-pi, pi) (see
+    SU2_PLAN_SO3); coefficients indexed by so3_coeff_index."""
+
+    def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored", real=False,
+                 group="su2"):
         if tables not in ("stored", "on_the_fly"):
             raise ValueError(f"tables must be 'stored' or 'on_the_fly', got {tables!r}")
-        flags = (PLAN_TABLES_ON_THE_FLY if tables == "on_the_fly" else 0) | (PLAN_REAL_SIGNALS if real else 0)
+        if group not in ("su2", "so3"):
+            raise ValueError(f"group must be 'su2' or 'so3', got {group!r}")
+        flags = ((PLAN_TABLES_ON_THE_FLY if tables == "on_the_fly" else 0) | (PLAN_REAL_SIGNALS if real else 0) |
+                 (PLAN_SO3 if group == "so3" else 0))
         self.tables = tables
         self.real = bool(real)
+        self.group = group
         lib = _load()
         self.B, self.batch = int(B), int(batch)
         self.dtype = _DTYPES[dtype]
@@ -260,7 +285,10 @@ class Plan(_PlanBase):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
         self.N = 2 * self.B
-        self.ncoef = num_coeffs(self.B) if self.B >= 1 else 0
+        if self.B < 1:
+            self.ncoef = 0
+        else:
+            self.ncoef = so3_num_coeffs(self.B) if group == "so3" else num_coeffs(self.B)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib.su2_plan_create_ex(self.B, self.batch, self.dtype, flags, ctypes.byref(h)),

@@ -231,12 +231,12 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
           const int l = rt * 16 + acc_row<T>(lane, r);
           if (l < L) {
             const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
-            const long long idx = coeff_index(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
+            const long long idx = coef_index_of(p.so3, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
             out[(cb0 + idx) * 2 + reim] = acc[i][rt][ct][r];
             if (p.real && (pi[i].tm != 0 || pi[i].tn != 0)) {
               // mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
               const T sg = (((pi[i].tm - pi[i].tn) / 2) & 1) ? T(-1) : T(1);
-              const long long mdx = coeff_index(pi[i].tl0 + 2 * l, -pi[i].tm, -pi[i].tn);
+              const long long mdx = coef_index_of(p.so3, pi[i].tl0 + 2 * l, -pi[i].tm, -pi[i].tn);
               out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
             }
           }
@@ -307,13 +307,13 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
         if (l < pi[q].L && bb < nb) {
           const int tl = pi[q].tl0 + 2 * l;
           const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
-          const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
+          const long long idx = coef_index_of(p.so3, tl, pi[q].tm, pi[q].tn);
           const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
           v = cin[(cb0 + idx) * 2 + reim];
           if (p.real) {
             // Hermitian part: (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
             const T sg = (((pi[q].tm - pi[q].tn) / 2) & 1) ? T(-1) : T(1);
-            const long long mdx = coeff_index(tl, -pi[q].tm, -pi[q].tn);
+            const long long mdx = coef_index_of(p.so3, tl, -pi[q].tm, -pi[q].tn);
             const T w = cin[(cb0 + mdx) * 2 + reim];
             v = T(0.5) * (v + (reim ? -sg : sg) * w);
           }

@@ -88,7 +88,7 @@ void clenshaw_curtis(int n, std::vector<long double>& w) {
 }
 
 void grid_ld(int B, std::vector<long double>& alpha, std::vector<long double>& beta, std::vector<long double>& gamma,
-             std::vector<long double>& W) {
+             std::vector<long double>& W, bool so3 = false) {
   const long double pi = 3.141592653589793238462643383279502884L;
   const int N = 2 * B;
   alpha.resize(N); beta.resize(N); gamma.resize(N);
@@ -98,7 +98,8 @@ void grid_ld(int B, std::vector<long double>& alpha, std::vector<long double>& b
   for (int i = 0; i < N; i++) {
     alpha[i] = -pi + 2.0L * pi * i / N;
     beta[i] = pi * i / (N - 1);
-    gamma[i] = -2.0L * pi + 4.0L * pi * i / N;
+    // SU(2): psi over [-2 pi, 2 pi); SO(3): the paper's [-pi, pi)
+    gamma[i] = so3 ? -pi + 2.0L * pi * i / N : -2.0L * pi + 4.0L * pi * i / N;
     W[i] = w[i] / (2.0L * N * N);
   }
 }
@@ -182,8 +183,21 @@ hipError_t upload_otf_scalars(su2_plan_s* pl, const std::vector<long double>& be
 
 su2_status_t build_plan(su2_plan_s* pl) {
   const int B = pl->B, N = 2 * B;
+  const bool so3 = pl->so3;
   pl->N = N;
-  pl->ncoef = (long long)B * (B + 1) * (2 * B + 1) / 6;
+  pl->ncoef = so3 ? (long long)((B - 1) / 2 + 1) * (2 * ((B - 1) / 2) + 1) * (2 * ((B - 1) / 2) + 3) / 3
+                  : (long long)B * (B + 1) * (2 * B + 1) / 6;
+  // ring bins of a pair (doubled indices): gamma frequency q, alpha frequency p,
+  // and the exponent e of the phase rho = i^e that the ring kernels apply.
+  //   SU(2): gamma_0 = -2 pi, alpha_0 = -pi: q = 2m, p = n (or n - 1/2 for
+  //          half-integer n, with the half-bin shift), rho = i^{n-m} (-1)^{2m} e^{-i pi n}
+  //   SO(3): gamma_0 = alpha_0 = -pi, integer m, n: q = m, p = n,
+  //          rho = i^{n-m} e^{-i pi m} e^{-i pi n} = i^{3n + m}
+  auto bin_q = [&](int tm) { return so3 ? imod(tm / 2, N) : imod(tm, N); };
+  auto bin_p = [&](int tn) { return so3 ? imod(tn / 2, N) : imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N); };
+  auto phase_e = [&](int tm, int tn) {
+    return so3 ? imod((3 * tn + tm) / 2, 4) : imod((tn - tm) / 2 + 2 * tm + 3 * tn, 4);
+  };
   const size_t cb = (pl->dtype == SU2_C128) ? 16 : 8;
 
   hipError_t e;
@@ -219,12 +233,14 @@ su2_status_t build_plan(su2_plan_s* pl) {
   for (int r = 0; r < split; r++) {
     pl->cls_begin[r] = (int)pairs.size();
     for (int tm = -(B - 1); tm <= B - 1; tm++) {
-      const int q = imod(tm, N);
+      if (so3 && (tm & 1)) continue;  // SO(3): integer m only
+      const int q = bin_q(tm);
       if (q % split != r) continue;
       const int qp = q / split;
       const int ccol = dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c);
       for (int tn = -(B - 1); tn <= B - 1; tn++) {
         if ((tn - tm) & 1) continue;
+        if (so3 && (tn & 1)) continue;
         PairInfo pi;
         pi.tm = tm; pi.tn = tn;
         pi.tl0 = abs(tm) > abs(tn) ? abs(tm) : abs(tn);
@@ -233,11 +249,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
         pi.lsum = 0;
         pi.coff = 0;
         pairs.push_back(pi);
-        const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
+        const int palpha = bin_p(tn);
         const int jrow = dif_position(palpha, N, pl->rad_n, pl->nrad_n);
         fftpos.push_back(jrow * pl->Nc + ccol);
-        // rho = i^{n-m} (-1)^{2m} e^{-i pi n} = i^{(tn-tm)/2 + 2 tm + 3 tn}
-        rho_e.push_back(imod((tn - tm) / 2 + 2 * tm + 3 * tn, 4));
+        rho_e.push_back(phase_e(tm, tn));
       }
     }
     pl->cls_end[r] = (int)pairs.size();
@@ -267,8 +282,8 @@ su2_status_t build_plan(su2_plan_s* pl) {
   for (int r = 0; r < FAST_ROUNDS; r++) { pl->rbeg[r] = pl->P; pl->rend[r] = 0; }
   for (int pidx = 0; pidx < pl->P; pidx++) {
     const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
-    const int q = imod(tm, N);
-    const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
+    const int q = bin_q(tm);
+    const int palpha = bin_p(tn);
     bins[(size_t)q * N + palpha] = (pidx << 2) | rho_e[pidx];
     const int r = q / (N / FAST_ROUNDS);
     pl->rbeg[r] = pidx < pl->rbeg[r] ? pidx : pl->rbeg[r];
@@ -317,7 +332,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
   for (int qp = 0; qp < pl->Nc; qp++) colq[dif_position(qp, pl->Nc, pl->rad_c, pl->nrad_c)] = qp;
 
   std::vector<long double> alpha, beta, gamma, W;
-  grid_ld(B, alpha, beta, gamma, W);
+  grid_ld(B, alpha, beta, gamma, W, so3);
   std::vector<long double> twr(2 * N), twi(2 * N);
   const long double pi_l = 3.141592653589793238462643383279502884L;
   for (int t = 0; t < 2 * N; t++) { twr[t] = cosl(pi_l * t / N); twi[t] = sinl(pi_l * t / N); }
@@ -530,11 +545,15 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   *out = nullptr;
   if (B < 1 || batch < 1) return SU2_ERR_INVALID_VALUE;
   if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
-  if (flags & ~(uint32_t)(SU2_PLAN_TABLES_ON_THE_FLY | SU2_PLAN_REAL_SIGNALS)) return SU2_ERR_INVALID_VALUE;
+  if (flags & ~(uint32_t)(SU2_PLAN_TABLES_ON_THE_FLY | SU2_PLAN_REAL_SIGNALS | SU2_PLAN_SO3))
+    return SU2_ERR_INVALID_VALUE;
   if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
   if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) && dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
+  const bool fast_b = B == 8 || B == 16 || B == 32 || B == 64;
   if ((flags & SU2_PLAN_REAL_SIGNALS) &&
-      (dtype == SU2_C64_BF16X3 || (flags & SU2_PLAN_TABLES_ON_THE_FLY) || (B != 8 && B != 16 && B != 32 && B != 64)))
+      (dtype == SU2_C64_BF16X3 || (flags & SU2_PLAN_TABLES_ON_THE_FLY) || !fast_b))
+    return SU2_ERR_UNSUPPORTED;
+  if ((flags & SU2_PLAN_SO3) && (dtype == SU2_C64_BF16X3 || (flags & ~(uint32_t)SU2_PLAN_SO3) || !fast_b))
     return SU2_ERR_UNSUPPORTED;
   su2_status_t st = check_device();
   if (st != SU2_OK) return st;
@@ -545,6 +564,7 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   pl->dtype = dtype;
   pl->otf = (flags & SU2_PLAN_TABLES_ON_THE_FLY) != 0;
   pl->real = (flags & SU2_PLAN_REAL_SIGNALS) != 0;
+  pl->so3 = (flags & SU2_PLAN_SO3) != 0;
   st = build_plan(pl);
   if (st != SU2_OK) {
     (void)hipDeviceSynchronize();
@@ -655,7 +675,7 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
 }
 
 su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream) {
-  if (!plan || plan->mixed || plan->real || !d_coeffs) return SU2_ERR_INVALID_VALUE;
+  if (!plan || plan->mixed || plan->real || plan->so3 || !d_coeffs) return SU2_ERR_INVALID_VALUE;
   if (depth != 1 && depth != 2) return SU2_ERR_INVALID_VALUE;
   if (depth == 2 && block != 2 && block != 4 && block != 8) return SU2_ERR_INVALID_VALUE;
   if (!shifted_supported(plan->B)) return SU2_ERR_UNSUPPORTED;
@@ -667,6 +687,17 @@ su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t bl
     e = launch_beta_forward_shifted<float>(otf_params<float>(plan, 0), (const cpx<float>*)plan->d_S,
                                            (cpx<float>*)d_coeffs, depth, block, (hipStream_t)stream);
   return e == hipSuccess ? SU2_OK : hip_fail(e);
+}
+
+int64_t su2_so3_num_coeffs(int32_t B) {
+  if (B < 1) return -1;
+  const int64_t L = (B - 1) / 2 + 1;  // integer degrees 0 .. L-1
+  return L * (2 * L - 1) * (2 * L + 1) / 3;
+}
+
+int64_t su2_so3_coeff_index(int32_t l, int32_t m, int32_t n) {
+  if (l < 0 || m < -l || m > l || n < -l || n > l) return -1;
+  return coef_index_of(1, 2 * l, 2 * m, 2 * n);
 }
 
 const char* su2_status_string(su2_status_t status) {

@@ -98,6 +98,7 @@ struct FastRingParams {
   // real signals (inverse): [q * N + p]: (source pair << 3) | (conjugate << 2) | e,
   // the source being the bin's own pair (2m >= 0) or its mirror (-m, -n)
   const int* bins_real;
+  int so3;            // SO(3) plan: integer n only, no half-bin shift on any q
 };
 
 // Parameters of the two-pass ring kernels (N = 256): the register-resident
@@ -126,7 +127,19 @@ struct BetaParams {
   // at (-m, -n), the inverse reads the Hermitian part of the coefficients
   int real;
   int tile0;                // first pair tile launched (grid x = ntiles - tile0)
+  int so3;                  // SO(3) plan: integer-l coefficient layout
 };
+
+// flat coefficient index of (2l, 2m, 2n): the SU(2) layout (2l-major blocks of
+// every l in {0, 1/2, 1, ...}) or, for SO(3) plans, blocks of integer l only
+// starting at l (2l-1)(2l+1) / 3
+__host__ __device__ inline long long coef_index_of(int so3, int tl, int tm, int tn) {
+  if (so3) {
+    const long long l = tl / 2, m = tm / 2, n = tn / 2;
+    return l * (2 * l - 1) * (2 * l + 1) / 3 + (m + l) * (2 * l + 1) + (n + l);
+  }
+  return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
+}
 
 // pair (m, n) of a real-signal plan whose values come from its mirror (-m, -n)
 __host__ __device__ inline bool mirrored_pair(int tm, int tn) { return tm < 0 || (tm == 0 && tn < 0); }

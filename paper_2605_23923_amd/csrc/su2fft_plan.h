@@ -39,6 +39,7 @@ struct su2_plan_s {
   // recurrence coefficients, node values
   bool otf = false;
   bool real = false;            // real-signal plan (pairs with 2m >= 0 carry the spectra)
+  bool so3 = false;             // SO(3) plan: integer l, gamma over [-pi, pi)
   int* d_bins_real = nullptr;
   double* d_seedc = nullptr;
   double* d_rcoef = nullptr;
@@ -114,6 +115,7 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   for (int i = 0; i < FAST_ROUNDS; i++) { r.rbeg[i] = pl->rbeg[i]; r.rend[i] = pl->rend[i]; }
   r.soff = pl->d_soff;
   r.bins_real = pl->d_bins_real;
+  r.so3 = pl->so3 ? 1 : 0;
   return r;
 }
 
@@ -156,6 +158,7 @@ BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
   b.coff = pl->d_coff;
   b.real = pl->real ? 1 : 0;
   b.tile0 = pl->real ? pl->rbeg[0] / PT : 0;
+  b.so3 = pl->so3 ? 1 : 0;
   return b;
 }
 

@@ -222,7 +222,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
   // ---- exchange 2 (by q slices) and phase 3: radix-N2 over j2 with the half-bin shift
   const int j1 = t % N1;
   // every phase-3 instance of this thread has q of the same parity: (t / N1) & 1
-  const int odd = (t / N1) & 1;
+  const int odd = p.so3 ? 0 : (t / N1) & 1;  // SO(3): integer n, no half-bin shift
   cpx<T> tw3[N2];  // e^{2 pi i (p2 + delta) j1 / N}
 #pragma unroll
   for (int p2 = 0; p2 < N2; p2++) tw3[p2] = tw[((2 * p2 + odd) * j1) % (2 * N)];
@@ -385,7 +385,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
   }
 
   // ---- phase 3': conj twiddle, radix-N2 over p2 -> j2, times e^{-2 pi i delta j2 / N2}
-  const int odd = (t / N1) & 1;
+  const int odd = p.so3 ? 0 : (t / N1) & 1;  // SO(3): integer n, no half-bin shift
   cpx<T> tw3[N2];
 #pragma unroll
   for (int pp = 0; pp < N2; pp++) tw3[pp] = tw[((2 * pp + odd) * j1) % (2 * N)];

@@ -9,7 +9,8 @@ Recipes (numpy PCG64 via ``default_rng(seed)``):
   var(l) = 1 ("flat") or (2l+1)^-2 ("decay"); optional blocks 2l in
   ``spike_tl`` scaled by ``spike_scale`` (small-l spikes);
 * samples: re and im i.i.d. uniform on [-1, 1] (not bandlimited).
-Coefficient layout: 2l-major blocks of (2l+1)^2 values (rows m, columns n).
+Coefficient layout: 2l-major blocks of (2l+1)^2 values (rows m, columns n);
+for the integer-degree (SO(3)) generator, l-major blocks of (2l+1)^2.
 """
 from __future__ import annotations
 
@@ -38,6 +39,26 @@ def coeffs(B: int, batch: int = 1, seed: int = 0, spectrum: str = "flat", spike_
     if len(spike_tl):
         mask = np.isin(tl, np.asarray(spike_tl))
         z[:, mask] *= spike_scale
+    return z.astype(dtype)
+
+
+def num_coeffs_so3(B: int) -> int:
+    """Integer degrees l with 2l < B: sum of (2l+1)^2."""
+    L = (B - 1) // 2 + 1
+    return L * (2 * L - 1) * (2 * L + 1) // 3
+
+
+def coeffs_so3(B: int, batch: int = 1, seed: int = 0, spectrum: str = "flat", dtype=np.complex128) -> np.ndarray:
+    """Coefficients of integer degrees only (l-major blocks of (2l+1)^2 values)."""
+    rng = np.random.default_rng(seed)
+    C = num_coeffs_so3(B)
+    z = (rng.standard_normal((batch, C)) + 1j * rng.standard_normal((batch, C))) / np.sqrt(2.0)
+    L = (B - 1) // 2 + 1
+    l = np.repeat(np.arange(L), (2 * np.arange(L) + 1) ** 2)
+    if spectrum == "decay":
+        z = z / (2.0 * l + 1.0)
+    elif spectrum != "flat":
+        raise ValueError(spectrum)
     return z.astype(dtype)
 
 

@@ -88,7 +88,7 @@ def test_argument_validation_before_any_device_call():
     # plan options: unknown bits, and on-the-fly tables with the split-BF16 mode
     lib.su2_plan_create_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_void_p)]
-    assert lib.su2_plan_create_ex(8, 1, 1, 4, ctypes.byref(h)) == 1
+    assert lib.su2_plan_create_ex(8, 1, 1, 8, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 1, 1, 0x80000000, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 1, 2, 1, ctypes.byref(h)) == 2
     assert lib.su2_plan_create_ex(0, 1, 1, 1, ctypes.byref(h)) == 1
@@ -97,6 +97,33 @@ def test_argument_validation_before_any_device_call():
     assert lib.su2_plan_create_ex(8, 1, 1, 3, ctypes.byref(h)) == 2
     assert lib.su2_plan_create_ex(24, 1, 1, 2, ctypes.byref(h)) == 2
     assert lib.su2_plan_create_ex(128, 1, 0, 2, ctypes.byref(h)) == 2
+    # SO(3): c128 / c64, B in {8, 16, 32, 64}, no other option
+    assert lib.su2_plan_create_ex(8, 1, 2, 4, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(8, 1, 1, 5, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(8, 1, 1, 6, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(24, 1, 0, 4, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(128, 1, 0, 4, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_ex(8, 0, 0, 4, ctypes.byref(h)) == 1
+
+
+def test_so3_layout_helpers_match_the_oracle():
+    """The SO(3) coefficient layout the library exports is the oracle's: the
+    same count for every B and the same flat index for every (l, m, n)."""
+    from oracle import so3 as oso3
+    lib = _lib()
+    lib.su2_so3_num_coeffs.argtypes = [ctypes.c_int32]
+    lib.su2_so3_num_coeffs.restype = ctypes.c_int64
+    lib.su2_so3_coeff_index.argtypes = [ctypes.c_int32] * 3
+    lib.su2_so3_coeff_index.restype = ctypes.c_int64
+    for B in range(1, 70):
+        assert lib.su2_so3_num_coeffs(B) == oso3.num_coeffs(B)
+    for l in range(0, 32):
+        for m in range(-l, l + 1):
+            for n in (-l, 0, l):
+                assert lib.su2_so3_coeff_index(l, m, n) == oso3.coeff_index(l, m, n)
+    assert lib.su2_so3_coeff_index(2, 3, 0) == -1
+    assert lib.su2_so3_coeff_index(-1, 0, 0) == -1
+    assert lib.su2_so3_num_coeffs(0) == -1
 
 
 def test_valid_plan_without_device_reports_no_device():
