@@ -37,10 +37,11 @@ STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_
 # a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf"
 # (Wigner-d values generated inside the contraction kernels instead of stored)
 # or "_real" (real signals: real samples, half of the pairs contracted)
+# or "_so3" (the transform on SO(3): integer degrees only, same grid size)
 
 
 def base_mode(mode: str) -> str:
-    for suffix in ("_otf", "_real"):
+    for suffix in ("_otf", "_real", "_so3"):
         if mode.endswith(suffix):
             return mode[: -len(suffix)]
     return mode
@@ -63,14 +64,22 @@ def retained_pairs(B: int) -> int:
     return 2 * B * B - 2 * B + 1
 
 
+def num_coeffs(B: int, mode: str) -> int:
+    """Coefficients (= table rows) per signal: every 2l < B, or integer l only for SO(3)."""
+    if mode.endswith("_so3"):
+        L = (B - 1) // 2 + 1
+        return L * (2 * L - 1) * (2 * L + 1) // 3
+    return B * (B + 1) * (2 * B + 1) // 6
+
+
 def table_bytes(B: int, mode: str) -> int:
     """Table bytes a contraction launch reads: the stored table, or the
     scalars of the generated one (3 recurrence coefficients per degree, a
     seed constant per pair, 3 values per node, all FP64)."""
-    C = B * (B + 1) * (2 * B + 1) // 6
+    C = num_coeffs(B, mode)
     if mode.endswith("_otf"):
         return 8 * (3 * C + retained_pairs(B) + 3 * 2 * B)
-    es = {"c128": 8, "c64": 4, "c64_bf16x3": 4}[mode]
+    es = {"c128": 8, "c64": 4, "c64_bf16x3": 4}[base_mode(mode)]
     return C * 2 * B * es
 
 
@@ -82,6 +91,15 @@ def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     ring = N ** 3 * cb                       # one signal's samples
     spec = retained_pairs(B) * N * cb        # one signal's retained ring spectra
     coef = C * cb
+    if mode.endswith("_so3"):
+        # every sample read; spectra of the (2L - 1)^2 integer pairs; the
+        # integer-degree coefficients and table rows
+        L = (B - 1) // 2 + 1
+        spec = (2 * L - 1) ** 2 * N * cb
+        coef = num_coeffs(B, mode) * cb
+        if stage.startswith("ring"):
+            return batch * (ring + spec)
+        return batch * (spec + coef) + table_bytes(B, mode)
     if mode.endswith("_real"):
         # real samples; spectra of the (P + 1) / 2 pairs with 2m >= 0 (mirrors
         # excluded); every coefficient written (forward) or read (inverse);
@@ -96,11 +114,10 @@ def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     return batch * (spec + coef) + table_bytes(B, mode)
 
 
-def useful_flops(stage: str, B: int, batch: int) -> float:
+def useful_flops(stage: str, B: int, batch: int, mode: str = "c64") -> float:
     """Useful real flops of a beta contraction: 4 per (l, m, n, k, signal)."""
     N = 2 * B
-    C = B * (B + 1) * (2 * B + 1) // 6
-    return 4.0 * N * C * batch if stage.startswith("beta") else 0.0
+    return 4.0 * N * num_coeffs(B, mode) * batch if stage.startswith("beta") else 0.0
 
 
 # sources of the kernels the B = 64 chain launches (the counter summaries in
@@ -138,9 +155,12 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
     import synth
 
     plan = su2.Plan(B, batch, base_mode(mode), tables="on_the_fly" if mode.endswith("_otf") else "stored",
-                    real=mode.endswith("_real"))
+                    real=mode.endswith("_real"), group="so3" if mode.endswith("_so3") else "su2")
     np_dt = "complex128" if base_mode(mode) == "c128" else "complex64"
-    c_host = synth.coeffs(B, batch, seed=2, spectrum="decay").astype(np_dt)
+    if mode.endswith("_so3"):
+        c_host = synth.coeffs_so3(B, batch, seed=2, spectrum="decay").astype(np_dt)
+    else:
+        c_host = synth.coeffs(B, batch, seed=2, spectrum="decay").astype(np_dt)
     coeffs = torch.from_numpy(c_host).to("cuda")
     samples = plan.inverse(coeffs)                       # input synthesis, not timed
     c_out = torch.empty_like(coeffs)
@@ -181,7 +201,8 @@ def run_mode(mode: str, B: int, batch: int, steps: int, warmup: int, timed_steps
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "stage_hbm_frac": {k: round(algorithmic_bytes(k, B, batch, mode) / (v * 1e-3) / HBM_PEAK, 4)
                            for k, v in stage_ms.items()},
-        "beta_mfma_useful_frac": {k: round(useful_flops(k, B, batch) / (stage_ms[k] * 1e-3) / MFMA_PEAK[base_mode(mode)], 5)
+        "beta_mfma_useful_frac": {k: round(useful_flops(k, B, batch, mode) / (stage_ms[k] * 1e-3) /
+                                           MFMA_PEAK[base_mode(mode)], 5)
                                   for k in STAGES if k.startswith("beta")},
     }
     plan.close()
@@ -348,10 +369,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="c64", choices=["c128", "c64", "c64_bf16x3"],
                     help="precision mode of the headline number")
-    ap.add_argument("--other-modes", default="c128,c64_bf16x3,c64_otf,c64_real",
+    ap.add_argument("--other-modes", default="c128,c64_bf16x3,c64_otf,c64_real,c64_so3",
                     help="comma-separated modes also timed and reported under 'modes' ('' for none); "
                          "'_otf' = Wigner-d values generated inside the contraction kernels, "
-                         "'_real' = real-signal plan")
+                         "'_real' = real-signal plan, '_so3' = SO(3) plan (integer degrees)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",

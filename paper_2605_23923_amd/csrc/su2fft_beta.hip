@@ -48,10 +48,6 @@ __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lan
 template <>
 __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
 
-__device__ __forceinline__ long long coeff_index(int tl, int tm, int tn) {
-  return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
-}
-
 template <class T>
 struct BetaCfg;
 template <>
@@ -212,33 +208,32 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
     }
   }
 
-  // epilogue: scatter into the 2l-major coefficient layout
+  // epilogue: scatter into the coefficient layout; the index of a degree is
+  // shared by the CT column groups of a lane
   T* out = reinterpret_cast<T*>(coeffs);
 #pragma unroll
   for (int i = 0; i < 2; i++) {
     const int L = pi[i].L;
-    if (L == 0) continue;
+    const bool mirror = p.real && (pi[i].tm != 0 || pi[i].tn != 0);
+    const T sg = (((pi[i].tm - pi[i].tn) / 2) & 1) ? T(-1) : T(1);
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++) {
-      if (rt * 16 >= L) continue;
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        if (bb >= nb) continue;
+      for (int r = 0; r < 4; r++) {
+        const int l = rt * 16 + acc_row<T>(lane, r);
+        if (l >= L) continue;
+        const int tl = pi[i].tl0 + 2 * l;
+        const int idx = coef_index_of(p.so3, tl, pi[i].tm, pi[i].tn);
+        const int mdx = coef_index_of(p.so3, tl, -pi[i].tm, -pi[i].tn);
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const int l = rt * 16 + acc_row<T>(lane, r);
-          if (l < L) {
+        for (int ct = 0; ct < CT; ct++) {
+          const int cc = ct * 16 + lrow;
+          const int bb = cc >> 1, reim = cc & 1;
+          if (bb < nb) {
             const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
-            const long long idx = coef_index_of(p.so3, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
             out[(cb0 + idx) * 2 + reim] = acc[i][rt][ct][r];
-            if (p.real && (pi[i].tm != 0 || pi[i].tn != 0)) {
-              // mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
-              const T sg = (((pi[i].tm - pi[i].tn) / 2) & 1) ? T(-1) : T(1);
-              const long long mdx = coef_index_of(p.so3, pi[i].tl0 + 2 * l, -pi[i].tm, -pi[i].tn);
-              out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
-            }
+            // real signals, mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
+            if (mirror) out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
           }
         }
       }

@@ -53,10 +53,6 @@ __device__ __forceinline__ void unpack8(const unsigned* w, u16x8& hi, u16x8& lo)
   }
 }
 
-__device__ __forceinline__ long long coeff_index_bf(int tl, int tm, int tn) {
-  return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
-}
-
 constexpr int XB_THREADS = 512;
 constexpr int XB_BT = 32;   // inverse: signals per workgroup (64 real columns)
 constexpr int XBF_BT = 16;  // forward: signals per workgroup (a 32-node S chunk is 64 KB)
@@ -197,7 +193,7 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
         for (int r = 0; r < 4; r++) {
           const int l = rt * 16 + 4 * lg + r;
           if (l < L) {
-            const long long idx = coeff_index_bf(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
+            const long long idx = coef_index_of(0, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
             out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
           }
         }
@@ -256,7 +252,7 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
           if (l < pi[q].L && bb < nb) {
             const int tl = pi[q].tl0 + 2 * l;
             const float sc = p.scale_mode == 0 ? float(tl + 1) : 1.f;
-            v[i] = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + coeff_index_bf(tl, pi[q].tm, pi[q].tn)) * 2 + reim];
+            v[i] = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + coef_index_of(0, tl, pi[q].tm, pi[q].tn)) * 2 + reim];
           }
         }
         split8(v, bhi[q][s][ct], blo[q][s][ct]);

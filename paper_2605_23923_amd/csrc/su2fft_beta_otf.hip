@@ -206,7 +206,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
         for (int r = 0; r < 4; r++) {
           const int l = rt * 16 + acc_row<T>(lane, r);
           if (l < L) {
-            const long long idx = coeff_index(pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
+            const long long idx = coef_index_of(0, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
             out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
           }
         }
@@ -260,7 +260,7 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
         T v = T(0);
         if (l < pi[q].L && bb < nb) {
           const int tl = pi[q].tl0 + 2 * l;
-          const long long idx = coeff_index(tl, pi[q].tm, pi[q].tn);
+          const long long idx = coef_index_of(0, tl, pi[q].tm, pi[q].tn);
           const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
           v = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim];
         }

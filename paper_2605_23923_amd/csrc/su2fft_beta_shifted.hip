@@ -111,7 +111,7 @@ __global__ __launch_bounds__(SH_THREADS) void beta_forward_shifted_kernel(const 
 #pragma unroll
   for (int l = 0; l < LMAX; l++) {
     if (l < L) {
-      const long long idx = coeff_index(q.tl0 + 2 * l, q.tm, q.tn);
+      const long long idx = coef_index_of(0, q.tl0 + 2 * l, q.tm, q.tn);
       out[(base + idx) * 2] = (T)accr[l];
       out[(base + idx) * 2 + 1] = (T)acci[l];
     }

@@ -133,12 +133,11 @@ struct BetaParams {
 // flat coefficient index of (2l, 2m, 2n): the SU(2) layout (2l-major blocks of
 // every l in {0, 1/2, 1, ...}) or, for SO(3) plans, blocks of integer l only
 // starting at l (2l-1)(2l+1) / 3
-__host__ __device__ inline long long coef_index_of(int so3, int tl, int tm, int tn) {
-  if (so3) {
-    const long long l = tl / 2, m = tm / 2, n = tn / 2;
-    return l * (2 * l - 1) * (2 * l + 1) / 3 + (m + l) * (2 * l + 1) + (n + l);
-  }
-  return (long long)tl * (tl + 1) * (2 * tl + 1) / 6 + (long long)((tm + tl) / 2) * (tl + 1) + (tn + tl) / 2;
+__host__ __device__ inline int coef_index_of(int so3, int tl, int tm, int tn) {
+  // inside a block both layouts are (2l+1) x (2l+1), row (tm + tl) / 2, column
+  // (tn + tl) / 2; only the block start differs (32-bit: at most 707264 values)
+  const int start = so3 ? (tl >> 1) * (tl - 1) * (tl + 1) / 3 : tl * (tl + 1) * (2 * tl + 1) / 6;
+  return start + ((tm + tl) >> 1) * (tl + 1) + ((tn + tl) >> 1);
 }
 
 // pair (m, n) of a real-signal plan whose values come from its mirror (-m, -n)
