@@ -22,6 +22,10 @@ namespace su2 {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// word 3 of a raw buffer resource on CDNA (gfx9 family): 32-bit data format,
+// no swizzle; range checking against word 2 (bytes) with stride 0
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
 
 template <class T>
 struct acc4;
@@ -211,6 +215,12 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   // epilogue: scatter into the coefficient layout; the index of a degree is
   // shared by the CT column groups of a lane
   T* out = reinterpret_cast<T*>(coeffs);
+  size_t cbase[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) {
+    const int bb = (ct * 16 + lrow) >> 1;
+    cbase[ct] = coef_offset(p.coff, b0 + (bb < nb ? bb : 0), p.ncoef);
+  }
 #pragma unroll
   for (int i = 0; i < 2; i++) {
     const int L = pi[i].L;
@@ -230,7 +240,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
           const int cc = ct * 16 + lrow;
           const int bb = cc >> 1, reim = cc & 1;
           if (bb < nb) {
-            const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
+            const size_t cb0 = cbase[ct];
             out[(cb0 + idx) * 2 + reim] = acc[i][rt][ct][r];
             // real signals, mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
             if (mirror) out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
@@ -277,63 +287,104 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   T* stage = reinterpret_cast<T*>(smem);
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
-  const T* cin = reinterpret_cast<const T*>(coeffs);
-  const PairInfo p0 = p.pairs[tile * PT];
-  const int lsum = p0.lsum;
-  const T* tabt = p.tab + p0.tab;
 
   PairInfo pi[2];
-  T bop[2][LQ][CT];
 #pragma unroll
   for (int q = 0; q < 2; q++) {
     pi[q] = p.pairs[tile * PT + wave + 8 * q];
     if (p.real && mirrored_pair(pi[q].tm, pi[q].tn)) pi[q].L = 0;
+  }
+
+  // B operands: the scaled coefficients of the wave's two pairs, gathered
+  // through LDS in rounds of 8 pairs x JC degrees.  In a round, thread
+  // (i, j) = (tid % 8, (tid / 8) % JC) loads coefficient (l_j, m_i, n_i) of
+  // its signals, so that 8 neighbouring lanes read the 8 pairs' values of one
+  // degree and signal, which lie side by side in the coefficient vector when
+  // the pairs share m (64 contiguous bytes instead of 8 scattered ones).
+  constexpr int J = 4 * LQ;                  // degrees held per pair
+  constexpr int JC = J < 16 ? J : 16;        // degrees per round
+  constexpr int CW = 2 * BT, CWP = CW + 16;  // columns (re, im per signal), padded row
+  constexpr int PS = JC * CWP + 4;           // LDS elements per pair
+  constexpr int RPT = BT * JC * 8 / INV_THREADS;  // coefficients loaded per thread and round
+  static_assert((BT * JC * 8) % INV_THREADS == 0 && 8 * PS <= 16 * NRS, "coefficient rounds");
+  T bop[2][LQ][CT];
+  {
+    T* cst = stage;
+    const int ci = tid & 7, cj = (tid >> 3) % JC, cb0 = tid / (8 * JC);
 #pragma unroll
-    for (int s = 0; s < LQ; s++) {
-      const int l = 4 * s + lk;
+    for (int q = 0; q < 2; q++) {
+      PairInfo pc = p.pairs[tile * PT + 8 * q + ci];
+      if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
+      const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        T v = T(0);
-        if (l < pi[q].L && bb < nb) {
-          const int tl = pi[q].tl0 + 2 * l;
-          const size_t cb0 = coef_offset(p.coff, b0 + bb, p.ncoef);
-          const long long idx = coef_index_of(p.so3, tl, pi[q].tm, pi[q].tn);
-          const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
-          v = cin[(cb0 + idx) * 2 + reim];
+      for (int jc0 = 0; jc0 < J; jc0 += JC) {
+        const int j = jc0 + cj;
+        const bool jok = j < pc.L;
+        const int tl = pc.tl0 + 2 * j;
+        const int idx = jok ? coef_index_of(p.so3, tl, pc.tm, pc.tn) : 0;
+        const int mdx = jok ? coef_index_of(p.so3, tl, -pc.tm, -pc.tn) : 0;
+        const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
+        cpx<T> v[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+          const int bb = cb0 + r * (INV_THREADS / (8 * JC));
+          const bool ok = jok && bb < nb;
+          const cpx<T>* c = coeffs + coef_offset(p.coff, b0 + (bb < nb ? bb : 0), p.ncoef);
+          v[r] = c[ok ? idx : 0];
           if (p.real) {
             // Hermitian part: (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
-            const T sg = (((pi[q].tm - pi[q].tn) / 2) & 1) ? T(-1) : T(1);
-            const long long mdx = coef_index_of(p.so3, tl, -pi[q].tm, -pi[q].tn);
-            const T w = cin[(cb0 + mdx) * 2 + reim];
-            v = T(0.5) * (v + (reim ? -sg : sg) * w);
+            const cpx<T> w = c[ok ? mdx : 0];
+            v[r].re = T(0.5) * (v[r].re + sg * w.re);
+            v[r].im = T(0.5) * (v[r].im - sg * w.im);
           }
-          v *= sc;
+          v[r].re = ok ? v[r].re * sc : T(0);
+          v[r].im = ok ? v[r].im * sc : T(0);
         }
-        bop[q][s][ct] = v;
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+          const int bb = cb0 + r * (INV_THREADS / (8 * JC));
+          T* d = cst + ci * PS + cj * CWP + 2 * bb;
+          d[0] = v[r].re;
+          d[1] = v[r].im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = jc0 / 4; s < (jc0 + JC) / 4; s++)
+#pragma unroll
+          for (int ct = 0; ct < CT; ct++)
+            bop[q][s][ct] = cst[wave * PS + (4 * s - jc0 + lk) * CWP + ct * 16 + lrow];
+        __syncthreads();
       }
     }
   }
 
-  // table values of a block of 16 nodes: A operands (row = node, col = degree)
+  // table values of a block of 16 nodes: A operands (row = node, col =
+  // degree), from the inverse-layout table: one load of 64 consecutive
+  // values per group of 4 degrees (zeros past N and L are stored there)
   T av[2][LQ];
-  auto fetch_a = [&](int k0) {
-    const int k = k0 + lrow;
+  auto fetch_a = [&](int kb) {
 #pragma unroll
     for (int q = 0; q < 2; q++) {
-      const int L = pi[q].L;
-      const T* trow = tabt + (size_t)k * lsum + pi[q].coff;
+      const T* src = p.tabi + pi[q].itab + (long long)kb * ((pi[q].L + 3) / 4) * 64 + lane;
 #pragma unroll
       for (int s = 0; s < LQ; s++) {
-        const int l = 4 * s + lk;
-        av[q][s] = (4 * s < L && l < L && k < N) ? trow[l] : T(0);
+        av[q][s] = T(0);
+        if (4 * s < pi[q].L) av[q][s] = src[64 * s];  // wave-uniform branch
       }
     }
   };
+  // the tile's slab of S as a buffer resource: stores of rows whose node or
+  // signal does not exist get an offset past the slab, and the hardware range
+  // check drops them; every lane issues the same unconditional stores
+  constexpr int VC = 16 / (int)sizeof(cpx<T>);
+  constexpr int NV = 16 * BT * (PT / VC);  // 16-byte stores per block of 16 nodes
+  static_assert(NV % INV_THREADS == 0, "store split");
+  const long long slab = (long long)N * p.batch * PT;
+  const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<T>)), BUFFER_RSRC_WORD3);
   fetch_a(0);
   for (int k0 = 0; k0 < N; k0 += 16) {
 #pragma unroll
@@ -360,22 +411,29 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
         for (int r = 0; r < 4; r++) stage[acc_row<T>(lane, r) * NRS + bb * PB + 2 * pp + reim] = acc[ct][r];
       }
     }
-    if (k0 + 16 < N) fetch_a(k0 + 16);
+    if (k0 + 16 < N) fetch_a(k0 / 16 + 1);
     __syncthreads();
-    // write the block: rows (node, signal) of PT pairs, 16 bytes per thread-store
-    constexpr int VC = 16 / (int)sizeof(cpx<T>);
-    for (int v = tid; v < 16 * BT * (PT / VC); v += INV_THREADS) {
+    // write the block: rows (node, signal) of PT pairs, 16 bytes per store.
+    // The thread index passes through an empty asm statement so that the
+    // store addresses are formed here rather than hoisted out of the node
+    // loop, where they would hold registers throughout.
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+#pragma unroll
+    for (int i = 0; i < NV / INV_THREADS; i++) {
+      const int v = tq + INV_THREADS * i;
       const int row = v / (PT / VC), pv = v - row * (PT / VC);
       const int kk = row / BT, bb = row - kk * BT;
       const int k = k0 + kk;
-      if (k < N && bb < nb) {
-        const T* src = stage + kk * NRS + bb * PB + 2 * pv * VC;
-        float4 w;
-        T* wd = reinterpret_cast<T*>(&w);
+      const T* src = stage + kk * NRS + bb * PB + 2 * pv * VC;
+      u32x4 w;
+      T* wd = reinterpret_cast<T*>(&w);
 #pragma unroll
-        for (int q = 0; q < 2 * VC; q++) wd[q] = src[q];
-        *reinterpret_cast<float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC) = w;
-      }
+      for (int e = 0; e < 2 * VC; e++) wd[e] = src[e];
+      const unsigned off = (k < N && bb < nb)
+                               ? (unsigned)((((long long)k * p.batch + b0 + bb) * PT + pv * VC) * (long long)sizeof(cpx<T>))
+                               : 0x80000000u;
+      __builtin_amdgcn_raw_buffer_store_b128(w, srsrc, off, 0, 0);
     }
     __syncthreads();
   }

@@ -248,6 +248,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
         pi.tab = 0;
         pi.lsum = 0;
         pi.coff = 0;
+        pi.itab = 0;
         pairs.push_back(pi);
         const int palpha = bin_p(tn);
         const int jrow = dif_position(palpha, N, pl->rad_n, pl->nrad_n);
@@ -262,7 +263,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
   pl->ntiles = pl->P_pad / PT;
   while ((int)pairs.size() < pl->P_pad) {
     PairInfo pi;
-    pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0; pi.lsum = 0; pi.coff = 0;
+    pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0; pi.lsum = 0; pi.coff = 0; pi.itab = 0;
     pairs.push_back(pi);
     fftpos.push_back(0);
     rho_e.push_back(0);
@@ -275,6 +276,9 @@ su2_status_t build_plan(su2_plan_s* pl) {
     tab += (long long)N * lsum;
   }
   pl->tab_elems = tab;
+  long long itab = 0;
+  for (auto& pi : pairs) { pi.itab = itab; itab += inverse_table_elems(pi.L, N); }
+  pl->itab_elems = itab;
   pl->h_pairs = pairs;
   // bin -> pair map for the register-resident ring kernels, and the pair range
   // of each slice of q values they process together
@@ -372,14 +376,30 @@ su2_status_t build_plan(su2_plan_s* pl) {
   // shifted-recurrence contraction use them (a few MB)
   if ((e = upload_otf_scalars(pl, beta)) != hipSuccess) return hip_fail(e);
   if (!pl->otf) {
-    // tables are padded by 64 bytes: the contraction kernels read whole 16-byte vectors
+    // tables are padded by 64 bytes of zeros: the contraction kernels read
+    // whole 16-byte vectors, and up to 3 elements past a pair's row segment
+    // (multiplied by zero operands)
     if ((e = pl->alloc((void**)&pl->d_tab64, sizeof(double) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemset(pl->d_tab64 + tab, 0, 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_dtable(B, N, pl->P_pad, pl->d_pairs, d_beta, pl->d_tab64, 0)) != hipSuccess) return hip_fail(e);
+    // the inverse-layout copy read by the inverse and adjoint contractions
+    if (pl->dtype == SU2_C128) {
+      if ((e = pl->alloc((void**)&pl->d_tabi64, sizeof(double) * (size_t)pl->itab_elems + 64)) != hipSuccess)
+        return hip_fail(e);
+      if ((e = launch_inverse_table<double>(N, pl->P_pad, pl->d_pairs, pl->d_tab64, pl->d_tabi64, 0)) != hipSuccess)
+        return hip_fail(e);
+    } else if (pl->dtype == SU2_C64) {
+      if ((e = pl->alloc((void**)&pl->d_tabi32, sizeof(float) * (size_t)pl->itab_elems + 64)) != hipSuccess)
+        return hip_fail(e);
+      if ((e = launch_inverse_table<float>(N, pl->P_pad, pl->d_pairs, pl->d_tab64, pl->d_tabi32, 0)) != hipSuccess)
+        return hip_fail(e);
+    }
   }
   if (pl->otf) {
     // no stored table
   } else if (pl->dtype == SU2_C64) {
     if ((e = pl->alloc((void**)&pl->d_tab32, sizeof(float) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemset(pl->d_tab32 + tab, 0, 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_round_table_f32(tab, pl->d_tab64, pl->d_tab32, 0)) != hipSuccess) return hip_fail(e);
   } else if (pl->dtype == SU2_C64_BF16X3) {
     if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);

@@ -52,7 +52,18 @@ struct PairInfo {
   long long tab;  // offset of the pair's tile block (in table elements)
   int lsum;       // row length of the tile block
   int coff;       // column offset of this pair inside a row
+  long long itab; // offset of the pair's values in the inverse-layout table (elements)
 };
+
+// Inverse-layout table: the values one wave of the inverse contraction loads
+// as matrix-core A operands, in lane order.  For a pair with L degrees,
+// S = ceil(L / 4) groups of 4 degrees and NB = ceil(N / 16) blocks of 16
+// nodes: element ((kb * S + s) * 64 + lane) holds d^l(beta_k) with
+// k = 16 kb + lane % 16 and l = 4 s + lane / 16 (zero past N or L), so one
+// load instruction reads 64 consecutive values.
+__host__ __device__ inline long long inverse_table_elems(int L, int N) {
+  return (long long)((L + 3) / 4) * ((N + 15) / 16) * 64;
+}
 
 // Parameters of the ring-FFT kernels (one workgroup per ring (signal, k)).
 template <class T>
@@ -120,6 +131,7 @@ struct BetaParams {
   long long ncoef;          // coefficients per signal
   const PairInfo* pairs;
   const T* tab;             // Wigner-d table, tile-major (see PairInfo)
+  const T* tabi;            // the same values in the inverse layout (see PairInfo::itab)
   int scale_mode;           // inverse: 0 -> (2l+1) weights, 1 -> none (adjoint)
   const long long* coff;    // per signal: offset of its coefficients (complex values), or null: b * ncoef
   // real signals: only pairs with 2m > 0, or 2m = 0 and 2n >= 0, are contracted;
@@ -256,6 +268,8 @@ hipError_t launch_ring_inverse_large(const LargeRingParams<T>& p, const cpx<T>* 
 hipError_t launch_dtable(int B, int N, int npairs, const PairInfo* pairs, const double* beta, double* tab64,
                          hipStream_t s);
 hipError_t launch_round_table_f32(long long n, const double* src, float* dst, hipStream_t s);
+template <class T>
+hipError_t launch_inverse_table(int N, int npairs, const PairInfo* pairs, const double* tab64, T* dst, hipStream_t s);
 hipError_t launch_split_table_bf16(long long n, const double* src, bf16x2_t* dst, hipStream_t s);
 
 }  // namespace su2

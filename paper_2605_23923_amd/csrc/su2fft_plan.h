@@ -4,6 +4,7 @@
 
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "su2fft_internal.h"
@@ -27,6 +28,9 @@ struct su2_plan_s {
   PairInfo* d_pairs = nullptr;
   double* d_tab64 = nullptr;
   float* d_tab32 = nullptr;
+  double* d_tabi64 = nullptr;   // inverse-layout copies (c128 / c64 plans with stored tables)
+  float* d_tabi32 = nullptr;
+  long long itab_elems = 0;
   bf16x2_t* d_tabbf = nullptr;
   unsigned* d_tabbf_fwd = nullptr;
   int* d_fftpos = nullptr;
@@ -154,6 +158,8 @@ BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
   b.ncoef = pl->ncoef;
   b.pairs = pl->d_pairs;
   b.tab = tab;
+  b.tabi = std::is_same<T, double>::value ? reinterpret_cast<const T*>(pl->d_tabi64)
+                                          : reinterpret_cast<const T*>(pl->d_tabi32);
   b.scale_mode = scale_mode;
   b.coff = pl->d_coff;
   b.real = pl->real ? 1 : 0;

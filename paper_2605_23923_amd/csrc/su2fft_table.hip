@@ -105,6 +105,32 @@ hipError_t launch_round_table_f32(long long n, const double* src, float* dst, hi
   return hipGetLastError();
 }
 
+// inverse layout (see PairInfo::itab): one workgroup per pair, values
+// rounded from the FP64 table as the tile-major copies are
+template <class T>
+__global__ void inverse_table_kernel(int N, const PairInfo* __restrict__ pairs, const double* __restrict__ tab,
+                                     T* __restrict__ dst) {
+  const PairInfo pi = pairs[blockIdx.x];
+  const int S = (pi.L + 3) / 4;
+  const long long n = inverse_table_elems(pi.L, N);
+  for (long long e = threadIdx.x; e < n; e += blockDim.x) {
+    const int lane = (int)(e & 63);
+    const long long g = e >> 6;
+    const int kb = (int)(g / S), s = (int)(g - (long long)kb * S);
+    const int k = 16 * kb + (lane & 15), l = 4 * s + (lane >> 4);
+    const double v = (k < N && l < pi.L) ? tab[pi.tab + (long long)k * pi.lsum + pi.coff + l] : 0.0;
+    dst[pi.itab + e] = (T)v;
+  }
+}
+
+template <class T>
+hipError_t launch_inverse_table(int N, int npairs, const PairInfo* pairs, const double* tab64, T* dst, hipStream_t s) {
+  hipLaunchKernelGGL(inverse_table_kernel<T>, dim3(npairs), dim3(256), 0, s, N, pairs, tab64, dst);
+  return hipGetLastError();
+}
+template hipError_t launch_inverse_table<float>(int, int, const PairInfo*, const double*, float*, hipStream_t);
+template hipError_t launch_inverse_table<double>(int, int, const PairInfo*, const double*, double*, hipStream_t);
+
 hipError_t launch_split_table_bf16(long long n, const double* src, bf16x2_t* dst, hipStream_t s) {
   hipLaunchKernelGGL(split_bf16_kernel, dim3(1024), dim3(256), 0, s, n, src, dst);
   return hipGetLastError();
