@@ -212,38 +212,57 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
     }
   }
 
-  // epilogue: scatter into the coefficient layout; the index of a degree is
-  // shared by the CT column groups of a lane
-  T* out = reinterpret_cast<T*>(coeffs);
-  size_t cbase[CT];
-#pragma unroll
-  for (int ct = 0; ct < CT; ct++) {
-    const int bb = (ct * 16 + lrow) >> 1;
-    cbase[ct] = coef_offset(p.coff, b0 + (bb < nb ? bb : 0), p.ncoef);
-  }
+  // epilogue: the coefficients leave through LDS in rounds of 8 pairs x 16
+  // degrees.  Each wave parks one row tile of its pair there; then thread
+  // (i, j) = (tid % 8, (tid / 8) % 16) writes coefficient (l_j, m_i, n_i) of
+  // its signals, so that 8 neighbouring lanes write the 8 pairs' values of
+  // one degree and signal, side by side in the coefficient vector when the
+  // pairs share m (64 contiguous bytes instead of 4-byte pieces).
+  constexpr int CW = 2 * BT, CWP = CW + 16;  // columns (re, im per signal), padded row
+  constexpr int PS = 16 * CWP + 4;           // LDS elements per pair
+  constexpr int RPT = BT * 16 * 8 / FWD_THREADS;
+  static_assert((BT * 16 * 8) % FWD_THREADS == 0 && (size_t)8 * PS * sizeof(T) <= FwdGeom<T, RTMAX>::SMEM,
+                "coefficient rounds");
+  T* cst = reinterpret_cast<T*>(smem);
+  const int ci = tid & 7, cj = (tid >> 3) & 15, cb0 = tid >> 7;
 #pragma unroll
   for (int i = 0; i < 2; i++) {
-    const int L = pi[i].L;
-    const bool mirror = p.real && (pi[i].tm != 0 || pi[i].tn != 0);
-    const T sg = (((pi[i].tm - pi[i].tn) / 2) & 1) ? T(-1) : T(1);
+    PairInfo pc = p.pairs[tile * PT + 8 * i + ci];
+    if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
+    const bool mirror = p.real && (pc.tm != 0 || pc.tn != 0);
+    const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++) {
+      __syncthreads();  // LDS free (main loop, or the previous round's reads)
+      if (rt * 16 < pi[i].L) {
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int l = rt * 16 + acc_row<T>(lane, r);
-        if (l >= L) continue;
-        const int tl = pi[i].tl0 + 2 * l;
-        const int idx = coef_index_of(p.so3, tl, pi[i].tm, pi[i].tn);
-        const int mdx = coef_index_of(p.so3, tl, -pi[i].tm, -pi[i].tn);
+        for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          const int cc = ct * 16 + lrow;
-          const int bb = cc >> 1, reim = cc & 1;
+          for (int r = 0; r < 4; r++) cst[wave * PS + acc_row<T>(lane, r) * CWP + ct * 16 + lrow] = acc[i][rt][ct][r];
+      }
+      __syncthreads();
+      const int j = rt * 16 + cj;
+      if (j < pc.L) {
+        const int tl = pc.tl0 + 2 * j;
+        const int idx = coef_index_of(p.so3, tl, pc.tm, pc.tn);
+        const int mdx = coef_index_of(p.so3, tl, -pc.tm, -pc.tn);
+#pragma unroll
+        for (int r = 0; r < RPT; r++) {
+          const int bb = cb0 + r * (FWD_THREADS / 128);
           if (bb < nb) {
-            const size_t cb0 = cbase[ct];
-            out[(cb0 + idx) * 2 + reim] = acc[i][rt][ct][r];
+            const T* src = cst + ci * PS + cj * CWP + 2 * bb;
+            cpx<T> v;
+            v.re = src[0];
+            v.im = src[1];
+            cpx<T>* c = coeffs + coef_offset(p.coff, b0 + bb, p.ncoef);
+            c[idx] = v;
             // real signals, mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
-            if (mirror) out[(cb0 + mdx) * 2 + reim] = (reim ? -sg : sg) * acc[i][rt][ct][r];
+            if (mirror) {
+              cpx<T> w;
+              w.re = sg * v.re;
+              w.im = -sg * v.im;
+              c[mdx] = w;
+            }
           }
         }
       }
