@@ -382,16 +382,20 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
 
   // table values of a block of 16 nodes: A operands (row = node, col =
   // degree), from the inverse-layout table: one load of 64 consecutive
-  // values per group of 4 degrees (zeros past N and L are stored there)
-  T av[2][LQ];
-  auto fetch_a = [&](int kb) {
+  // values per group of 4 degrees (zeros past N and L are stored there).
+  // The next block's values are requested before this block's products, so
+  // they have the whole block (products, staging, stores) to arrive; where
+  // two register sets do not fit (FP64 with 64 degrees), after the products.
+  constexpr bool EARLY = sizeof(T) * LQ <= 64;
+  T av[2][LQ], avn[2][LQ];
+  auto fetch_a = [&](T (&dst)[2][LQ], int kb) {
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const T* src = p.tabi + pi[q].itab + (long long)kb * ((pi[q].L + 3) / 4) * 64 + lane;
 #pragma unroll
       for (int s = 0; s < LQ; s++) {
-        av[q][s] = T(0);
-        if (4 * s < pi[q].L) av[q][s] = src[64 * s];  // wave-uniform branch
+        dst[q][s] = T(0);
+        if (4 * s < pi[q].L) dst[q][s] = src[64 * s];  // wave-uniform branch
       }
     }
   };
@@ -404,8 +408,10 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   const long long slab = (long long)N * p.batch * PT;
   const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<T>)), BUFFER_RSRC_WORD3);
-  fetch_a(0);
+  fetch_a(av, 0);
   for (int k0 = 0; k0 < N; k0 += 16) {
+    if constexpr (EARLY)
+      if (k0 + 16 < N) fetch_a(avn, k0 / 16 + 1);
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const int L = pi[q].L;
@@ -430,7 +436,8 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
         for (int r = 0; r < 4; r++) stage[acc_row<T>(lane, r) * NRS + bb * PB + 2 * pp + reim] = acc[ct][r];
       }
     }
-    if (k0 + 16 < N) fetch_a(k0 / 16 + 1);
+    if constexpr (!EARLY)
+      if (k0 + 16 < N) fetch_a(av, k0 / 16 + 1);
     __syncthreads();
     // write the block: rows (node, signal) of PT pairs, 16 bytes per store.
     // The thread index passes through an empty asm statement so that the
@@ -455,6 +462,12 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
       __builtin_amdgcn_raw_buffer_store_b128(w, srsrc, off, 0, 0);
     }
     __syncthreads();
+    if constexpr (EARLY) {
+#pragma unroll
+      for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int s = 0; s < LQ; s++) av[q][s] = avn[q][s];
+    }
   }
 }
 
