@@ -56,7 +56,10 @@ extern "C" {
 typedef enum {
   SU2_OK = 0,
   SU2_ERR_INVALID_VALUE = 1, /* null pointer, B < 1, batch < 1, unknown dtype, null plan */
-  SU2_ERR_UNSUPPORTED = 2,   /* B > 128, or N = 2B not of the form 2^a 3^b */
+  SU2_ERR_UNSUPPORTED = 2,   /* B > 128, N = 2B not of the form 2^a 3^b, or a batch so
+                                large that N x batch x 16 ring-spectrum values of one
+                                pair tile exceed 2^31 - 1 bytes (batch > 131072 at
+                                B = 64 in SU2_C64) */
   SU2_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed; nothing is leaked */
   SU2_ERR_HIP = 4,           /* a HIP call or kernel launch failed (see su2_last_hip_error) */
   SU2_ERR_NO_DEVICE = 5      /* no usable GPU */

@@ -185,6 +185,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
   const int B = pl->B, N = 2 * B;
   const bool so3 = pl->so3;
   pl->N = N;
+  // the contraction kernels address one pair tile's ring spectra (N nodes x
+  // batch x 16 pairs) with 32-bit byte offsets
+  if ((size_t)N * (size_t)pl->batch * PT * (pl->dtype == SU2_C128 ? 16 : 8) > (size_t)INT32_MAX)
+    return SU2_ERR_UNSUPPORTED;
   pl->ncoef = so3 ? (long long)((B - 1) / 2 + 1) * (2 * ((B - 1) / 2) + 1) * (2 * ((B - 1) / 2) + 3) / 3
                   : (long long)B * (B + 1) * (2 * B + 1) / 6;
   // ring bins of a pair (doubled indices): gamma frequency q, alpha frequency p,
@@ -568,6 +572,8 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   if (flags & ~(uint32_t)(SU2_PLAN_TABLES_ON_THE_FLY | SU2_PLAN_REAL_SIGNALS | SU2_PLAN_SO3))
     return SU2_ERR_INVALID_VALUE;
   if (B > 128 || !only_2_3(2 * B)) return SU2_ERR_UNSUPPORTED;
+  if ((size_t)2 * B * (size_t)batch * PT * (dtype == SU2_C128 ? 16 : 8) > (size_t)INT32_MAX)
+    return SU2_ERR_UNSUPPORTED;  // see build_plan
   if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) && dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
   const bool fast_b = B == 8 || B == 16 || B == 32 || B == 64;
   if ((flags & SU2_PLAN_REAL_SIGNALS) &&

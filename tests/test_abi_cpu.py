@@ -73,6 +73,8 @@ def test_argument_validation_before_any_device_call():
     assert _create(8, 1, 7)[0] == 1           # unknown dtype
     assert _create(5, 1, 0)[0] == 2           # N = 10 is not 2^a 3^b
     assert _create(129, 1, 0)[0] == 2         # beyond the largest bandlimit
+    assert _create(64, 131073, 1)[0] == 2     # one pair tile's spectra beyond 32-bit offsets
+    assert _create(8, 524289, 0)[0] == 2
     assert lib.su2_plan_create(8, 1, 0, None) == 1
     assert lib.su2_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
     assert lib.su2_inverse(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
