@@ -63,6 +63,102 @@ struct BetaCfg<double> {
   static constexpr int BT = 16;  // 32 real columns
 };
 
+// ---- coefficients through LDS ----
+//
+// A wave's matrix-core operands (inverse) or results (forward) belong to two
+// pairs and all the workgroup's signals; read or written straight from the
+// coefficient vectors, every lane would touch its own 4- or 8-byte piece of a
+// different cache line.  Instead the workgroup moves them through LDS in
+// rounds of 8 pairs (i = 0..7: pairs 8 h + i of the tile) x JC degree indices
+// j, with thread (i, j) = (tid % 8, (tid / 8) % JC) handling coefficient
+// (l_j, m_i, n_i) of its signals: 8 neighbouring lanes cover the 8 pairs'
+// values of one degree and signal, which lie side by side in the coefficient
+// vector when the pairs share m.  LDS layout of a round:
+// cst[i * PS + (j - j0) * CWP + 2 * signal + (re, im)].
+template <class T, int BT, int JC, int NTHR>
+struct CoefRound {
+  static constexpr int CW = 2 * BT, CWP = CW + 16, PS = JC * CWP + 4;
+  static constexpr int STEP = NTHR / (8 * JC);  // signals between a thread's coefficients
+  static constexpr int RPT = BT / STEP;         // coefficients per thread and round
+  static constexpr size_t ELEMS = (size_t)8 * PS;
+  static_assert(NTHR % (8 * JC) == 0 && BT % STEP == 0, "coefficient round split");
+
+  // inverse: the scaled coefficients (2l+1 or 1) of pairs 8h..8h+7, degree
+  // indices j0..j0+JC-1, into LDS (zero past L or the batch; the Hermitian
+  // part for real plans).  Ends with a barrier: the round is readable.
+  __device__ static void gather(const cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int h, int j0,
+                                int b0, int nb, T* cst, int tid) {
+    const int ci = tid & 7, cj = (tid / 8) % JC, cb0 = tid / (8 * JC);
+    PairInfo pc = p.pairs[tile * PT + 8 * h + ci];
+    if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
+    const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
+    const int j = j0 + cj;
+    const bool jok = j < pc.L;
+    const int tl = pc.tl0 + 2 * j;
+    const int idx = jok ? coef_index_of(p.so3, tl, pc.tm, pc.tn) : 0;
+    const int mdx = jok ? coef_index_of(p.so3, tl, -pc.tm, -pc.tn) : 0;
+    const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
+    cpx<T> v[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {  // every load issued unconditionally, masked afterwards
+      const int bb = cb0 + r * STEP;
+      const bool ok = jok && bb < nb;
+      const cpx<T>* c = coeffs + coef_offset(p.coff, b0 + (bb < nb ? bb : 0), p.ncoef);
+      v[r] = c[ok ? idx : 0];
+      if (p.real) {
+        // Hermitian part: (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
+        const cpx<T> w = c[ok ? mdx : 0];
+        v[r].re = T(0.5) * (v[r].re + sg * w.re);
+        v[r].im = T(0.5) * (v[r].im - sg * w.im);
+      }
+      v[r].re = ok ? v[r].re * sc : T(0);
+      v[r].im = ok ? v[r].im * sc : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+      T* d = cst + ci * PS + cj * CWP + 2 * (cb0 + r * STEP);
+      d[0] = v[r].re;
+      d[1] = v[r].im;
+    }
+    __syncthreads();
+  }
+
+  // forward: the sums parked in LDS for pairs 8h..8h+7, degree indices
+  // j0..j0+JC-1, out to the coefficient vectors (with the mirror
+  // (-1)^{m-n} conj(fhat) at (-m, -n) for real plans).
+  __device__ static void store(cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int h, int j0, int b0,
+                               int nb, const T* cst, int tid) {
+    const int ci = tid & 7, cj = (tid / 8) % JC, cb0 = tid / (8 * JC);
+    PairInfo pc = p.pairs[tile * PT + 8 * h + ci];
+    if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
+    const int j = j0 + cj;
+    if (j >= pc.L) return;
+    const bool mirror = p.real && (pc.tm != 0 || pc.tn != 0);
+    const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
+    const int tl = pc.tl0 + 2 * j;
+    const int idx = coef_index_of(p.so3, tl, pc.tm, pc.tn);
+    const int mdx = coef_index_of(p.so3, tl, -pc.tm, -pc.tn);
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+      const int bb = cb0 + r * STEP;
+      if (bb < nb) {
+        const T* src = cst + ci * PS + cj * CWP + 2 * bb;
+        cpx<T> v;
+        v.re = src[0];
+        v.im = src[1];
+        cpx<T>* c = coeffs + coef_offset(p.coff, b0 + bb, p.ncoef);
+        c[idx] = v;
+        if (mirror) {
+          cpx<T> w;
+          w.re = sg * v.re;
+          w.im = -sg * v.im;
+          c[mdx] = w;
+        }
+      }
+    }
+  }
+};
+
 // Forward contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
 // pairs w and w + 8 of the tile.  The workgroup streams the tile's S slab and
 // table rows through LDS in chunks of KC nodes, fetching chunk c+1 into
@@ -212,60 +308,25 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
     }
   }
 
-  // epilogue: the coefficients leave through LDS in rounds of 8 pairs x 16
-  // degrees.  Each wave parks one row tile of its pair there; then thread
-  // (i, j) = (tid % 8, (tid / 8) % 16) writes coefficient (l_j, m_i, n_i) of
-  // its signals, so that 8 neighbouring lanes write the 8 pairs' values of
-  // one degree and signal, side by side in the coefficient vector when the
-  // pairs share m (64 contiguous bytes instead of 4-byte pieces).
-  constexpr int CW = 2 * BT, CWP = CW + 16;  // columns (re, im per signal), padded row
-  constexpr int PS = 16 * CWP + 4;           // LDS elements per pair
-  constexpr int RPT = BT * 16 * 8 / FWD_THREADS;
-  static_assert((BT * 16 * 8) % FWD_THREADS == 0 && (size_t)8 * PS * sizeof(T) <= FwdGeom<T, RTMAX>::SMEM,
-                "coefficient rounds");
+  // epilogue: the coefficients leave through LDS (CoefRound), one row tile
+  // of 16 degrees of pairs 8h .. 8h+7 per round
+  typedef CoefRound<T, BT, 16, FWD_THREADS> CR;
+  static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX>::SMEM, "coefficient rounds fit");
   T* cst = reinterpret_cast<T*>(smem);
-  const int ci = tid & 7, cj = (tid >> 3) & 15, cb0 = tid >> 7;
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
-    PairInfo pc = p.pairs[tile * PT + 8 * i + ci];
-    if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
-    const bool mirror = p.real && (pc.tm != 0 || pc.tn != 0);
-    const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
+  for (int h = 0; h < 2; h++) {
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++) {
       __syncthreads();  // LDS free (main loop, or the previous round's reads)
-      if (rt * 16 < pi[i].L) {
+      if (rt * 16 < pi[h].L) {
 #pragma unroll
         for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-          for (int r = 0; r < 4; r++) cst[wave * PS + acc_row<T>(lane, r) * CWP + ct * 16 + lrow] = acc[i][rt][ct][r];
+          for (int r = 0; r < 4; r++)
+            cst[wave * CR::PS + acc_row<T>(lane, r) * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
       }
       __syncthreads();
-      const int j = rt * 16 + cj;
-      if (j < pc.L) {
-        const int tl = pc.tl0 + 2 * j;
-        const int idx = coef_index_of(p.so3, tl, pc.tm, pc.tn);
-        const int mdx = coef_index_of(p.so3, tl, -pc.tm, -pc.tn);
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-          const int bb = cb0 + r * (FWD_THREADS / 128);
-          if (bb < nb) {
-            const T* src = cst + ci * PS + cj * CWP + 2 * bb;
-            cpx<T> v;
-            v.re = src[0];
-            v.im = src[1];
-            cpx<T>* c = coeffs + coef_offset(p.coff, b0 + bb, p.ncoef);
-            c[idx] = v;
-            // real signals, mirror: fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
-            if (mirror) {
-              cpx<T> w;
-              w.re = sg * v.re;
-              w.im = -sg * v.im;
-              c[mdx] = w;
-            }
-          }
-        }
-      }
+      CR::store(coeffs, p, tile, h, rt * 16, b0, nb, cst, tid);
     }
   }
 }
@@ -318,65 +379,22 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   }
 
   // B operands: the scaled coefficients of the wave's two pairs, gathered
-  // through LDS in rounds of 8 pairs x JC degrees.  In a round, thread
-  // (i, j) = (tid % 8, (tid / 8) % JC) loads coefficient (l_j, m_i, n_i) of
-  // its signals, so that 8 neighbouring lanes read the 8 pairs' values of one
-  // degree and signal, which lie side by side in the coefficient vector when
-  // the pairs share m (64 contiguous bytes instead of 8 scattered ones).
-  constexpr int J = 4 * LQ;                  // degrees held per pair
-  constexpr int JC = J < 16 ? J : 16;        // degrees per round
-  constexpr int CW = 2 * BT, CWP = CW + 16;  // columns (re, im per signal), padded row
-  constexpr int PS = JC * CWP + 4;           // LDS elements per pair
-  constexpr int RPT = BT * JC * 8 / INV_THREADS;  // coefficients loaded per thread and round
-  static_assert((BT * JC * 8) % INV_THREADS == 0 && 8 * PS <= 16 * NRS, "coefficient rounds");
+  // through LDS (CoefRound) in rounds of 8 pairs x JC degrees
+  constexpr int J = 4 * LQ;            // degrees held per pair
+  constexpr int JC = J < 16 ? J : 16;  // degrees per round
+  typedef CoefRound<T, BT, JC, INV_THREADS> CR;
+  static_assert(CR::ELEMS <= (size_t)16 * NRS, "coefficient rounds fit in the stage buffer");
   T bop[2][LQ][CT];
-  {
-    T* cst = stage;
-    const int ci = tid & 7, cj = (tid >> 3) % JC, cb0 = tid / (8 * JC);
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
-      PairInfo pc = p.pairs[tile * PT + 8 * q + ci];
-      if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
-      const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
+  for (int h = 0; h < 2; h++) {
 #pragma unroll
-      for (int jc0 = 0; jc0 < J; jc0 += JC) {
-        const int j = jc0 + cj;
-        const bool jok = j < pc.L;
-        const int tl = pc.tl0 + 2 * j;
-        const int idx = jok ? coef_index_of(p.so3, tl, pc.tm, pc.tn) : 0;
-        const int mdx = jok ? coef_index_of(p.so3, tl, -pc.tm, -pc.tn) : 0;
-        const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
-        cpx<T> v[RPT];
+    for (int j0 = 0; j0 < J; j0 += JC) {
+      CR::gather(coeffs, p, tile, h, j0, b0, nb, stage, tid);
 #pragma unroll
-        for (int r = 0; r < RPT; r++) {
-          const int bb = cb0 + r * (INV_THREADS / (8 * JC));
-          const bool ok = jok && bb < nb;
-          const cpx<T>* c = coeffs + coef_offset(p.coff, b0 + (bb < nb ? bb : 0), p.ncoef);
-          v[r] = c[ok ? idx : 0];
-          if (p.real) {
-            // Hermitian part: (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
-            const cpx<T> w = c[ok ? mdx : 0];
-            v[r].re = T(0.5) * (v[r].re + sg * w.re);
-            v[r].im = T(0.5) * (v[r].im - sg * w.im);
-          }
-          v[r].re = ok ? v[r].re * sc : T(0);
-          v[r].im = ok ? v[r].im * sc : T(0);
-        }
+      for (int s = j0 / 4; s < (j0 + JC) / 4; s++)
 #pragma unroll
-        for (int r = 0; r < RPT; r++) {
-          const int bb = cb0 + r * (INV_THREADS / (8 * JC));
-          T* d = cst + ci * PS + cj * CWP + 2 * bb;
-          d[0] = v[r].re;
-          d[1] = v[r].im;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = jc0 / 4; s < (jc0 + JC) / 4; s++)
-#pragma unroll
-          for (int ct = 0; ct < CT; ct++)
-            bop[q][s][ct] = cst[wave * PS + (4 * s - jc0 + lk) * CWP + ct * 16 + lrow];
-        __syncthreads();
-      }
+        for (int ct = 0; ct < CT; ct++) bop[h][s][ct] = stage[wave * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
+      __syncthreads();
     }
   }
 

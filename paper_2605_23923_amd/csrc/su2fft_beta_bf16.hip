@@ -176,28 +176,24 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
     if (c + 1 < nchunk) commit();
   }
 
-  float* out = reinterpret_cast<float*>(coeffs);
+  // epilogue: the coefficients leave through LDS (CoefRound), one row tile
+  // of 16 degrees of pairs 8h .. 8h+7 per round
+  typedef CoefRound<float, BT, 16, XB_THREADS> CR;
+  static_assert(CR::ELEMS * sizeof(float) <= XBF_SMEM, "coefficient rounds fit");
+  float* cst = reinterpret_cast<float*>(smem);
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
-    const int L = pi[i].L;
-    if (L == 0) continue;
+  for (int h = 0; h < 2; h++) {
 #pragma unroll
     for (int rt = 0; rt < RTMAX; rt++) {
-      if (rt * 16 >= L) continue;
+      __syncthreads();  // LDS free (main loop, or the previous round's reads)
+      if (rt * 16 < pi[h].L) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        if (bb >= nb) continue;
+        for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const int l = rt * 16 + 4 * lg + r;
-          if (l < L) {
-            const long long idx = coef_index_of(0, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
-            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
-          }
-        }
+          for (int r = 0; r < 4; r++) cst[wave * CR::PS + (4 * lg + r) * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
       }
+      __syncthreads();
+      CR::store(coeffs, p, tile, h, rt * 16, b0, nb, cst, tid);
     }
   }
 }
@@ -213,8 +209,11 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
 
 // Inverse.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8 and
 // keeps their split, scaled coefficients as B operands (32 degrees per
-// instruction); the nodes are swept in blocks of 16 and staged through LDS so
-// that S is written in whole 16-pair rows.
+// instruction), gathered through LDS like the FP32 path's; the nodes are swept
+// in blocks of 16 (the table words of the next block requested before the
+// current block's products) and staged through LDS so that S is written in
+// whole 16-pair rows, by buffer stores that stay in flight across the next
+// block's products.
 template <int LQ>
 __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __restrict__ coeffs,
                                                          cpx<float>* __restrict__ S, const BetaParams<float>& p,
@@ -225,42 +224,73 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
   float* stage = reinterpret_cast<float*>(smem);
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lrow = lane & 15, lg = lane >> 4;
   const int N = p.N;
-  const float* cin = reinterpret_cast<const float*>(coeffs);
   const PairInfo p0 = p.pairs[tile * PT];
   const int lsum = p0.lsum;
   const unsigned* tb = tabi + p0.tab;
 
   PairInfo pi[2];
+#pragma unroll
+  for (int q = 0; q < 2; q++) pi[q] = p.pairs[tile * PT + wave + 8 * q];
+
+  // B operands: lane (lrow, lg) holds degrees 32 s + 8 lg + i, i = 0..7, of
+  // column ct * 16 + lrow; rounds of 16 degrees, so a lane's group of 8 comes
+  // from one round
+  constexpr int J = 32 * LQ;
+  typedef CoefRound<float, BT, 16, XB_THREADS> CR;
+  static_assert(CR::ELEMS * sizeof(float) <= XBI_SMEM, "coefficient rounds fit in the stage buffer");
   u16x8 bhi[2][LQ][CT], blo[2][LQ][CT];
 #pragma unroll
   for (int q = 0; q < 2; q++) {
-    pi[q] = p.pairs[tile * PT + wave + 8 * q];
 #pragma unroll
-    for (int s = 0; s < LQ; s++) {
+    for (int j0 = 0; j0 < J; j0 += 16) {
+      CR::gather(coeffs, p, tile, q, j0, b0, nb, stage, tid);
+      const int s = j0 / 32;
+      const int g = 32 * s + 8 * lg - j0;  // this lane's group inside the round, if 0 or 8
+      if (g == 0 || g == 8) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        float v[8];
+        for (int ct = 0; ct < CT; ct++) {
+          float v[8];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-          const int l = 32 * s + 8 * lg + i;
-          v[i] = 0.f;
-          if (l < pi[q].L && bb < nb) {
-            const int tl = pi[q].tl0 + 2 * l;
-            const float sc = p.scale_mode == 0 ? float(tl + 1) : 1.f;
-            v[i] = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + coef_index_of(0, tl, pi[q].tm, pi[q].tn)) * 2 + reim];
-          }
+          for (int i = 0; i < 8; i++) v[i] = stage[wave * CR::PS + (g + i) * CR::CWP + ct * 16 + lrow];
+          split8(v, bhi[q][s][ct], blo[q][s][ct]);
         }
-        split8(v, bhi[q][s][ct], blo[q][s][ct]);
       }
+      __syncthreads();
     }
   }
 
+  // table words of a block of 16 nodes: lane (lrow, lg) reads 8 consecutive
+  // degrees of node k0 + lrow (rows past N read row N - 1 and are never
+  // stored; degrees past L read the words that follow in the tile block, or
+  // the zeroed table padding, and meet zero B operands)
+  unsigned aw[2][LQ][8], awn[2][LQ][8];
+  auto fetch_a = [&](unsigned (&dst)[2][LQ][8], int k0) {
+    const int k = k0 + lrow < N ? k0 + lrow : N - 1;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const unsigned* trow = tb + (size_t)k * lsum + pi[q].coff + 8 * lg;
+#pragma unroll
+      for (int s = 0; s < LQ; s++) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) dst[q][s][i] = 0u;
+        if (32 * s < pi[q].L) {  // wave-uniform branch
+#pragma unroll
+          for (int i = 0; i < 8; i++) dst[q][s][i] = trow[32 * s + i];
+        }
+      }
+    }
+  };
+  constexpr int NV = 16 * BT * (PT / 2);  // 16-byte stores per block of 16 nodes
+  static_assert(NV % XB_THREADS == 0, "store split");
+  const long long slab = (long long)N * p.batch * PT;
+  const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<float>)), BUFFER_RSRC_WORD3);
+  fetch_a(aw, 0);
   for (int k0 = 0; k0 < N; k0 += 16) {
+    if (k0 + 16 < N) fetch_a(awn, k0 + 16);
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const int L = pi[q].L;
@@ -268,19 +298,11 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
       floatx4 acc[CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-      const int k = k0 + lrow;
-      const unsigned* trow = tb + (size_t)k * lsum + pi[q].coff;
 #pragma unroll
       for (int s = 0; s < LQ; s++) {
         if (32 * s < L) {
-          unsigned w[8];
-#pragma unroll
-          for (int i = 0; i < 8; i++) {
-            const int l = 32 * s + 8 * lg + i;
-            w[i] = (l < L && k < N) ? trow[l] : 0u;
-          }
           u16x8 ahi, alo;
-          unpack8(w, ahi, alo);
+          unpack8(aw[q][s], ahi, alo);
 #pragma unroll
           for (int ct = 0; ct < CT; ct++) {
             acc[ct] = mfma_bf16(ahi, bhi[q][s][ct], acc[ct]);
@@ -298,17 +320,33 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
       }
     }
     __syncthreads();
-    for (int v = tid; v < 16 * BT * (PT / 2); v += XB_THREADS) {
+    // the thread index passes through an empty asm statement so that the
+    // store addresses are formed here, not hoisted out of the node loop
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+#pragma unroll
+    for (int i = 0; i < NV / XB_THREADS; i++) {
+      const int v = tq + XB_THREADS * i;
       const int row = v / (PT / 2), pv = v - row * (PT / 2);
       const int kk = row / BT, bb = row - kk * BT;
       const int k = k0 + kk;
-      if (k < N && bb < nb) {
-        const float* src = stage + row * PB + 4 * pv;
-        *reinterpret_cast<float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + 2 * pv) =
-            make_float4(src[0], src[1], src[2], src[3]);
-      }
+      const float* src = stage + row * PB + 4 * pv;
+      u32x4 w;
+      float* wd = reinterpret_cast<float*>(&w);
+#pragma unroll
+      for (int e = 0; e < 4; e++) wd[e] = src[e];
+      const unsigned off = (k < N && bb < nb)
+                               ? (unsigned)((((long long)k * p.batch + b0 + bb) * PT + 2 * pv) * (long long)sizeof(cpx<float>))
+                               : 0x80000000u;  // past the slab: dropped by the range check
+      __builtin_amdgcn_raw_buffer_store_b128(w, srsrc, off, 0, 0);
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+      for (int s = 0; s < LQ; s++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) aw[q][s][i] = awn[q][s][i];
   }
 }
 

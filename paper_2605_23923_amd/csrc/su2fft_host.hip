@@ -406,7 +406,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
     if ((e = hipMemset(pl->d_tab32 + tab, 0, 64)) != hipSuccess) return hip_fail(e);
     if ((e = launch_round_table_f32(tab, pl->d_tab64, pl->d_tab32, 0)) != hipSuccess) return hip_fail(e);
   } else if (pl->dtype == SU2_C64_BF16X3) {
-    if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab + 64)) != hipSuccess) return hip_fail(e);
+    // 256 bytes of zeros after the last block: the split inverse reads up to
+    // 31 words past a pair's row segment (against zero operands)
+    if ((e = pl->alloc((void**)&pl->d_tabbf, sizeof(bf16x2_t) * (size_t)tab + 256)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemset(pl->d_tabbf + tab, 0, 256)) != hipSuccess) return hip_fail(e);
     if ((e = launch_split_table_bf16(tab, pl->d_tab64, pl->d_tabbf, 0)) != hipSuccess) return hip_fail(e);
     const long long fwd_words = tab / N * (long long)((N + 7) / 8) * 8;
     if ((e = pl->alloc((void**)&pl->d_tabbf_fwd, sizeof(unsigned) * (size_t)fwd_words + 64)) != hipSuccess)

@@ -218,8 +218,13 @@ def test_absurd_batch_is_out_of_memory_without_leak():
     torch.cuda.synchronize()
     free0, _ = torch.cuda.mem_get_info()
     with pytest.raises(su2.SU2Error) as ei:
-        su2.Plan(128, 1 << 30, "c128")
+        # the largest batch whose pair-tile spectra still take 32-bit offsets;
+        # its ring spectra alone would need 4.4 TB
+        su2.Plan(128, 32767, "c128")
     assert ei.value.status == 3
+    with pytest.raises(su2.SU2Error) as ei:
+        su2.Plan(128, 1 << 30, "c128")
+    assert ei.value.status == 2
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info()
     assert abs(free1 - free0) < 64 << 20
