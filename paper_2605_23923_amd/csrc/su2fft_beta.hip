@@ -69,27 +69,28 @@ struct BetaCfg<double> {
 // pairs and all the workgroup's signals; read or written straight from the
 // coefficient vectors, every lane would touch its own 4- or 8-byte piece of a
 // different cache line.  Instead the workgroup moves them through LDS in
-// rounds of 8 pairs (i = 0..7: pairs 8 h + i of the tile) x JC degree indices
-// j, with thread (i, j) = (tid % 8, (tid / 8) % JC) handling coefficient
-// (l_j, m_i, n_i) of its signals: 8 neighbouring lanes cover the 8 pairs'
-// values of one degree and signal, which lie side by side in the coefficient
-// vector when the pairs share m.  LDS layout of a round:
+// rounds of all 16 pairs of the tile x 8 degree indices j, with thread
+// (i, j) = (tid % 16, (tid / 16) % 8) handling coefficient (l_j, m_i, n_i) of
+// its signals: 16 neighbouring lanes cover the 16 pairs' values of one degree
+// and signal, which lie side by side in the coefficient vector (a whole
+// 128-byte line for FP32) when the pairs share m.  LDS layout of a round:
 // cst[i * PS + (j - j0) * CWP + 2 * signal + (re, im)].
-template <class T, int BT, int JC, int NTHR>
+template <class T, int BT, int NTHR>
 struct CoefRound {
+  static constexpr int JC = 8;                  // degree indices per round
   static constexpr int CW = 2 * BT, CWP = CW + 16, PS = JC * CWP + 4;
-  static constexpr int STEP = NTHR / (8 * JC);  // signals between a thread's coefficients
-  static constexpr int RPT = BT / STEP;         // coefficients per thread and round
-  static constexpr size_t ELEMS = (size_t)8 * PS;
-  static_assert(NTHR % (8 * JC) == 0 && BT % STEP == 0, "coefficient round split");
+  static constexpr int STEP = NTHR / (PT * JC);  // signals between a thread's coefficients
+  static constexpr int RPT = BT / STEP;          // coefficients per thread and round
+  static constexpr size_t ELEMS = (size_t)PT * PS;
+  static_assert(NTHR % (PT * JC) == 0 && BT % STEP == 0, "coefficient round split");
 
-  // inverse: the scaled coefficients (2l+1 or 1) of pairs 8h..8h+7, degree
-  // indices j0..j0+JC-1, into LDS (zero past L or the batch; the Hermitian
-  // part for real plans).  Ends with a barrier: the round is readable.
-  __device__ static void gather(const cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int h, int j0,
-                                int b0, int nb, T* cst, int tid) {
-    const int ci = tid & 7, cj = (tid / 8) % JC, cb0 = tid / (8 * JC);
-    PairInfo pc = p.pairs[tile * PT + 8 * h + ci];
+  // inverse: the scaled coefficients (2l+1 or 1) of the tile's pairs, degree
+  // indices j0..j0+7, into LDS (zero past L or the batch; the Hermitian part
+  // for real plans).  Ends with a barrier: the round is readable.
+  __device__ static void gather(const cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int j0, int b0,
+                                int nb, T* cst, int tid) {
+    const int ci = tid % PT, cj = (tid / PT) % JC, cb0 = tid / (PT * JC);
+    PairInfo pc = p.pairs[tile * PT + ci];
     if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
     const T sg = (((pc.tm - pc.tn) / 2) & 1) ? T(-1) : T(1);
     const int j = j0 + cj;
@@ -123,13 +124,13 @@ struct CoefRound {
     __syncthreads();
   }
 
-  // forward: the sums parked in LDS for pairs 8h..8h+7, degree indices
-  // j0..j0+JC-1, out to the coefficient vectors (with the mirror
+  // forward: the sums parked in LDS for the tile's pairs, degree indices
+  // j0..j0+7, out to the coefficient vectors (with the mirror
   // (-1)^{m-n} conj(fhat) at (-m, -n) for real plans).
-  __device__ static void store(cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int h, int j0, int b0,
-                               int nb, const T* cst, int tid) {
-    const int ci = tid & 7, cj = (tid / 8) % JC, cb0 = tid / (8 * JC);
-    PairInfo pc = p.pairs[tile * PT + 8 * h + ci];
+  __device__ static void store(cpx<T>* __restrict__ coeffs, const BetaParams<T>& p, int tile, int j0, int b0, int nb,
+                               const T* cst, int tid) {
+    const int ci = tid % PT, cj = (tid / PT) % JC, cb0 = tid / (PT * JC);
+    PairInfo pc = p.pairs[tile * PT + ci];
     if (p.real && mirrored_pair(pc.tm, pc.tn)) pc.L = 0;
     const int j = j0 + cj;
     if (j >= pc.L) return;
@@ -308,26 +309,31 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
     }
   }
 
-  // epilogue: the coefficients leave through LDS (CoefRound), one row tile
-  // of 16 degrees of pairs 8h .. 8h+7 per round
-  typedef CoefRound<T, BT, 16, FWD_THREADS> CR;
+  // epilogue: the coefficients leave through LDS (CoefRound), 8 degrees of
+  // all 16 pairs per round; each wave parks the rows of its two pairs that
+  // fall in the round
+  typedef CoefRound<T, BT, FWD_THREADS> CR;
   static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX>::SMEM, "coefficient rounds fit");
   T* cst = reinterpret_cast<T*>(smem);
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
+  for (int j0 = 0; j0 < 16 * RTMAX; j0 += CR::JC) {
+    const int rt = j0 / 16, r0 = j0 % 16;
+    __syncthreads();  // LDS free (main loop, or the previous round's reads)
 #pragma unroll
-    for (int rt = 0; rt < RTMAX; rt++) {
-      __syncthreads();  // LDS free (main loop, or the previous round's reads)
+    for (int h = 0; h < 2; h++) {
       if (rt * 16 < pi[h].L) {
 #pragma unroll
         for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-          for (int r = 0; r < 4; r++)
-            cst[wave * CR::PS + acc_row<T>(lane, r) * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
+          for (int r = 0; r < 4; r++) {
+            const int row = acc_row<T>(lane, r) - r0;
+            if (row >= 0 && row < CR::JC)
+              cst[(wave + 8 * h) * CR::PS + row * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
+          }
       }
-      __syncthreads();
-      CR::store(coeffs, p, tile, h, rt * 16, b0, nb, cst, tid);
     }
+    __syncthreads();
+    CR::store(coeffs, p, tile, j0, b0, nb, cst, tid);
   }
 }
 
@@ -379,23 +385,22 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   }
 
   // B operands: the scaled coefficients of the wave's two pairs, gathered
-  // through LDS (CoefRound) in rounds of 8 pairs x JC degrees
-  constexpr int J = 4 * LQ;            // degrees held per pair
-  constexpr int JC = J < 16 ? J : 16;  // degrees per round
-  typedef CoefRound<T, BT, JC, INV_THREADS> CR;
-  static_assert(CR::ELEMS <= (size_t)16 * NRS, "coefficient rounds fit in the stage buffer");
+  // through LDS (CoefRound) in rounds of 8 degrees of all 16 pairs
+  constexpr int J = 4 * LQ;  // degrees held per pair
+  typedef CoefRound<T, BT, INV_THREADS> CR;
+  static_assert(CR::ELEMS <= (size_t)16 * NRS && J % CR::JC == 0, "coefficient rounds fit in the stage buffer");
   T bop[2][LQ][CT];
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
+  for (int j0 = 0; j0 < J; j0 += CR::JC) {
+    CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
 #pragma unroll
-    for (int j0 = 0; j0 < J; j0 += JC) {
-      CR::gather(coeffs, p, tile, h, j0, b0, nb, stage, tid);
+    for (int h = 0; h < 2; h++)
 #pragma unroll
-      for (int s = j0 / 4; s < (j0 + JC) / 4; s++)
+      for (int s = j0 / 4; s < (j0 + CR::JC) / 4; s++)
 #pragma unroll
-        for (int ct = 0; ct < CT; ct++) bop[h][s][ct] = stage[wave * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
-      __syncthreads();
-    }
+        for (int ct = 0; ct < CT; ct++)
+          bop[h][s][ct] = stage[(wave + 8 * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
+    __syncthreads();
   }
 
   // table values of a block of 16 nodes: A operands (row = node, col =

@@ -176,25 +176,29 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
     if (c + 1 < nchunk) commit();
   }
 
-  // epilogue: the coefficients leave through LDS (CoefRound), one row tile
-  // of 16 degrees of pairs 8h .. 8h+7 per round
-  typedef CoefRound<float, BT, 16, XB_THREADS> CR;
+  // epilogue: the coefficients leave through LDS (CoefRound), 8 degrees of
+  // all 16 pairs per round
+  typedef CoefRound<float, BT, XB_THREADS> CR;
   static_assert(CR::ELEMS * sizeof(float) <= XBF_SMEM, "coefficient rounds fit");
   float* cst = reinterpret_cast<float*>(smem);
 #pragma unroll
-  for (int h = 0; h < 2; h++) {
+  for (int j0 = 0; j0 < 16 * RTMAX; j0 += CR::JC) {
+    const int rt = j0 / 16, r0 = j0 % 16;
+    __syncthreads();  // LDS free (main loop, or the previous round's reads)
 #pragma unroll
-    for (int rt = 0; rt < RTMAX; rt++) {
-      __syncthreads();  // LDS free (main loop, or the previous round's reads)
+    for (int h = 0; h < 2; h++) {
       if (rt * 16 < pi[h].L) {
 #pragma unroll
         for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-          for (int r = 0; r < 4; r++) cst[wave * CR::PS + (4 * lg + r) * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
+          for (int r = 0; r < 4; r++) {
+            const int row = 4 * lg + r - r0;
+            if (row >= 0 && row < CR::JC) cst[(wave + 8 * h) * CR::PS + row * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
+          }
       }
-      __syncthreads();
-      CR::store(coeffs, p, tile, h, rt * 16, b0, nb, cst, tid);
     }
+    __syncthreads();
+    CR::store(coeffs, p, tile, j0, b0, nb, cst, tid);
   }
 }
 
@@ -236,30 +240,28 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
   for (int q = 0; q < 2; q++) pi[q] = p.pairs[tile * PT + wave + 8 * q];
 
   // B operands: lane (lrow, lg) holds degrees 32 s + 8 lg + i, i = 0..7, of
-  // column ct * 16 + lrow; rounds of 16 degrees, so a lane's group of 8 comes
-  // from one round
+  // column ct * 16 + lrow; a round of 8 degrees (CoefRound) is exactly one
+  // lane group's 8 degrees
   constexpr int J = 32 * LQ;
-  typedef CoefRound<float, BT, 16, XB_THREADS> CR;
-  static_assert(CR::ELEMS * sizeof(float) <= XBI_SMEM, "coefficient rounds fit in the stage buffer");
+  typedef CoefRound<float, BT, XB_THREADS> CR;
+  static_assert(CR::ELEMS * sizeof(float) <= XBI_SMEM && CR::JC == 8, "coefficient rounds fit in the stage buffer");
   u16x8 bhi[2][LQ][CT], blo[2][LQ][CT];
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
+  for (int j0 = 0; j0 < J; j0 += 8) {
+    CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
+    const int s = j0 / 32;
+    if (8 * lg == j0 % 32) {
 #pragma unroll
-    for (int j0 = 0; j0 < J; j0 += 16) {
-      CR::gather(coeffs, p, tile, q, j0, b0, nb, stage, tid);
-      const int s = j0 / 32;
-      const int g = 32 * s + 8 * lg - j0;  // this lane's group inside the round, if 0 or 8
-      if (g == 0 || g == 8) {
+      for (int q = 0; q < 2; q++)
 #pragma unroll
         for (int ct = 0; ct < CT; ct++) {
           float v[8];
 #pragma unroll
-          for (int i = 0; i < 8; i++) v[i] = stage[wave * CR::PS + (g + i) * CR::CWP + ct * 16 + lrow];
+          for (int i = 0; i < 8; i++) v[i] = stage[(wave + 8 * q) * CR::PS + i * CR::CWP + ct * 16 + lrow];
           split8(v, bhi[q][s][ct], blo[q][s][ct]);
         }
-      }
-      __syncthreads();
     }
+    __syncthreads();
   }
 
   // table words of a block of 16 nodes: lane (lrow, lg) reads 8 consecutive
