@@ -337,8 +337,12 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     }
   }
   cpx<T> a[G::I1][N2];
+  // REAL: only the first q slice is transformed along alpha; the gamma
+  // frequencies of the second slice are the conjugates of the first's
+  // (G[j][N - q] = conj(G[j][q]) for a real ring), taken in exchange 2'
+  constexpr int RA = REAL ? 1 : ROUNDS;  // rounds of phases 4' and 3'
 #pragma unroll
-  for (int r = 0; r < ROUNDS; r++) {
+  for (int r = 0; r < RA; r++) {
     const int rs = REAL ? 0 : r;  // slice staged in this round
     const int pb = p.rbeg[rs], pe = p.rend[rs];
     static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
@@ -390,7 +394,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
   for (int pp = 0; pp < N2; pp++) tw3[pp] = tw[((2 * pp + odd) * j1) % (2 * N)];
 #pragma unroll
-  for (int s = 0; s < G::I1; s++) {
+  for (int s = 0; s < G::I1 / ROUNDS * RA; s++) {
 #pragma unroll
     for (int pp = 0; pp < N2; pp++) a[s][pp] = cmulc(a[s][pp], tw3[pp]);
     dftr<T, N2, -1>(a[s]);
@@ -411,8 +415,33 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 
   // ---- exchange 2' and phase 2': radix-N1 over q1 -> l1
   cpx<T> c[G::I2][N1];
+  if constexpr (REAL) {
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < ROUNDS; r++) {
+    for (int s = 0; s < G::I1 / ROUNDS; s++) {
+      const int q = t / N1 + (NT / N1) * s;
+#pragma unroll
+      for (int j2 = 0; j2 < N2; j2++) buf[q * G::P2 + j1 + N1 * j2] = a[s][j2];
+    }
+    __syncthreads();
+    static_assert(G::QR % N2 == 0, "slice boundary on a q1 boundary");
+#pragma unroll
+    for (int s = 0; s < G::I2; s++) {
+      const int q2 = t / N + (NT / N) * s;
+#pragma unroll
+      for (int q1 = 0; q1 < N1; q1++) {
+        if (q1 < G::QR / N2) {
+          c[s][q1] = buf[(q2 + N2 * q1) * G::P2 + jr];
+        } else {  // q >= N/2: conj(G[j][N - q]); q = N/2 holds no retained bin
+          const int qm = N - q2 - N2 * q1;
+          const cpx<T> v = buf[(qm < G::QR ? qm : 0) * G::P2 + jr];
+          c[s][q1] = qm < G::QR ? cpx<T>{v.re, -v.im} : cpx<T>{T(0), T(0)};
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < (REAL ? 0 : ROUNDS); r++) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
