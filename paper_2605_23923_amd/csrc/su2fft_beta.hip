@@ -166,12 +166,17 @@ struct CoefRound {
 // registers (16-byte loads) while the matrix cores work on chunk c.
 constexpr int FWD_THREADS = 512;
 
-template <class T, int RTMAX>
+// KC: beta nodes per streamed chunk.  4 in FP32 when the grid has at least
+// 1.5 workgroups per CU (fewer prefetch registers, two resident workgroups:
+// measured 14 % faster than 8 at B = 64 batch 32), otherwise 8 (more bytes
+// in flight per workgroup: measured better for grids of one workgroup per
+// CU); 8 in FP64 (measured 8 % faster than 4).
+template <class T>
+constexpr int fwd_kc_default() { return sizeof(T) == 4 ? 4 : 8; }
+
+template <class T, int RTMAX, int KC_ = fwd_kc_default<T>()>
 struct FwdGeom {
-  // beta nodes per streamed chunk: 4 in FP32 (fewer prefetch registers, two
-  // workgroups per CU: measured 14 % faster than 8), 8 in FP64 (measured 8 %
-  // faster than 4)
-  static constexpr int KC = sizeof(T) == 4 ? 4 : 8;
+  static constexpr int KC = KC_;
   static constexpr int BT = BetaCfg<T>::BT;
   static constexpr int PB = 2 * PT + 2;
   static constexpr int PK = BT * PB + 16;
@@ -185,12 +190,12 @@ struct FwdGeom {
   static constexpr size_t SMEM = SMEM_LOOP > SMEM_EPI ? SMEM_LOOP : SMEM_EPI;
 };
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int KC_ = fwd_kc_default<T>()>
 __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
                                                   const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
   typedef typename acc4<T>::type accT;
   constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
-  constexpr int KC = FwdGeom<T, RTMAX>::KC;
+  constexpr int KC = KC_;
   constexpr int PB = 2 * PT + 2;            // reals per (node, signal) row: 16 pairs x (re, im) + pad
   constexpr int PK = BT * PB + 16;          // reals per node
   constexpr int TMAX = PT * 16 * RTMAX;     // longest tile row
@@ -319,7 +324,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   // all 16 pairs per round; each wave parks the rows of its two pairs that
   // fall in the round
   typedef CoefRound<T, BT, FWD_THREADS> CR;
-  static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX>::SMEM, "coefficient rounds fit");
+  static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX, KC>::SMEM, "coefficient rounds fit");
   T* cst = reinterpret_cast<T*>(smem);
 #pragma unroll
   for (int j0 = 0; j0 < 16 * RTMAX; j0 += CR::JC) {
@@ -343,11 +348,11 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   }
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int KC>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_body<T, RTMAX>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_forward_body<T, RTMAX, KC>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
@@ -513,26 +518,42 @@ static hipError_t set_smem(K kern, size_t smem) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
 }
 
+template <class T, int RTMAX, int KC>
+static hipError_t launch_forward_shape(const BetaParams<T>& p, dim3 grid, const cpx<T>* S, cpx<T>* coeffs,
+                                       hipStream_t s) {
+  constexpr size_t smem = FwdGeom<T, RTMAX, KC>::SMEM;
+  hipError_t e;
+  if ((e = set_smem(beta_forward_kernel<T, RTMAX, KC>, smem)) != hipSuccess) return e;
+  hipLaunchKernelGGL((beta_forward_kernel<T, RTMAX, KC>), grid, dim3(FWD_THREADS), smem, s, S, coeffs, p);
+  return hipGetLastError();
+}
+
+template <class T, int RTMAX>
+static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx<T>* S, cpx<T>* coeffs,
+                                    hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    // two resident workgroups per CU pay off once most CUs get two (grids
+    // of at least 1.5 workgroups per CU)
+    static int cus = 0;
+    if (cus == 0) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                   hipSuccess || cus < 1)
+        cus = 256;
+    }
+    if (2LL * grid.x * grid.y >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4>(p, grid, S, coeffs, s);
+  }
+  return launch_forward_shape<T, RTMAX, 8>(p, grid, S, coeffs, s);
+}
+
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
   constexpr int BT = BetaCfg<T>::BT;
   dim3 grid(p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
   const int rt = beta_rtmax(p.B);
-  hipError_t e;
-  if (rt == 1) {
-    if ((e = set_smem(beta_forward_kernel<T, 1>, FwdGeom<T, 1>::SMEM)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL((beta_forward_kernel<T, 1>), grid, dim3(FWD_THREADS), (FwdGeom<T, 1>::SMEM), s, S, coeffs, p);
-  } else if (rt == 2) {
-    if ((e = set_smem(beta_forward_kernel<T, 2>, FwdGeom<T, 2>::SMEM)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL((beta_forward_kernel<T, 2>), grid, dim3(FWD_THREADS), (FwdGeom<T, 2>::SMEM), s, S, coeffs, p);
-  } else {
-    if ((e = set_smem(beta_forward_kernel<T, 4>, FwdGeom<T, 4>::SMEM)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL((beta_forward_kernel<T, 4>), grid, dim3(FWD_THREADS), (FwdGeom<T, 4>::SMEM), s, S, coeffs, p);
-  }
-  return hipGetLastError();
+  if (rt == 1) return launch_forward_rt<T, 1>(p, grid, S, coeffs, s);
+  if (rt == 2) return launch_forward_rt<T, 2>(p, grid, S, coeffs, s);
+  return launch_forward_rt<T, 4>(p, grid, S, coeffs, s);
 }
 
 template <class T>
