@@ -189,29 +189,30 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
     if (c + 1 < nchunk) commit();
   }
 
-  T* out = reinterpret_cast<T*>(coeffs);
+  // epilogue: the coefficients leave through LDS (CoefRound), 8 degrees of
+  // all 16 pairs per round
+  typedef CoefRound<T, BT, FWD_THREADS> CR;
+  static_assert(CR::ELEMS * sizeof(T) <= G::SMEM_C, "coefficient rounds fit");
+  T* cst = reinterpret_cast<T*>(smem);
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
-    const int L = pi[i].L;
-    if (L == 0) continue;
+  for (int j0 = 0; j0 < 16 * RTMAX; j0 += CR::JC) {
+    const int rt = j0 / 16, r0 = j0 % 16;
+    __syncthreads();  // LDS free (main loop, or the previous round's reads)
 #pragma unroll
-    for (int rt = 0; rt < RTMAX; rt++) {
-      if (rt * 16 >= L) continue;
+    for (int h = 0; h < 2; h++) {
+      if (rt * 16 < pi[h].L) {
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        if (bb >= nb) continue;
+        for (int ct = 0; ct < CT; ct++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          const int l = rt * 16 + acc_row<T>(lane, r);
-          if (l < L) {
-            const long long idx = coef_index_of(0, pi[i].tl0 + 2 * l, pi[i].tm, pi[i].tn);
-            out[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim] = acc[i][rt][ct][r];
+          for (int r = 0; r < 4; r++) {
+            const int row = acc_row<T>(lane, r) - r0;
+            if (row >= 0 && row < CR::JC)
+              cst[(wave + 8 * h) * CR::PS + row * CR::CWP + ct * 16 + lrow] = acc[h][rt][ct][r];
           }
-        }
       }
     }
+    __syncthreads();
+    CR::store(coeffs, p, tile, j0, b0, nb, cst, tid);
   }
 }
 
@@ -240,33 +241,29 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
   const int wave = tid >> 6, lane = tid & 63;
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
-  const T* cin = reinterpret_cast<const T*>(coeffs);
   const PairInfo p0 = p.pairs[tile * PT];
   const long long row0 = p0.tab / N;
   otf_load_coeffs(sC, op.rcoef, row0, p0.lsum, tid, INV_THREADS);
 
   PairInfo pi[2];
+#pragma unroll
+  for (int q = 0; q < 2; q++) pi[q] = p.pairs[tile * PT + wave + 8 * q];
+  // B operands: the scaled coefficients gathered through LDS (CoefRound)
+  constexpr int J = 4 * LQ;
+  typedef CoefRound<T, BT, INV_THREADS> CR;
+  static_assert(CR::ELEMS <= (size_t)16 * NRS && J % CR::JC == 0, "coefficient rounds fit in the stage buffer");
   T bop[2][LQ][CT];
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
-    pi[q] = p.pairs[tile * PT + wave + 8 * q];
+  for (int j0 = 0; j0 < J; j0 += CR::JC) {
+    CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
 #pragma unroll
-    for (int s = 0; s < LQ; s++) {
-      const int l = 4 * s + lk;
+    for (int h = 0; h < 2; h++)
 #pragma unroll
-      for (int ct = 0; ct < CT; ct++) {
-        const int cc = ct * 16 + lrow;
-        const int bb = cc >> 1, reim = cc & 1;
-        T v = T(0);
-        if (l < pi[q].L && bb < nb) {
-          const int tl = pi[q].tl0 + 2 * l;
-          const long long idx = coef_index_of(0, tl, pi[q].tm, pi[q].tn);
-          const T sc = p.scale_mode == 0 ? T(tl + 1) : T(1);
-          v = sc * cin[(coef_offset(p.coff, b0 + bb, p.ncoef) + idx) * 2 + reim];
-        }
-        bop[q][s][ct] = v;
-      }
-    }
+      for (int s = j0 / 4; s < (j0 + CR::JC) / 4; s++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          bop[h][s][ct] = stage[(wave + 8 * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
+    __syncthreads();
   }
 
   __syncthreads();
