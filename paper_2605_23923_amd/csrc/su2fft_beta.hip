@@ -359,8 +359,9 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>*
 // pairs w and w + 8.  Each wave keeps its pairs' scaled coefficients as
 // matrix-core B operands in registers, then sweeps the N nodes in blocks of
 // 16; a block's outputs for all 16 pairs are gathered in LDS and written as
-// full PT-pair rows of S.  The table values of the next block are fetched
-// while the current block is staged and written.
+// full PT-pair rows of S.  The table values of the next block are requested
+// before the current block's products (see fetch_a), and the stores of S stay
+// in flight while the next block's products run.
 constexpr int INV_THREADS = 512;
 
 // staging buffer: 16 node rows of BT (signal) rows of PB reals, each node row
