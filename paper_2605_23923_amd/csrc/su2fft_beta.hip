@@ -396,25 +396,6 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
     if (p.real && mirrored_pair(pi[q].tm, pi[q].tn)) pi[q].L = 0;
   }
 
-  // B operands: the scaled coefficients of the wave's two pairs, gathered
-  // through LDS (CoefRound) in rounds of 8 degrees of all 16 pairs
-  constexpr int J = 4 * LQ;  // degrees held per pair
-  typedef CoefRound<T, BT, INV_THREADS> CR;
-  static_assert(CR::ELEMS <= (size_t)16 * NRS && J % CR::JC == 0, "coefficient rounds fit in the stage buffer");
-  T bop[2][LQ][CT];
-#pragma unroll
-  for (int j0 = 0; j0 < J; j0 += CR::JC) {
-    CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
-#pragma unroll
-    for (int h = 0; h < 2; h++)
-#pragma unroll
-      for (int s = j0 / 4; s < (j0 + CR::JC) / 4; s++)
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++)
-          bop[h][s][ct] = stage[(wave + 8 * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
-    __syncthreads();
-  }
-
   // table values of a block of 16 nodes: A operands (row = node, col =
   // degree), from the inverse-layout table: one load of 64 consecutive
   // values per group of 4 degrees (zeros past N and L are stored there).
@@ -434,6 +415,27 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
       }
     }
   };
+  fetch_a(av, 0);  // in flight while the coefficients are gathered
+
+  // B operands: the scaled coefficients of the wave's two pairs, gathered
+  // through LDS (CoefRound) in rounds of 8 degrees of all 16 pairs
+  constexpr int J = 4 * LQ;  // degrees held per pair
+  typedef CoefRound<T, BT, INV_THREADS> CR;
+  static_assert(CR::ELEMS <= (size_t)16 * NRS && J % CR::JC == 0, "coefficient rounds fit in the stage buffer");
+  T bop[2][LQ][CT];
+#pragma unroll
+  for (int j0 = 0; j0 < J; j0 += CR::JC) {
+    CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int s = j0 / 4; s < (j0 + CR::JC) / 4; s++)
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+          bop[h][s][ct] = stage[(wave + 8 * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
+    __syncthreads();
+  }
+
   // the tile's slab of S as a buffer resource: stores of rows whose node or
   // signal does not exist get an offset past the slab, and the hardware range
   // check drops them; every lane issues the same unconditional stores
@@ -443,7 +445,6 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   const long long slab = (long long)N * p.batch * PT;
   const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<T>)), BUFFER_RSRC_WORD3);
-  fetch_a(av, 0);
   for (int k0 = 0; k0 < N; k0 += 16) {
     if constexpr (EARLY)
       if (k0 + 16 < N) fetch_a(avn, k0 / 16 + 1);

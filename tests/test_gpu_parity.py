@@ -236,3 +236,23 @@ def test_wrong_tensor_arguments_are_rejected():
         plan.forward(torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda"))
     with pytest.raises(ValueError):
         plan.forward(torch.zeros((1, 8, 8, 8), dtype=torch.complex64, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_launch_shape_does_not_change_results(dtype):
+    """The forward contraction picks its node-chunk size from the grid (FP32:
+    4-node chunks for grids of at least 1.5 workgroups per CU, else 8), and the
+    inverse runs its signal tiles in parallel; neither changes a signal's
+    result (bitwise), since the products accumulate over the nodes in the
+    same order.  B = 32 with 128 signals gives a large grid, one signal a
+    small one."""
+    B, batch = 32, 128
+    x = synth.samples_uniform(B, batch, seed=13, dtype=NPDT[dtype])
+    c = synth.coeffs(B, batch, seed=14, dtype=NPDT[dtype])
+    big = su2.Plan(B, batch, dtype)
+    one = su2.Plan(B, 1, dtype)
+    f = _host(big.forward(_dev(x)))
+    s = _host(big.inverse(_dev(c)))
+    for b in (0, 63, 127):
+        assert np.array_equal(f[b], _host(one.forward(_dev(x[b:b + 1])))[0])
+        assert np.array_equal(s[b], _host(one.inverse(_dev(c[b:b + 1])))[0])
