@@ -315,6 +315,53 @@ def secondary_configs(steps: int, warmup: int):
     return out
 
 
+def measured_peaks():
+    """What this device sustains, from the library's calibration kernels
+    (su2fft_calib.h): a streaming copy and fill of 1 GiB buffers (HBM) and
+    back-to-back 16x16 matrix-core products at 8 workgroups of 4 waves per CU,
+    each the fastest of 5 timed launches (HIP events on the launch stream)."""
+    import torch
+
+    import paper_2605_23923_amd as su2
+
+    def best_ms(fn, reps=5):
+        fn()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return min(times)
+
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    su2.calib_fill(src, 1.0)
+    copy_ms = best_ms(lambda: su2.calib_copy(src, dst))
+    fill_ms = best_ms(lambda: su2.calib_fill(dst, 2.0))
+    del src, dst
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    wg = 8 * cus
+    out = torch.empty(wg * 256, dtype=torch.float32, device="cuda")
+    mfma = {}
+    for kind, iters in (("fp64", 400), ("fp32", 800), ("bf16", 1500)):
+        flops = []
+        ms = best_ms(lambda: flops.append(su2.calib_mfma(kind, wg, iters, out)))
+        mfma[kind] = round(flops[-1] / (ms * 1e-3) / 1e12, 2)
+    torch.cuda.synchronize()
+    return {"copy_GBps": round(2 * nbytes / (copy_ms * 1e-3) / 1e9, 1),
+            "fill_GBps": round(nbytes / (fill_ms * 1e-3) / 1e9, 1),
+            "mfma_TFLOPs": mfma,
+            "published": {"hbm_GBps": HBM_PEAK / 1e9,
+                          "mfma_TFLOPs": {"fp64": MFMA_PEAK["c128"] / 1e12, "fp32": MFMA_PEAK["c64"] / 1e12,
+                                          "bf16": MFMA_PEAK["c64_bf16x3"] / 1e12}},
+            "method": "su2_calib_copy / su2_calib_fill over 1 GiB (copy counts read + write), su2_calib_mfma "
+                      "16x16x4 FP64/FP32 and 16x16x32 BF16 at %d workgroups x 256 threads; best of 5" % wg}
+
+
 def cpu_baseline(B: int, budget_s: float):
     """The oracle's direct sum on a bounded sample: the forward transform of one
     signal restricted to a subset of its coefficients (a few of every 2l), timed
@@ -375,6 +422,8 @@ def main():
                          "'_real' = real-signal plan, '_so3' = SO(3) plan (integer degrees)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-calibration", action="store_true",
+                    help="skip the copy / fill / matrix-core calibration reported under 'measured_peaks'")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the mixed-bandlimit and B=128 workloads reported under 'other_workloads'")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -435,6 +484,10 @@ def main():
         "modes": {m: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for m, r in modes.items()},
         "source_digest": digest,
     }
+    if not args.no_calibration:
+        peaks = measured_peaks()
+        line["measured_peaks"] = peaks
+        roof["frac_of_measured_copy"] = round(achieved / (peaks["copy_GBps"] * 1e9), 4)
     if not args.no_secondary:
         line["other_workloads"] = secondary_configs(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:

@@ -97,6 +97,12 @@ def _load():
     lib.su2_status_string.restype = ctypes.c_char_p
     lib.su2_last_hip_error.argtypes = []
     lib.su2_last_hip_error.restype = i32
+    lib.su2_calib_copy.argtypes = [vp, vp, i64, vp]
+    lib.su2_calib_copy.restype = i32
+    lib.su2_calib_fill.argtypes = [vp, i64, ctypes.c_float, vp]
+    lib.su2_calib_fill.restype = i32
+    lib.su2_calib_mfma.argtypes = [i32, i32, i32, vp, dp, vp]
+    lib.su2_calib_mfma.restype = i32
     _lib = lib
     return lib
 
@@ -138,6 +144,43 @@ def grid(B: int):
 
 def _stream_handle(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _device_buffer(t, what: str):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{what}: a contiguous device tensor is required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def calib_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Streaming copy of src's bytes into dst on the current stream (calibration
+    kernel: 2 x nbytes of HBM traffic)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("calib_copy: dst is smaller than src")
+    _check(_load().su2_calib_copy(_device_buffer(src, "calib_copy"), _device_buffer(dst, "calib_copy"), n,
+                                  _stream_handle(src.device)), "su2_calib_copy")
+
+
+def calib_fill(dst: torch.Tensor, value: float) -> None:
+    """Streaming write of `value` to every float of dst on the current stream."""
+    _check(_load().su2_calib_fill(_device_buffer(dst, "calib_fill"), dst.numel() * dst.element_size(),
+                                  float(value), _stream_handle(dst.device)), "su2_calib_fill")
+
+
+CALIB_MFMA_KINDS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+def calib_mfma(kind: str, workgroups: int, iters: int, out: torch.Tensor) -> float:
+    """Back-to-back matrix-core products (kind 'fp64', 'fp32' or 'bf16') on the
+    current stream; out holds workgroups x 256 float32.  Returns the flops the
+    launch executes."""
+    if out.dtype != torch.float32 or out.numel() < workgroups * 256:
+        raise ValueError("calib_mfma: out must hold workgroups x 256 float32 values")
+    flops = ctypes.c_double(0.0)
+    _check(_load().su2_calib_mfma(CALIB_MFMA_KINDS[kind], int(workgroups), int(iters), _device_buffer(out, "calib_mfma"),
+                                  ctypes.byref(flops), _stream_handle(out.device)), "su2_calib_mfma")
+    return flops.value
 
 
 class _PlanBase:

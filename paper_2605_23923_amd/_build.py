@@ -16,7 +16,7 @@ RESOURCES = os.path.join(HERE, "kernel_resources.json")
 # su2fft_kernels.hip is the one translation unit of the transform kernels: it
 # includes su2fft_ring.hip, su2fft_ring_fast.hip, su2fft_beta.hip and
 # su2fft_beta_bf16.hip and adds the work-list kernels of mixed plans
-SOURCES = ["su2fft_host.hip", "su2fft_kernels.hip", "su2fft_table.hip"]
+SOURCES = ["su2fft_host.hip", "su2fft_kernels.hip", "su2fft_table.hip", "su2fft_calib.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -135,3 +135,21 @@ def test_valid_plan_without_device_reports_no_device():
     else:
         assert st == 5, f"expected SU2_ERR_NO_DEVICE, got {st}"
         assert not h.value
+
+
+def test_calibration_arguments_validated_before_any_device_call():
+    lib = _lib()
+    vp = ctypes.c_void_p
+    p16, p32, p8 = vp(1 << 20), vp((1 << 20) + (1 << 16)), vp((1 << 20) + 8)
+    assert lib.su2_calib_copy(None, p16, 4096, None) == 1
+    assert lib.su2_calib_copy(p16, p32, 0, None) == 1                 # empty
+    assert lib.su2_calib_copy(p16, p32, 4100, None) == 1              # not a multiple of 16
+    assert lib.su2_calib_copy(p8, p32, 4096, None) == 1               # misaligned
+    assert lib.su2_calib_copy(p16, vp((1 << 20) + 4096), 8192, None) == 1   # overlapping ranges
+    assert lib.su2_calib_fill(None, 4096, ctypes.c_float(1.0), None) == 1
+    assert lib.su2_calib_fill(p16, -16, ctypes.c_float(1.0), None) == 1
+    flops = ctypes.c_double()
+    assert lib.su2_calib_mfma(3, 1, 1, p16, ctypes.byref(flops), None) == 1      # unknown kind
+    assert lib.su2_calib_mfma(1, 0, 1, p16, ctypes.byref(flops), None) == 1      # no workgroups
+    assert lib.su2_calib_mfma(1, 1, 0, p16, ctypes.byref(flops), None) == 1      # no iterations
+    assert lib.su2_calib_mfma(1, 1, 1, None, ctypes.byref(flops), None) == 1
