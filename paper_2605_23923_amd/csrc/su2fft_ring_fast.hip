@@ -146,6 +146,31 @@ __device__ __forceinline__ constexpr int kept_row(int i) { return i < N1 / 4 ? i
 template <class T>
 constexpr int fast_waves_per_simd() { return sizeof(T) == 4 ? 4 : 2; }
 
+// Columns (gamma frequencies q) of the alpha transform: thread t's phase-3
+// instance si has q = q0(t) + (NT / N1) si, q0 running over NT / N1 values.
+// DEAL: where a wave's q0 values fit in one half of that range they are dealt
+// out by parity (even q0 in the first half of the threads, odd in the
+// second), so every wave's columns share the parity of q that decides the
+// half-bin shift, which is then a branch per wave rather than a select per
+// lane.  The forward transform deals (its shift comes before the phase-3 DFT;
+// about 2 % faster FP32 forward ring at N = 128); the inverse, whose shift
+// follows the DFT, measured 2 % slower dealt and keeps q0 = t / N1.
+template <int N1, int NT, bool DEAL>
+struct Phase3Cols {
+  static constexpr int QN = NT / N1, H = QN / 2, W = 64 / N1;  // W: q0 values per wave
+  static constexpr bool BY_PARITY = DEAL && W <= H && H % W == 0;
+  __device__ static __forceinline__ int q0(int t) {
+    const int c = t / N1;
+    return BY_PARITY ? 2 * (c % H) + c / H : c;
+  }
+  // 1 when this thread's columns are odd (half-integer n, shifted by half a
+  // bin); never for SO(3) plans (integer n only); wave-uniform when BY_PARITY
+  __device__ static __forceinline__ int parity(int t, int so3) {
+    const int odd = so3 ? 0 : q0(t) & 1;
+    return BY_PARITY ? __builtin_amdgcn_readfirstlane(odd) : odd;
+  }
+};
+
 // multiply by e^{i pi j / N2} (the half-bin shift at node j of an N2-point
 // transform) with the root as a compile-time constant
 template <class T, int N2, int J, int SIGN>
@@ -163,6 +188,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
                                                        const FastRingParams<T>& p, int b, int k,
                                                        unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  typedef Phase3Cols<N1, NT, true> P3;
   constexpr int N = G::N;
   constexpr int RR = REAL ? 1 : ROUNDS;  // q slices formed after the gamma transform
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
@@ -221,8 +247,8 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
 
   // ---- exchange 2 (by q slices) and phase 3: radix-N2 over j2 with the half-bin shift
   const int j1 = t % N1;
-  // every phase-3 instance of this thread has q of the same parity: (t / N1) & 1
-  const int odd = p.so3 ? 0 : (t / N1) & 1;  // SO(3): integer n, no half-bin shift
+  // every phase-3 instance of this thread has q of the parity of q0(t)
+  const int odd = P3::parity(t, p.so3);
   cpx<T> tw3[N2];  // e^{2 pi i (p2 + delta) j1 / N}
 #pragma unroll
   for (int p2 = 0; p2 < N2; p2++) tw3[p2] = tw[((2 * p2 + odd) * j1) % (2 * N)];
@@ -240,7 +266,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int q = t / N1 + (NT / N1) * si;
+      const int q = P3::q0(t) + (NT / N1) * si;
 #pragma unroll
       for (int j2 = 0; j2 < N2; j2++) a[si][j2] = buf[(q - r * G::QR) * G::P2 + j1 + N1 * j2];
     }
@@ -282,7 +308,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int qq = t / N1 + (NT / N1) * si;
+      const int qq = P3::q0(t) + (NT / N1) * si;
 #pragma unroll
       for (int pp = 0; pp < N2; pp++) buf[((qq - r * G::QR) * N2 + pp) * G::P3 + j1] = a[si][pp];
     }
@@ -312,6 +338,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
                                                        const FastRingParams<T>& p, int b, int k,
                                                        unsigned char* smem_raw, int t) {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  typedef Phase3Cols<N1, NT, false> P3;
   constexpr int N = G::N;
   static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -382,14 +409,14 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int qq = t / N1 + (NT / N1) * si;
+      const int qq = P3::q0(t) + (NT / N1) * si;
 #pragma unroll
       for (int pp = 0; pp < N2; pp++) a[si][pp] = buf[((qq - r * G::QR) * N2 + pp) * G::P3 + j1];
     }
   }
 
   // ---- phase 3': conj twiddle, radix-N2 over p2 -> j2, times e^{-2 pi i delta j2 / N2}
-  const int odd = p.so3 ? 0 : (t / N1) & 1;  // SO(3): integer n, no half-bin shift
+  const int odd = P3::parity(t, p.so3);
   cpx<T> tw3[N2];
 #pragma unroll
   for (int pp = 0; pp < N2; pp++) tw3[pp] = tw[((2 * pp + odd) * j1) % (2 * N)];
@@ -419,7 +446,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
-      const int q = t / N1 + (NT / N1) * s;
+      const int q = P3::q0(t) + (NT / N1) * s;
 #pragma unroll
       for (int j2 = 0; j2 < N2; j2++) buf[q * G::P2 + j1 + N1 * j2] = a[s][j2];
     }
@@ -446,7 +473,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
       const int si = r * (G::I1 / ROUNDS) + s;
-      const int q = t / N1 + (NT / N1) * si;
+      const int q = P3::q0(t) + (NT / N1) * si;
 #pragma unroll
       for (int j2 = 0; j2 < N2; j2++) buf[(q - r * G::QR) * G::P2 + j1 + N1 * j2] = a[si][j2];
     }
