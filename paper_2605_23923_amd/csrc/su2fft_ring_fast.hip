@@ -323,9 +323,14 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
     for (int i = 0; i < N1 / 2; i++)
       if (ent[i] >= 0) buf[(ent[i] >> 2) - pb] = ipow_scale(h[kept_row<N1>(i)], ent[i] & 3, Wk);
     __syncthreads();
-    for (int pi = pb + t; pi < pe; pi += NT) {
-      const int tile = pi / PT;
-      S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] = buf[pi - pb];
+    // pairs pi = pb + t + NT i: NT pairs are NT / PT whole tiles apart, so
+    // each step moves the address by a fixed stride
+    static_assert(NT % PT == 0, "whole tiles per step");
+    if (pb + t < pe) {
+      const int tile0 = (pb + t) / PT;
+      cpx<T>* dst = S + (((size_t)tile0 * N + k) * p.batch + b) * PT + (pb + t - tile0 * PT);
+      const size_t step = (size_t)(NT / PT) * N * p.batch * PT;
+      for (int pi = pb + t; pi < pe; pi += NT, dst += step) *dst = buf[pi - pb];
     }
   }
 }
@@ -356,12 +361,15 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
   for (int r = 0; r < SR; r++) {
     const int pb = p.rbeg[r], pe = p.rend[r];
+    // pairs pi = pb + t + NT i: NT pairs are NT / PT whole tiles apart, so
+    // each step moves the address by a fixed stride
+    static_assert(NT % PT == 0, "whole tiles per step");
+    const int tile0 = (pb + t) / PT;
+    const cpx<T>* src = S + (((size_t)tile0 * N + k) * p.batch + b) * PT + (pb + t - tile0 * PT);
+    const size_t step = (size_t)(NT / PT) * N * p.batch * PT;
 #pragma unroll
-    for (int i = 0; i < SPR; i++) {
-      const int pi = pb + t + NT * i;
-      const int tile = pi / PT;
-      sv[r][i] = pi < pe ? S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] : cpx<T>{T(0), T(0)};
-    }
+    for (int i = 0; i < SPR; i++)
+      sv[r][i] = pb + t + NT * i < pe ? src[i * step] : cpx<T>{T(0), T(0)};
   }
   cpx<T> a[G::I1][N2];
   // REAL: only the first q slice is transformed along alpha; the gamma
