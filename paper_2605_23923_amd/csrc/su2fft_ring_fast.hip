@@ -338,40 +338,84 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
 // REAL: the output ring is real.  Only the first q slice's pairs (2m >= 0)
 // hold spectra; every bin reads its pair's value or the conjugate of its
 // mirror pair's (bins_real), and only the real part is written.
-template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL = false>
-__device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, void* __restrict__ xov,
-                                                       const FastRingParams<T>& p, int b, int k,
-                                                       unsigned char* smem_raw, int t) {
+// Shapes of the inverse ring's per-thread inputs: the retained spectra of
+// the ring's q slices (SR slices of SPR values; REAL: both rounds read the
+// first slice) and the phase-4' bin entries of each of the RA rounds.
+template <int N1, int N2, int NT, int ROUNDS, bool REAL>
+struct InvShape {
   typedef FastGeom<N1, N2, NT, ROUNDS> G;
-  typedef Phase3Cols<N1, NT, false> P3;
-  constexpr int N = G::N;
-  static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = buf + G::BUF;
-  for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
-  const T scale = p.adjoint ? p.W[k] : T(1);
-  const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
+  static constexpr int SR = REAL ? 1 : ROUNDS, SPR = G::SLICE_PER_THREAD, RA = REAL ? 1 : ROUNDS;
+};
 
-  // ---- the retained bins of both slices are fetched up front (one exposed
-  //      latency per ring); then per round: stage the slice in LDS, gather,
-  //      phase 4' (radix-N1 over p1 -> j1), exchange 3' (write)
-  constexpr int SPR = G::SLICE_PER_THREAD;
-  constexpr int SR = REAL ? 1 : ROUNDS;  // distinct slices held (REAL: both rounds read the first)
-  cpx<T> sv[SR][SPR];
+// This thread's phase-4' bin entries (column q = t / N2 + (NT / N2) r, row
+// p2 = t mod N2): the same for every ring of a plan.
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL>
+__device__ __forceinline__ void ring_inverse_fast_entries(const FastRingParams<T>& p,
+                                                          int (&ent)[InvShape<N1, N2, NT, ROUNDS, REAL>::RA][N1 / 2],
+                                                          int t) {
+  constexpr int N = N1 * N2;
+  const int* bins = REAL ? p.bins_real : p.bins;
 #pragma unroll
-  for (int r = 0; r < SR; r++) {
+  for (int r = 0; r < InvShape<N1, N2, NT, ROUNDS, REAL>::RA; r++) {
+    const int q = t / N2 + (NT / N2) * r;
+#pragma unroll
+    for (int i = 0; i < N1 / 2; i++) ent[r][i] = bins[q * N + t % N2 + N2 * kept_row<N1>(i)];
+  }
+}
+
+// The retained spectra of ring (b, k) in slices [r0, r1), and (with_scale)
+// the ring's scale (W_k for the adjoint, else 1).  Every thread issues the
+// same loads: an index past its slice reads the slice's first pair and the
+// value is replaced by zero, so the compiler counts the loads in flight
+// exactly when it places its waits.
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL>
+__device__ __forceinline__ void ring_inverse_fast_gather(
+    const cpx<T>* __restrict__ S, const FastRingParams<T>& p, int b, int k,
+    cpx<T> (&sv)[InvShape<N1, N2, NT, ROUNDS, REAL>::SR][InvShape<N1, N2, NT, ROUNDS, REAL>::SPR], T& scale,
+    int t, int r0 = 0, int r1 = InvShape<N1, N2, NT, ROUNDS, REAL>::SR, bool with_scale = true) {
+  typedef InvShape<N1, N2, NT, ROUNDS, REAL> SH;
+  constexpr int N = N1 * N2, SPR = SH::SPR;
+  if (with_scale) scale = p.adjoint ? p.W[k] : T(1);
+#pragma unroll
+  for (int r = 0; r < SH::SR; r++) {
+    if (r < r0 || r >= r1) continue;
     const int pb = p.rbeg[r], pe = p.rend[r];
     // pairs pi = pb + t + NT i: NT pairs are NT / PT whole tiles apart, so
     // each step moves the address by a fixed stride
     static_assert(NT % PT == 0, "whole tiles per step");
     const int tile0 = (pb + t) / PT;
     const cpx<T>* src = S + (((size_t)tile0 * N + k) * p.batch + b) * PT + (pb + t - tile0 * PT);
-    const size_t step = (size_t)(NT / PT) * N * p.batch * PT;
+    // the slice's first pair, relative to src (the offset is selected, not
+    // the pointer, so that each value is one load)
+    const long long first = (long long)((((size_t)(pb / PT) * N + k) * p.batch + b) * PT + (pb - pb / PT * PT)) -
+                            (long long)((((size_t)tile0 * N + k) * p.batch + b) * PT + (pb + t - tile0 * PT));
+    const long long step = (long long)(NT / PT) * N * p.batch * PT;
 #pragma unroll
-    for (int i = 0; i < SPR; i++)
-      sv[r][i] = pb + t + NT * i < pe ? src[i * step] : cpx<T>{T(0), T(0)};
+    for (int i = 0; i < SPR; i++) {
+      const bool in = pb + t + NT * i < pe;
+      const cpx<T> v = src[in ? i * step : first];
+      sv[r][i] = in ? v : cpx<T>{T(0), T(0)};
+    }
   }
-  cpx<T> a[G::I1][N2];
+}
+
+// Phases 4' to 1' of one ring from its gathered spectra; the output ring is
+// left in a (a[s][l2] is sample (j, l1 + N1 l2), j = t / N1 + (NT / N1) s,
+// l1 = t mod N1).  buf is the exchange buffer and tw the table e^{i pi t / N}
+// already in LDS; the first barrier orders buf against earlier use.
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL>
+__device__ __forceinline__ void ring_inverse_fast_transform(
+    const cpx<T> (&sv)[InvShape<N1, N2, NT, ROUNDS, REAL>::SR][InvShape<N1, N2, NT, ROUNDS, REAL>::SPR],
+    const int (&entr)[InvShape<N1, N2, NT, ROUNDS, REAL>::RA][N1 / 2], T scale, const FastRingParams<T>& p,
+    cpx<T>* buf, const cpx<T>* tw, cpx<T> (&a)[N1 * N2 * N1 / NT][N2], int t) {
+  typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  typedef Phase3Cols<N1, NT, false> P3;
+  constexpr int N = G::N;
+  static_assert(ROUNDS == FAST_ROUNDS, "pair ranges are given per round");
+  constexpr int SPR = G::SLICE_PER_THREAD;
+  const int p2 = t % N2, j1 = t % N1, jr = t % N, l1 = t % N1;
+  // per round: stage the slice in LDS, gather the bins, phase 4' (radix-N1
+  // over p1 -> j1), exchange 3' (write)
   // REAL: only the first q slice is transformed along alpha; the gamma
   // frequencies of the second slice are the conjugates of the first's
   // (G[j][N - q] = conj(G[j][q]) for a real ring), taken in exchange 2'
@@ -382,10 +426,7 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
     const int pb = p.rbeg[rs], pe = p.rend[rs];
     static_assert(G::I2 / ROUNDS == 1, "one phase-4 instance per round");
     const int q = t / N2 + (NT / N2) * r;
-    int ent[N1 / 2];
-    const int* bins = REAL ? p.bins_real : p.bins;
-#pragma unroll
-    for (int i = 0; i < N1 / 2; i++) ent[i] = bins[q * N + p2 + N2 * kept_row<N1>(i)];
+    const int* ent = entr[r];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SPR; i++)
@@ -525,6 +566,19 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
 #pragma unroll
     for (int q2 = 1; q2 < N2; q2++) a[s][q2] = cmulc(a[s][q2], tw1[q2]);
     dftr<T, N2, -1>(a[s]);
+  }
+}
+
+// The output ring held in a (as ring_inverse_fast_transform leaves it) to
+// the samples xov: coalesced rows, non-temporal stores (REAL: real parts).
+template <class T, int N1, int N2, int NT, bool REAL>
+__device__ __forceinline__ void ring_inverse_fast_store(const cpx<T> (&a)[N1 * N2 * N1 / NT][N2],
+                                                        void* __restrict__ xov, int t) {
+  constexpr int N = N1 * N2;
+  const int l1 = t % N1;
+#pragma unroll
+  for (int s = 0; s < N * N1 / NT; s++) {
+    const int j = t / N1 + (NT / N1) * s;
 #pragma unroll
     for (int l2 = 0; l2 < N2; l2++) {
       if constexpr (REAL)
@@ -533,6 +587,25 @@ __device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict_
         st_stream(reinterpret_cast<cpx<T>*>(xov) + j * N + l1 + N1 * l2, a[s][l2]);
     }
   }
+}
+
+template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL = false>
+__device__ __forceinline__ void ring_inverse_fast_body(const cpx<T>* __restrict__ S, void* __restrict__ xov,
+                                                       const FastRingParams<T>& p, int b, int k,
+                                                       unsigned char* smem_raw, int t) {
+  typedef FastGeom<N1, N2, NT, ROUNDS> G;
+  typedef InvShape<N1, N2, NT, ROUNDS, REAL> SH;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + G::BUF;
+  for (int i = t; i < 2 * G::N; i += NT) tw[i] = p.tw[i];
+  cpx<T> sv[SH::SR][SH::SPR];
+  T scale;
+  ring_inverse_fast_gather<T, N1, N2, NT, ROUNDS, REAL>(S, p, b, k, sv, scale, t);
+  int ent[SH::RA][N1 / 2];
+  ring_inverse_fast_entries<T, N1, N2, NT, ROUNDS, REAL>(p, ent, t);
+  cpx<T> a[G::I1][N2];
+  ring_inverse_fast_transform<T, N1, N2, NT, ROUNDS, REAL>(sv, ent, scale, p, buf, tw, a, t);
+  ring_inverse_fast_store<T, N1, N2, NT, REAL>(a, xov, t);
 }
 
 // Split of the N-point transforms and threads per ring for each supported N
@@ -610,6 +683,55 @@ __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_invers
   ring_inverse_fast_group<T, N, REAL>(S, samples, p, b, ring0 - b * N, smem_raw, threadIdx.x);
 }
 
+// N = 128 inverse, two rings per workgroup (nodes k0, k0 + 1 of one
+// signal).  The second ring's spectra are requested after the first ring's
+// transform and before its sample stores, so their latency hides behind the
+// stores, and the first ring's stores drain while the second ring is
+// transformed (a workgroup keeps its slot until its stores have completed).
+// The bin entries are the same for both rings.  Used for FP64, where a CU
+// holds a single workgroup (0.449 -> 0.419 ms at B = 64 batch 32); FP32 rings
+// run two workgroups per CU, which already cover these latencies (measured
+// no change), and keep one ring per workgroup.
+template <class T, bool REAL>
+__global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_inverse_fast_pair(
+    const cpx<T>* __restrict__ S, void* __restrict__ samples, FastRingParams<T> p) {
+  typedef FastRing<T, 128> R;
+  typedef FastCfg<128> C;
+  constexpr int N1 = C::N1, N2 = C::N2, NT = C::NTR, N = 128;
+  typedef InvShape<N1, N2, NT, FAST_ROUNDS, REAL> SH;
+  typedef typename std::conditional<REAL, T, cpx<T>>::type E;
+  static_assert(R::RPW == 1 && NT == FAST_NT, "one ring per workgroup pass");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = buf + R::G::BUF;
+  const int t = threadIdx.x;
+  for (int i = t; i < 2 * N; i += NT) tw[i] = p.tw[i];
+  const int ring0 = 2 * blockIdx.x, b = ring0 / N, k0 = ring0 - b * N;  // N even: k0 + 1 < N
+  E* xo = reinterpret_cast<E*>(samples) + ring_offset(p.soff, b, N);
+  cpx<T> sv[SH::SR][SH::SPR];
+  T scale;
+  ring_inverse_fast_gather<T, N1, N2, NT, FAST_ROUNDS, REAL>(S, p, b, k0, sv, scale, t);
+  int ent[SH::RA][N1 / 2];
+  ring_inverse_fast_entries<T, N1, N2, NT, FAST_ROUNDS, REAL>(p, ent, t);
+  cpx<T> a[R::G::I1][N2];
+  ring_inverse_fast_transform<T, N1, N2, NT, FAST_ROUNDS, REAL>(sv, ent, scale, p, buf, tw, a, t);
+  // a copy of the thread index the compiler cannot see through, so that the
+  // second ring's addresses are formed where they are used rather than held
+  // in registers across the first ring
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  // the second ring's first slice before the first ring's stores (all of it
+  // would not fit the register budget beside the first ring's output), the
+  // rest after them
+  ring_inverse_fast_gather<T, N1, N2, NT, FAST_ROUNDS, REAL>(S, p, b, k0 + 1, sv, scale, t2, 0, 1);
+  __builtin_amdgcn_sched_barrier(0);
+  ring_inverse_fast_store<T, N1, N2, NT, REAL>(a, xo + (size_t)k0 * N * N, t);
+  __builtin_amdgcn_sched_barrier(0);
+  ring_inverse_fast_gather<T, N1, N2, NT, FAST_ROUNDS, REAL>(S, p, b, k0 + 1, sv, scale, t2, 1, SH::SR, false);
+  ring_inverse_fast_transform<T, N1, N2, NT, FAST_ROUNDS, REAL>(sv, ent, scale, p, buf, tw, a, t2);
+  ring_inverse_fast_store<T, N1, N2, NT, REAL>(a, xo + (size_t)(k0 + 1) * N * N, t2);
+}
+
 template <class T>
 bool fast_ring_supported(int N) {
   return N == 16 || N == 32 || N == 64 || N == 128;
@@ -661,6 +783,16 @@ static hipError_t launch_fast(bool forward, bool real, const FastRingParams<T>& 
                               hipStream_t s) {
   typedef FastRing<T, N> R;
   if (!slices_fit<T, N>(p) || (real && !p.bins_real)) return hipErrorInvalidValue;
+  if constexpr (N == 128 && std::is_same<T, double>::value) {
+    if (!forward) {  // two rings per workgroup (a signal's N rings pair up)
+      const void* kern = real ? (const void*)ring_inverse_fast_pair<T, true> : (const void*)ring_inverse_fast_pair<T, false>;
+      hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)R::SMEM);
+      if (e != hipSuccess) return e;
+      FastRingParams<T> pp = p;
+      void* args[] = {(void*)&in, (void*)&out, (void*)&pp};
+      return hipLaunchKernel(kern, dim3((unsigned)((long long)p.batch * N / 2)), dim3(FAST_NT), args, R::SMEM, s);
+    }
+  }
   const void* kern =
       forward ? (real ? (const void*)ring_forward_fast<T, N, true> : (const void*)ring_forward_fast<T, N, false>)
               : (real ? (const void*)ring_inverse_fast<T, N, true> : (const void*)ring_inverse_fast<T, N, false>);
