@@ -51,6 +51,8 @@ def kernel_name(stage: str, mode: str) -> str:
     """Name of the kernel that runs `stage` at B=64, as rocprofv3 lists it (template type kept)."""
     t = "double" if base_mode(mode) == "c128" else "float"
     if stage.startswith("ring"):
+        if stage != "ring_forward" and t == "double":
+            return "ring_inverse_fast_pair<double>"   # FP64 inverse: two rings per workgroup
         return f"ring_{'forward' if stage == 'ring_forward' else 'inverse'}_fast<{t}>"
     kind = "forward" if stage == "beta_forward" else "inverse"
     if mode == "c64_bf16x3":
