@@ -166,7 +166,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kerne
     if constexpr (RTMAX_MAX >= 2)
       if (g.rtmax == 2) beta_forward_bf16x3_body<2>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     if constexpr (RTMAX_MAX >= 4)
-      if (g.rtmax == 4) beta_forward_bf16x3_body<4>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
+      if (g.rtmax == 4) beta_forward_bf16x3_body<4, false>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     __syncthreads();
   }
 }
