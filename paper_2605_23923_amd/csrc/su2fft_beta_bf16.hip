@@ -243,13 +243,15 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
 // in blocks of 16 (the table words of the next block requested before the
 // current block's products) and staged through LDS so that S is written in
 // whole 16-pair rows, by buffer stores that stay in flight across the next
-// block's products.
-template <int LQ>
+// block's products.  BT signals per workgroup: 32, or 16 for batches of at
+// most 16, which would leave half of a 32-signal tile's columns empty.
+template <int LQ, int BT = XB_BT>
 __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __restrict__ coeffs,
                                                          cpx<float>* __restrict__ S, const BetaParams<float>& p,
                                                          const unsigned* __restrict__ tabi, int tile, int bt,
                                                          unsigned char* smem, int tid) {
-  constexpr int BT = XB_BT, CT = 2 * BT / 16;
+  constexpr int CT = 2 * BT / 16;
+  static_assert(BT == 16 || BT == 32, "signal tile");
   constexpr int PB = 2 * PT + 2;
   float* stage = reinterpret_cast<float*>(smem);
   const int b0 = bt * BT;
@@ -378,13 +380,13 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
   }
 }
 
-template <int LQ>
+template <int LQ, int BT>
 __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const cpx<float>* __restrict__ coeffs,
                                                                          cpx<float>* __restrict__ S,
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_bf16x3_body<LQ>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Reorder the tile-major split table into the node-interleaved forward layout.
@@ -431,17 +433,22 @@ hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned
 
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s) {
-  dim3 grid(p.ntiles, (p.batch + XB_BT - 1) / XB_BT);
+  const bool narrow = p.batch <= 16;  // 16-signal tiles
+  const int bt = narrow ? 16 : XB_BT;
+  dim3 grid(p.ntiles, (p.batch + bt - 1) / bt);
   const int lq2 = beta_bf16_lq(p.B);
   hipError_t e;
-#define SU2_XBI_CASE(Q)                                                                                           \
-  if (lq2 == Q) {                                                                                                 \
-    if ((e = set_smem_bf(beta_inverse_bf16x3_kernel<Q>, XBI_SMEM)) != hipSuccess) return e;                       \
-    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<Q>), grid, dim3(XB_THREADS), XBI_SMEM, s, coeffs, S, p, tabi); \
-    return hipGetLastError();                                                                                     \
+#define SU2_XBI_CASE(Q, BTC)                                                                                  \
+  if (lq2 == Q && bt == BTC) {                                                                                \
+    if ((e = set_smem_bf(beta_inverse_bf16x3_kernel<Q, BTC>, XBI_SMEM)) != hipSuccess) return e;              \
+    hipLaunchKernelGGL((beta_inverse_bf16x3_kernel<Q, BTC>), grid, dim3(XB_THREADS), XBI_SMEM, s, coeffs, S, p, \
+                       tabi);                                                                                 \
+    return hipGetLastError();                                                                                 \
   }
-  SU2_XBI_CASE(1)
-  SU2_XBI_CASE(2)
+  SU2_XBI_CASE(1, XB_BT)
+  SU2_XBI_CASE(2, XB_BT)
+  SU2_XBI_CASE(1, 16)
+  SU2_XBI_CASE(2, 16)
 #undef SU2_XBI_CASE
   return hipErrorInvalidValue;
 }
