@@ -319,6 +319,14 @@ def secondary_configs(steps: int, warmup: int):
                                                1, batch)
     out["b128_batch16_c64_tables_on_the_fly"] = run_whole(lambda: su2.Plan(B, batch, "c64", tables="on_the_fly"),
                                                          x, c, max(2, steps // 5), 1, batch)
+    # the same shape with the plain FP32 contraction (stored table), beside the split-BF16 one
+    out["b128_batch16_c64"] = run_whole(lambda: su2.Plan(B, batch, "c64"), x, c, max(2, steps // 5), 1, batch)
+    del x, c
+    torch.cuda.empty_cache()
+    # and in FP64 throughout
+    x = torch.from_numpy(synth.samples_uniform(B, batch, seed=4, dtype=np.complex128)).to("cuda")
+    c = torch.from_numpy(synth.coeffs(B, batch, seed=4, dtype=np.complex128)).to("cuda")
+    out["b128_batch16_c128"] = run_whole(lambda: su2.Plan(B, batch, "c128"), x, c, max(2, steps // 5), 1, batch)
     del x, c
     torch.cuda.empty_cache()
     return out

@@ -370,17 +370,20 @@ constexpr int INV_THREADS = 512;
 template <class T>
 struct InvStage {
   static constexpr int PB = 2 * PT + 2;
-  static constexpr int NRS = BetaCfg<T>::BT * PB + 4;
+  static constexpr int NRS = BetaCfg<T>::BT * PB + 4;  // sized for the widest signal tile
 };
 
 template <class T>
 constexpr size_t inverse_smem() { return (size_t)16 * InvStage<T>::NRS * sizeof(T); }
 
-template <class T, int LQ>
+// BT signals per workgroup: BetaCfg<T>::BT, or 16 for FP32 batches of at
+// most 16, which would leave half of a 32-signal tile's columns empty.
+template <class T, int LQ, int BT = BetaCfg<T>::BT>
 __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
                                                   const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
   typedef typename acc4<T>::type accT;
-  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int CT = 2 * BT / 16;
+  static_assert(BT <= BetaCfg<T>::BT && BT % 8 == 0, "signal tile");
   constexpr int PB = InvStage<T>::PB, NRS = InvStage<T>::NRS;
   T* stage = reinterpret_cast<T*>(smem);
   const int b0 = bt * BT;
@@ -507,11 +510,11 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   }
 }
 
-template <class T, int LQ>
+template <class T, int LQ, int BT>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
                                                                    cpx<T>* __restrict__ S, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_body<T, LQ>(coeffs, S, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_inverse_body<T, LQ, BT>(coeffs, S, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)
@@ -560,22 +563,29 @@ hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* 
 
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
-  constexpr int BT = BetaCfg<T>::BT;
-  dim3 grid(p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
+  constexpr int BTW = BetaCfg<T>::BT;                             // widest signal tile
+  constexpr int BTN = BTW > 16 ? 16 : BTW;                         // for batches of at most 16
+  const int bt = p.batch <= BTN ? BTN : BTW;
+  dim3 grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt);
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);
   hipError_t e;
-#define SU2_INV_CASE(Q)                                                                             \
-  if (lq == Q) {                                                                                    \
-    if ((e = set_smem(beta_inverse_kernel<T, Q>, smem)) != hipSuccess) \
-      return e;                                                                                     \
-    hipLaunchKernelGGL((beta_inverse_kernel<T, Q>), grid, dim3(INV_THREADS), smem, s, coeffs, S, p); \
-    return hipGetLastError();                                                                       \
+#define SU2_INV_CASE(Q, BTC)                                                                            \
+  if (lq == Q && bt == BTC) {                                                                           \
+    if ((e = set_smem(beta_inverse_kernel<T, Q, BTC>, smem)) != hipSuccess) return e;                   \
+    hipLaunchKernelGGL((beta_inverse_kernel<T, Q, BTC>), grid, dim3(INV_THREADS), smem, s, coeffs, S, p); \
+    return hipGetLastError();                                                                           \
   }
-  SU2_INV_CASE(2)
-  SU2_INV_CASE(4)
-  SU2_INV_CASE(8)
-  SU2_INV_CASE(16)
+  SU2_INV_CASE(2, BTW)
+  SU2_INV_CASE(4, BTW)
+  SU2_INV_CASE(8, BTW)
+  SU2_INV_CASE(16, BTW)
+  if constexpr (BTN != BTW) {
+    SU2_INV_CASE(2, BTN)
+    SU2_INV_CASE(4, BTN)
+    SU2_INV_CASE(8, BTN)
+    SU2_INV_CASE(16, BTN)
+  }
 #undef SU2_INV_CASE
   return hipErrorInvalidValue;
 }

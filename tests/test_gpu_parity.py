@@ -79,6 +79,19 @@ def test_inverse_and_adjoint_match_oracle(B, dtype):
             _check(ga[b].reshape(-1)[pts], oracle.adjoint(B, c[b], pts), TOL[dtype], f"adjoint B={B} {dtype} s{b}")
 
 
+@pytest.mark.parametrize("B,batch", [(8, 21), (12, 45)])
+def test_c64_inverse_partial_wide_signal_tile(B, batch):
+    """Batches above 16 take the 32-signal FP32 inverse tiles (batches of at
+    most 16 take 16-signal tiles); here the last tile is partial."""
+    c = synth.coeffs(B, batch, seed=300 + batch, dtype=np.complex64)
+    plan = su2.Plan(B, batch, "c64")
+    gi = _host(plan.inverse(_dev(c)))
+    ga = _host(plan.adjoint(_dev(c)))
+    for b in (0, batch // 2, batch - 1):
+        _check(gi[b], oracle.inverse(B, c[b]), TOL["c64"], f"inverse B={B} batch {batch} s{b}")
+        _check(ga[b], oracle.adjoint(B, c[b]), TOL["c64"], f"adjoint B={B} batch {batch} s{b}")
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_b32_several_rings_per_workgroup_sampled(dtype):
     """B = 32 (N = 64, four rings per ring-kernel workgroup), odd batch: sampled
