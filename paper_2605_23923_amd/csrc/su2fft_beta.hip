@@ -174,10 +174,10 @@ constexpr int FWD_THREADS = 512;
 template <class T>
 constexpr int fwd_kc_default() { return sizeof(T) == 4 ? 4 : 8; }
 
-template <class T, int RTMAX, int KC_ = fwd_kc_default<T>()>
+template <class T, int RTMAX, int KC_ = fwd_kc_default<T>(), int BT_ = BetaCfg<T>::BT>
 struct FwdGeom {
   static constexpr int KC = KC_;
-  static constexpr int BT = BetaCfg<T>::BT;
+  static constexpr int BT = BT_;
   static constexpr int PB = 2 * PT + 2;
   static constexpr int PK = BT * PB + 16;
   static constexpr int TMAX = PT * 16 * RTMAX;
@@ -190,11 +190,13 @@ struct FwdGeom {
   static constexpr size_t SMEM = SMEM_LOOP > SMEM_EPI ? SMEM_LOOP : SMEM_EPI;
 };
 
-template <class T, int RTMAX, int KC_ = fwd_kc_default<T>()>
+// BT_ signals per workgroup: BetaCfg<T>::BT, or 16 for FP32 batches of at
+// most 16, which would leave half of a 32-signal tile's columns empty.
+template <class T, int RTMAX, int KC_ = fwd_kc_default<T>(), int BT_ = BetaCfg<T>::BT>
 __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
                                                   const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
   typedef typename acc4<T>::type accT;
-  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int BT = BT_, CT = 2 * BT / 16;
   constexpr int KC = KC_;
   constexpr int PB = 2 * PT + 2;            // reals per (node, signal) row: 16 pairs x (re, im) + pad
   constexpr int PK = BT * PB + 16;          // reals per node
@@ -324,7 +326,7 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   // all 16 pairs per round; each wave parks the rows of its two pairs that
   // fall in the round
   typedef CoefRound<T, BT, FWD_THREADS> CR;
-  static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX, KC>::SMEM, "coefficient rounds fit");
+  static_assert(CR::ELEMS * sizeof(T) <= FwdGeom<T, RTMAX, KC, BT>::SMEM, "coefficient rounds fit");
   T* cst = reinterpret_cast<T*>(smem);
 #pragma unroll
   for (int j0 = 0; j0 < 16 * RTMAX; j0 += CR::JC) {
@@ -348,11 +350,11 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
   }
 }
 
-template <class T, int RTMAX, int KC>
+template <class T, int RTMAX, int KC, int BT>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_body<T, RTMAX, KC>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_forward_body<T, RTMAX, KC, BT>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
@@ -523,17 +525,17 @@ static hipError_t set_smem(K kern, size_t smem) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
 }
 
-template <class T, int RTMAX, int KC>
+template <class T, int RTMAX, int KC, int BT>
 static hipError_t launch_forward_shape(const BetaParams<T>& p, dim3 grid, const cpx<T>* S, cpx<T>* coeffs,
                                        hipStream_t s) {
-  constexpr size_t smem = FwdGeom<T, RTMAX, KC>::SMEM;
+  constexpr size_t smem = FwdGeom<T, RTMAX, KC, BT>::SMEM;
   hipError_t e;
-  if ((e = set_smem(beta_forward_kernel<T, RTMAX, KC>, smem)) != hipSuccess) return e;
-  hipLaunchKernelGGL((beta_forward_kernel<T, RTMAX, KC>), grid, dim3(FWD_THREADS), smem, s, S, coeffs, p);
+  if ((e = set_smem(beta_forward_kernel<T, RTMAX, KC, BT>, smem)) != hipSuccess) return e;
+  hipLaunchKernelGGL((beta_forward_kernel<T, RTMAX, KC, BT>), grid, dim3(FWD_THREADS), smem, s, S, coeffs, p);
   return hipGetLastError();
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int BT>
 static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx<T>* S, cpx<T>* coeffs,
                                     hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
@@ -546,19 +548,26 @@ static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx
                                                    hipSuccess || cus < 1)
         cus = 256;
     }
-    if (2LL * grid.x * grid.y >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4>(p, grid, S, coeffs, s);
+    if (2LL * grid.x * grid.y >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
   }
-  return launch_forward_shape<T, RTMAX, 8>(p, grid, S, coeffs, s);
+  return launch_forward_shape<T, RTMAX, 8, BT>(p, grid, S, coeffs, s);
 }
 
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
-  constexpr int BT = BetaCfg<T>::BT;
-  dim3 grid(p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
+  constexpr int BTW = BetaCfg<T>::BT;      // widest signal tile
+  constexpr int BTN = BTW > 16 ? 16 : BTW;  // for batches of at most 16
   const int rt = beta_rtmax(p.B);
-  if (rt == 1) return launch_forward_rt<T, 1>(p, grid, S, coeffs, s);
-  if (rt == 2) return launch_forward_rt<T, 2>(p, grid, S, coeffs, s);
-  return launch_forward_rt<T, 4>(p, grid, S, coeffs, s);
+  if (BTN != BTW && p.batch <= BTN) {
+    dim3 grid(p.ntiles - p.tile0, (p.batch + BTN - 1) / BTN);
+    if (rt == 1) return launch_forward_rt<T, 1, BTN>(p, grid, S, coeffs, s);
+    if (rt == 2) return launch_forward_rt<T, 2, BTN>(p, grid, S, coeffs, s);
+    return launch_forward_rt<T, 4, BTN>(p, grid, S, coeffs, s);
+  }
+  dim3 grid(p.ntiles - p.tile0, (p.batch + BTW - 1) / BTW);
+  if (rt == 1) return launch_forward_rt<T, 1, BTW>(p, grid, S, coeffs, s);
+  if (rt == 2) return launch_forward_rt<T, 2, BTW>(p, grid, S, coeffs, s);
+  return launch_forward_rt<T, 4, BTW>(p, grid, S, coeffs, s);
 }
 
 template <class T>

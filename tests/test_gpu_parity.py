@@ -80,14 +80,17 @@ def test_inverse_and_adjoint_match_oracle(B, dtype):
 
 
 @pytest.mark.parametrize("B,batch", [(8, 21), (12, 45)])
-def test_c64_inverse_partial_wide_signal_tile(B, batch):
-    """Batches above 16 take the 32-signal FP32 inverse tiles (batches of at
-    most 16 take 16-signal tiles); here the last tile is partial."""
+def test_c64_partial_wide_signal_tile(B, batch):
+    """Batches above 16 take the 32-signal FP32 contraction tiles (batches of
+    at most 16 take 16-signal tiles); here the last tile is partial."""
+    x = synth.samples_uniform(B, batch, seed=400 + batch, dtype=np.complex64)
     c = synth.coeffs(B, batch, seed=300 + batch, dtype=np.complex64)
     plan = su2.Plan(B, batch, "c64")
+    gf = _host(plan.forward(_dev(x)))
     gi = _host(plan.inverse(_dev(c)))
     ga = _host(plan.adjoint(_dev(c)))
     for b in (0, batch // 2, batch - 1):
+        _check(gf[b], oracle.forward(B, x[b]), TOL["c64"], f"forward B={B} batch {batch} s{b}")
         _check(gi[b], oracle.inverse(B, c[b]), TOL["c64"], f"inverse B={B} batch {batch} s{b}")
         _check(ga[b], oracle.adjoint(B, c[b]), TOL["c64"], f"adjoint B={B} batch {batch} s{b}")
 
