@@ -36,9 +36,9 @@ __device__ __forceinline__ double otf_seed(const OtfParams<T>& p, const PairInfo
   return p.seedc[pidx] * powi_d(p.ck[k], pc) * powi_d(p.sk[k], ps);
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int BT_ = BetaCfg<T>::BT>
 struct OtfFwd {
-  static constexpr int BT = BetaCfg<T>::BT;
+  static constexpr int BT = BT_;  // signals per workgroup (16 for FP32 batches of at most 16)
   static constexpr int KC = 8;                 // nodes per S chunk
   static constexpr int PB = 2 * PT + 2;
   static constexpr int PK = BT * PB + 16;
@@ -57,11 +57,11 @@ __device__ __forceinline__ void otf_load_coeffs(double* sC, const double* rcoef,
   for (int j = tid; j < 3 * lsum; j += nthreads) sC[j] = rcoef[3 * row0 + j];
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int BT_ = BetaCfg<T>::BT>
 __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ coeffs,
                                                       const OtfParams<T>& op, int tile, int bt, unsigned char* smem,
                                                       int tid) {
-  typedef OtfFwd<T, RTMAX> G;
+  typedef OtfFwd<T, RTMAX, BT_> G;
   typedef typename acc4<T>::type accT;
   const BetaParams<T>& p = op.b;
   constexpr int BT = G::BT, CT = 2 * BT / 16, KC = G::KC, PB = G::PB, PK = G::PK, GK = G::GK;
@@ -216,22 +216,22 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
   }
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, int BT>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_otf_kernel(const cpx<T>* __restrict__ S,
                                                                        cpx<T>* __restrict__ coeffs, OtfParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_otf_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_forward_otf_body<T, RTMAX, BT>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // Inverse: as beta_inverse_body, with the A operands (node k = k0 + lrow,
 // degree l = 4 s + lk) generated per lane.
-template <class T, int LQ, bool GEN_LDS>
+template <class T, int LQ, bool GEN_LDS, int BT_ = BetaCfg<T>::BT>
 __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
                                                       const OtfParams<T>& op, int tile, int bt, unsigned char* smem,
                                                       int tid) {
   typedef typename acc4<T>::type accT;
   const BetaParams<T>& p = op.b;
-  constexpr int BT = BetaCfg<T>::BT, CT = 2 * BT / 16;
+  constexpr int BT = BT_, CT = 2 * BT / 16;  // BT_: 16 for FP32 batches of at most 16
   constexpr int PB = InvStage<T>::PB, NRS = InvStage<T>::NRS;
   T* stage = reinterpret_cast<T*>(smem);
   double* sC = reinterpret_cast<double*>(smem + inverse_smem<T>());  // the tile's recurrence coefficients
@@ -380,11 +380,11 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
   }
 }
 
-template <class T, int LQ, bool GEN_LDS>
+template <class T, int LQ, bool GEN_LDS, int BT>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_otf_kernel(const cpx<T>* __restrict__ coeffs,
                                                                        cpx<T>* __restrict__ S, OtfParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_otf_body<T, LQ, GEN_LDS>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_inverse_otf_body<T, LQ, GEN_LDS, BT>(coeffs, S, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
 // LDS of the inverse: staging, recurrence coefficients and (GEN_LDS) the
@@ -401,43 +401,56 @@ constexpr bool inverse_gen_lds() { return inverse_otf_smem<T, LQ, true>() <= 160
 
 template <class T>
 hipError_t launch_beta_forward_otf(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
-  constexpr int BT = BetaCfg<T>::BT;
-  const dim3 grid(p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  constexpr int BTW = BetaCfg<T>::BT, BTN = BTW > 16 ? 16 : BTW;  // widest tile; batches of at most 16
+  const int bt = p.b.batch <= BTN ? BTN : BTW;
+  const dim3 grid(p.b.ntiles, (p.b.batch + bt - 1) / bt);
   const int rt = beta_rtmax(p.b.B);
   hipError_t e;
-#define SU2_OTF_FWD(R)                                                                                    \
-  if (rt == R) {                                                                                          \
-    if ((e = set_smem(beta_forward_otf_kernel<T, R>, OtfFwd<T, R>::SMEM)) != hipSuccess) return e;         \
-    hipLaunchKernelGGL((beta_forward_otf_kernel<T, R>), grid, dim3(FWD_THREADS), (OtfFwd<T, R>::SMEM), s, S, \
-                       coeffs, p);                                                                        \
-    return hipGetLastError();                                                                             \
+#define SU2_OTF_FWD(R, BTC)                                                                                     \
+  if (rt == R && bt == BTC) {                                                                                   \
+    if ((e = set_smem(beta_forward_otf_kernel<T, R, BTC>, OtfFwd<T, R, BTC>::SMEM)) != hipSuccess) return e;      \
+    hipLaunchKernelGGL((beta_forward_otf_kernel<T, R, BTC>), grid, dim3(FWD_THREADS), (OtfFwd<T, R, BTC>::SMEM), s, \
+                       S, coeffs, p);                                                                           \
+    return hipGetLastError();                                                                                   \
   }
-  SU2_OTF_FWD(1)
-  SU2_OTF_FWD(2)
-  SU2_OTF_FWD(4)
+  SU2_OTF_FWD(1, BTW)
+  SU2_OTF_FWD(2, BTW)
+  SU2_OTF_FWD(4, BTW)
+  if constexpr (BTN != BTW) {
+    SU2_OTF_FWD(1, BTN)
+    SU2_OTF_FWD(2, BTN)
+    SU2_OTF_FWD(4, BTN)
+  }
 #undef SU2_OTF_FWD
   return hipErrorInvalidValue;
 }
 
 template <class T>
 hipError_t launch_beta_inverse_otf(const OtfParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
-  constexpr int BT = BetaCfg<T>::BT;
-  const dim3 grid(p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  constexpr int BTW = BetaCfg<T>::BT, BTN = BTW > 16 ? 16 : BTW;  // widest tile; batches of at most 16
+  const int bt = p.b.batch <= BTN ? BTN : BTW;
+  const dim3 grid(p.b.ntiles, (p.b.batch + bt - 1) / bt);
   const int lq = beta_lq(p.b.B);
   hipError_t e;
-#define SU2_OTF_INV(Q)                                                                                    \
-  if (lq == Q) {                                                                                          \
-    constexpr bool GL = inverse_gen_lds<T, Q>();                                                          \
-    constexpr size_t smem = inverse_otf_smem<T, Q, GL>();                                                 \
-    if ((e = set_smem(beta_inverse_otf_kernel<T, Q, GL>, smem)) != hipSuccess) return e;                  \
-    hipLaunchKernelGGL((beta_inverse_otf_kernel<T, Q, GL>), grid, dim3(INV_THREADS), smem, s, coeffs, S,  \
-                       p);                                                                                \
-    return hipGetLastError();                                                                             \
+#define SU2_OTF_INV(Q, BTC)                                                                                   \
+  if (lq == Q && bt == BTC) {                                                                                 \
+    constexpr bool GL = inverse_gen_lds<T, Q>();                                                              \
+    constexpr size_t smem = inverse_otf_smem<T, Q, GL>();                                                     \
+    if ((e = set_smem(beta_inverse_otf_kernel<T, Q, GL, BTC>, smem)) != hipSuccess) return e;                 \
+    hipLaunchKernelGGL((beta_inverse_otf_kernel<T, Q, GL, BTC>), grid, dim3(INV_THREADS), smem, s, coeffs, S, \
+                       p);                                                                                    \
+    return hipGetLastError();                                                                                 \
   }
-  SU2_OTF_INV(2)
-  SU2_OTF_INV(4)
-  SU2_OTF_INV(8)
-  SU2_OTF_INV(16)
+  SU2_OTF_INV(2, BTW)
+  SU2_OTF_INV(4, BTW)
+  SU2_OTF_INV(8, BTW)
+  SU2_OTF_INV(16, BTW)
+  if constexpr (BTN != BTW) {
+    SU2_OTF_INV(2, BTN)
+    SU2_OTF_INV(4, BTN)
+    SU2_OTF_INV(8, BTN)
+    SU2_OTF_INV(16, BTN)
+  }
 #undef SU2_OTF_INV
   return hipErrorInvalidValue;
 }

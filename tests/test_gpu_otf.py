@@ -54,7 +54,7 @@ def test_otf_matches_oracle(B, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("B,batch", [(24, 3), (64, 32)])
+@pytest.mark.parametrize("B,batch", [(24, 3), (16, 21), (64, 32)])
 def test_otf_equals_stored_tables(B, batch, dtype):
     x = synth.samples_uniform(B, batch, seed=910, dtype=NPDT[dtype])
     c = synth.coeffs(B, batch, seed=911, spectrum="decay", dtype=NPDT[dtype])
