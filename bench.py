@@ -249,6 +249,29 @@ def run_whole(make_plan, x, c, steps: int, warmup: int, batch: int):
     return info
 
 
+def run_separate(make_plan, x, c, steps: int, warmup: int):
+    """Forward and inverse of one plan timed apart (HIP events, mean over steps)."""
+    import torch
+
+    plan = make_plan()
+    y = plan.forward(x)
+    xi = plan.inverse(c)
+    res = {}
+    for name, fn in (("forward_ms", lambda: plan.forward(x, out=y)), ("inverse_ms", lambda: plan.inverse(c, out=xi))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / steps, 4)
+    plan.close()
+    return res
+
+
 def shifted_forms(steps: int):
     """The forward contraction at B=64 batch 32 (c64 plan) in its three forms:
     the table contraction on the matrix cores, and the shifted-recurrence
@@ -310,6 +333,14 @@ def secondary_configs(steps: int, warmup: int):
     del x, c
     torch.cuda.empty_cache()
     out["b64_batch32_beta_forward_shifted_c64"] = shifted_forms(steps)
+    # one signal at B = 64 (the table, read once per launch, then outweighs the
+    # ring spectra), forward and inverse timed separately, FP32 and FP64
+    for dt, npdt in (("c64", np.complex64), ("c128", np.complex128)):
+        x = torch.from_numpy(synth.samples_uniform(64, 1, seed=2, dtype=npdt)).to("cuda")
+        c = torch.from_numpy(synth.coeffs(64, 1, seed=2, spectrum="decay", dtype=npdt)).to("cuda")
+        out[f"b64_batch1_{dt}"] = run_separate(lambda: su2.Plan(64, 1, dt), x, c, steps, warmup)
+        del x, c
+    torch.cuda.empty_cache()
     # B = 128, batch 16, split-BF16 contraction
     B, batch = 128, 16
     N = 2 * B
