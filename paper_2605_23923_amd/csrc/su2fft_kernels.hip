@@ -47,6 +47,7 @@ template <class T>
 struct GroupDev {
   int fast;               // register-resident ring kernels
   int rtmax, lq, lq2;     // contraction shapes of the group's bandlimit
+  int narrow;             // FP32 group of at most 16 signals: 16-signal contraction tiles
   RingParams<T> rp[3];    // generic ring kernels: forward, inverse, adjoint
   FastRingParams<T> fp[3];
   BetaParams<T> bp[3];    // contraction: forward, inverse, adjoint
@@ -122,11 +123,22 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-    if constexpr (RTMAX_MAX >= 2)
-      if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-    if constexpr (RTMAX_MAX >= 4)
-      if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+    constexpr int KC = fwd_kc_default<T>();
+    if (g.narrow) {
+      if constexpr (BetaCfg<T>::BT > 16) {
+        if (g.rtmax == 1) beta_forward_body<T, 1, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+        if constexpr (RTMAX_MAX >= 2)
+          if (g.rtmax == 2) beta_forward_body<T, 2, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+        if constexpr (RTMAX_MAX >= 4)
+          if (g.rtmax == 4) beta_forward_body<T, 4, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      }
+    } else {
+      if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      if constexpr (RTMAX_MAX >= 2)
+        if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      if constexpr (RTMAX_MAX >= 4)
+        if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+    }
     __syncthreads();
   }
 }
@@ -142,13 +154,25 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
     const BetaParams<T>& p = g.bp[dir];
-    if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
-    if constexpr (LQ_MAX >= 4)
-      if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem, t);
-    if constexpr (LQ_MAX >= 8)
-      if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem, t);
-    if constexpr (LQ_MAX >= 16)
-      if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+    if (g.narrow) {
+      if constexpr (BetaCfg<T>::BT > 16) {
+        if (g.lq == 2) beta_inverse_body<T, 2, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+        if constexpr (LQ_MAX >= 4)
+          if (g.lq == 4) beta_inverse_body<T, 4, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+        if constexpr (LQ_MAX >= 8)
+          if (g.lq == 8) beta_inverse_body<T, 8, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+        if constexpr (LQ_MAX >= 16)
+          if (g.lq == 16) beta_inverse_body<T, 16, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+      }
+    } else {
+      if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
+      if constexpr (LQ_MAX >= 4)
+        if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem, t);
+      if constexpr (LQ_MAX >= 8)
+        if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem, t);
+      if constexpr (LQ_MAX >= 16)
+        if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+    }
     __syncthreads();
   }
 }
@@ -181,9 +205,15 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-    if constexpr (LQ2_MAX >= 2)
-      if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+    if (g.narrow) {
+      if (g.lq2 == 1) beta_inverse_bf16x3_body<1, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      if constexpr (LQ2_MAX >= 2)
+        if (g.lq2 == 2) beta_inverse_bf16x3_body<2, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+    } else {
+      if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      if constexpr (LQ2_MAX >= 2)
+        if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+    }
     __syncthreads();
   }
 }
@@ -391,6 +421,8 @@ su2_status_t build_worklists(su2_plan_s* pl) {
     d.rtmax = beta_rtmax(gp->B);
     d.lq = beta_lq(gp->B);
     d.lq2 = beta_bf16_lq(gp->B);
+    // as single-B plans: FP32 groups of at most 16 signals take 16-signal tiles
+    d.narrow = sizeof(T) == 4 && gp->batch <= 16 ? 1 : 0;
     const T* tab = std::is_same<T, double>::value ? (const T*)gp->d_tab64 : (const T*)gp->d_tab32;
     for (int dir = 0; dir < 3; dir++) {
       d.rp[dir] = ring_params<T>(gp, dir == 2);
@@ -417,8 +449,8 @@ su2_status_t build_worklists(su2_plan_s* pl) {
       for (int i = 0; i < gp->batch; i++)
         for (int k = 0; k < N; k++) ringg.push_back({ring_cost, WorkItem{gi, i, k}});
     }
-    const int btf = bf ? XBF_BT : BetaCfg<T>::BT;
-    const int bti = bf ? XB_BT : BetaCfg<T>::BT;
+    const int btf = bf ? XBF_BT : (d.narrow ? 16 : BetaCfg<T>::BT);
+    const int bti = d.narrow ? 16 : (bf ? XB_BT : BetaCfg<T>::BT);
     for (int t = 0; t < gp->ntiles; t++) {
       const double tile_cost = (double)N * std::max(1, gp->h_pairs[t * PT].lsum);
       for (int b = 0; b * btf < gp->batch; b++)
