@@ -67,3 +67,10 @@ def test_more_than_one_gpu_is_refused():
                          text=True, timeout=120, cwd=ROOT)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
+
+
+def test_shifted_depth1_flops():
+    # A_{rho-1} s^{Lb} + B_{rho-1} s^{Lb-1}: two real x complex multiply-adds
+    # per (coefficient, node, signal), twice the table form's count
+    assert bench.shifted_depth1_flops(64, 1) == 2 * bench.useful_flops("beta_forward", 64, 1) == 8 * 128 * 89440
+    assert bench.shifted_depth1_flops(64, 32) == 32 * bench.shifted_depth1_flops(64, 1)

@@ -69,6 +69,25 @@ def test_shifted_equals_table_contraction_b64(dtype, depth, block):
     assert _rel(got[5][sel], oracle.forward(B, x[5], sel)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("B,batch", [(24, 37), (36, 5), (64, 1)])
+def test_shifted_depth1_ragged_batches(dtype, B, batch):
+    """Depth 1 on the matrix cores takes 32 signals per workgroup: a second,
+    partial signal tile (37), a batch far below one tile (5, 1), one and two
+    row tiles of degrees (B = 24: L <= 12; B = 36, 64: L up to 18 and 32)."""
+    x = synth.samples_uniform(B, batch, seed=2000 + B, dtype=NPDT[dtype])
+    plan = su2.Plan(B, batch, dtype)
+    table = _host(plan.forward(_dev(x)))
+    got = _host(_shifted(plan, _dev(x), 1, 4))
+    rel = _rel(got, table)
+    print(f"shifted depth 1 vs table B={B} batch={batch} {dtype}: rel {rel:.3e}", flush=True)
+    assert rel <= (1e-12 if dtype == "c128" else 1e-6)
+    rng = np.random.default_rng(B)
+    sel = rng.choice(oracle.num_coeffs(B), 32, replace=False)
+    last = batch - 1
+    assert _rel(got[last][sel], oracle.forward(B, x[last], sel)) <= TOL[dtype]
+
+
 def test_shifted_matches_oracle_projections_on_gpu_spectra():
     """The oracle's k = 1 and k = 2 projections of oracle/shifted.py, applied to
     one pair's node values, agree with the GPU stage for that pair's degrees."""
