@@ -281,12 +281,13 @@ def run_separate(make_plan, x, c, steps: int, warmup: int):
 def shifted_forms(steps: int):
     """The forward contraction at B=64 batch 32 (c64 plan) in its three forms:
     the table contraction on the matrix cores, and the shifted-recurrence
-    (divide-and-conquer) form at depth 1 (FP64 matrix cores, the shifted
-    polynomials generated in FP64 on the vector ALUs) and depth 2 (coarse
-    step 4, FP64 vector ALUs).  Depth 1 is priced by its contraction: two
-    real-times-complex multiply-adds per (coefficient, node, signal), one
-    against each stored product, i.e. 8 N C(B) flops per signal, against the
-    dense FP64 matrix-core peak."""
+    (divide-and-conquer) form at depth 1 and at depth 2 with coarse step 16
+    (FP64 matrix cores, the shifted polynomials generated in FP64 on the
+    vector ALUs), and at depth 2 with coarse step 4 (FP64 vector ALUs).  The
+    matrix-core forms are priced by their contraction: two real-times-complex
+    multiply-adds per (coefficient, node, signal), one against each stored
+    product, i.e. 8 N C(B) flops per signal, against the dense FP64
+    matrix-core peak."""
     import numpy as np
     import torch
 
@@ -301,6 +302,7 @@ def shifted_forms(steps: int):
     res = {}
     for name, fn in (("table_ms", lambda: plan.run_stage("beta_forward", None, out)),
                      ("shifted_depth1_ms", lambda: plan.beta_forward_shifted(out, 1, 4)),
+                     ("shifted_depth2_block16_ms", lambda: plan.beta_forward_shifted(out, 2, 16)),
                      ("shifted_depth2_block4_ms", lambda: plan.beta_forward_shifted(out, 2, 4))):
         fn()
         torch.cuda.synchronize()
@@ -313,9 +315,11 @@ def shifted_forms(steps: int):
         res[name] = round(e0.elapsed_time(e1) / max(3, steps // 5), 4)
     C = B * (B + 1) * (2 * B + 1) // 6
     flops = shifted_depth1_flops(B, batch)
-    ach = flops / (res["shifted_depth1_ms"] * 1e-3)
-    res["roofline_depth1"] = {"bound": "mfma", "achieved": round(ach / 1e12, 3), "peak": MFMA_PEAK["c128"] / 1e12,
-                              "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK["c128"], 4)}
+    for form in ("depth1", "depth2_block16"):
+        ach = flops / (res[f"shifted_{form}_ms"] * 1e-3)
+        res[f"roofline_{form}"] = {"bound": "mfma", "achieved": round(ach / 1e12, 3),
+                                   "peak": MFMA_PEAK["c128"] / 1e12, "unit": "TFLOP/s",
+                                   "frac": round(ach / MFMA_PEAK["c128"], 4)}
     plan.close()
     return res
 

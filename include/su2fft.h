@@ -213,11 +213,14 @@ su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t*
  * degrees l0 .. l0+L-1 and base level Lb = l0 + 1 it forms the stored products
  * s^{Lb} = S d^{l0+1}, s^{Lb-1} = S d^{l0} of the pair's ring spectrum S and
  *   depth 1:  fhat(l0+1+r) = <s^{Lb}, A_r^{Lb}> + <s^{Lb-1}, B_r^{Lb}>,
- *   depth 2:  r = n1 + n2 with n1 a multiple of `block` (2, 4 or 8; ignored at
- *             depth 1) and the four terms <s^{Lb}, A_{n2}^{Lb+n1} A_{n1}^{Lb}> +
+ *   depth 2:  r = n1 + n2 with n1 a multiple of `block` (2, 4, 8 or 16;
+ *             ignored at depth 1) and the four terms <s^{Lb}, A_{n2}^{Lb+n1} A_{n1}^{Lb}> +
  *             <s^{Lb}, B_{n2}^{Lb+n1} A_{n1-1}^{Lb}> + <s^{Lb-1}, A_{n2}^{Lb+n1} B_{n1}^{Lb}> +
  *             <s^{Lb-1}, B_{n2}^{Lb+n1} B_{n1-1}^{Lb}>,
- * with the shifted polynomials A, B generated per node in FP64.  Reads the
+ * with the shifted polynomials A, B generated per node in FP64.  Depth 1 and
+ * depth 2 with block 16 (the matrix-core row tile: the fine chains of the two
+ * row tiles run side by side) contract on the FP64 matrix cores; blocks 2, 4
+ * and 8 run on the vector ALUs.  Reads the
  * ring spectra that su2_run_stage(SU2_STAGE_RING_FORWARD) left in the plan and
  * writes d_coeffs exactly like su2_run_stage(SU2_STAGE_BETA_FORWARD) (same
  * values up to rounding).  Arithmetic in FP64 for every dtype (the method's

@@ -29,8 +29,14 @@
 //   fhat(l0 + rho) = sum_k A_{rho-1}(x_k) s^{Lb}_k + B_{rho-1}(x_k) s^{Lb-1}_k,
 // the product of an L x 2N matrix (A and B at the nodes) with the 2N x batch
 // matrix of stored products: FP64 16x16x4 products whose K index runs over
-// (node, polynomial).  Depth 2 keeps one thread per (pair, signal), which
-// walks the nodes with its L accumulators in registers.
+// (node, polynomial).  Depth 2 with a coarse step of 16 (one matrix-core row
+// tile) runs on the same kernel: rows rho = 16 + n2 + 1 contract the fine
+// polynomials A_{n2}, B_{n2} of level Lb + 16 against the shifted stored
+// products u = A_16 s^{Lb} + B_16 s^{Lb-1} and v = A_15 s^{Lb} + B_15 s^{Lb-1},
+// so the fine chains of the two row tiles are independent and run side by
+// side (16-18 dependent steps instead of L).  Depth 2 with coarse steps 2, 4
+// or 8 keeps one thread per (pair, signal), which walks the nodes with its L
+// accumulators in registers.
 #include "su2fft_internal.h"
 
 namespace su2 {
@@ -53,9 +59,16 @@ struct ShMfma {
   static constexpr int PB = 2 * PT + 2;
   static constexpr int PK = BT * PB + 16;
   static constexpr int TMAX = PT * 16 * RTMAX;  // longest tile row (sum of L)
-  static constexpr size_t OFF_G = (size_t)SK * PK * sizeof(T);                    // [node][A | B][lsum]
-  static constexpr size_t OFF_D = OFF_G + (size_t)SK * 2 * TMAX * sizeof(double);  // [node][pair][d1 | d0]
-  static constexpr size_t OFF_C = OFF_D + (size_t)SK * PT * 2 * sizeof(double);    // recurrence coefficients
+  // generated rows: element (degree row j of the tile, node kk, polynomial h)
+  // at j * GS + 2 kk + h; the odd stride GS spreads a step's writes (16
+  // (node, polynomial) of a pair side by side) and the operand reads (16
+  // consecutive degrees) over distinct banks
+  static constexpr int GS = 2 * SK + 1;
+  static constexpr size_t OFF_G = (size_t)SK * PK * sizeof(T);
+  // per (node, pair): d^{l0+1}, d^{l0}, then (depth 2) A_16, B_16, A_15, B_15 of level Lb
+  static constexpr int DS = 6;
+  static constexpr size_t OFF_D = OFF_G + (size_t)TMAX * GS * sizeof(double);
+  static constexpr size_t OFF_C = OFF_D + (size_t)SK * PT * DS * sizeof(double);  // recurrence coefficients
   static constexpr size_t OFF_X = OFF_C + (size_t)TMAX * 3 * sizeof(double);     // x, cos, sin of the nodes
   static constexpr int NX = 128;                                                   // nodes (B <= 64)
   static constexpr size_t END = OFF_X + (size_t)3 * NX * sizeof(double);
@@ -64,7 +77,7 @@ struct ShMfma {
   static_assert(OFF_G % 8 == 0, "FP64 rows aligned");
 };
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, bool SPLIT>
 __device__ __forceinline__ void beta_forward_shifted_mfma_body(const cpx<T>* __restrict__ S,
                                                                cpx<T>* __restrict__ coeffs, const OtfParams<T>& op,
                                                                int tile, int bt, unsigned char* smem, int tid) {
@@ -102,44 +115,63 @@ __device__ __forceinline__ void beta_forward_shifted_mfma_body(const cpx<T>* __r
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-  // rows of nodes g0 .. g0 + SK - 1: thread (pair gi, node g0 + gk,
-  // polynomial h) runs X_{-1}, X_0, X_1, .. with X = A (h = 0) or B (h = 1);
-  // past the last node the stored products are zero.  The pair, its seed's
-  // constant and exponents are the thread's for the whole launch.
-  const int gh = tid & 1, ggk = (tid >> 1) % SK, ggi = (tid >> 1) / SK;
-  const bool gthr = tid < 2 * PT * SK;
-  PairInfo gq = p.pairs[tile * PT + (gthr ? ggi : 0)];
-  if (!gthr) gq.L = 0;
-  int gtop = 0, gpc = 0, gps = 0, gneg = 0;
+  // rows of nodes g0 .. g0 + SK - 1: thread (pair gi, node g0 + gk, row
+  // tile gt, polynomial h) runs X_{-1}, X_0, X_1, .. with X = A (h = 0) or
+  // B (h = 1) of level Lb + 16 gt, from the recurrence coefficients of the
+  // degrees it stands for.  At depth 1 one chain (gt = 0) covers all L rows;
+  // at depth 2 the chain of tile 0 runs on to A_15, A_16 (B_15, B_16), the
+  // coarse polynomials of the shifted stored products.  Past the last node
+  // the stored products are zero.  The pair, its seed's constant and
+  // exponents are the thread's for the whole launch.
+  constexpr int GT = SPLIT ? RTMAX : 1;
+  constexpr int DS = G::DS;
+  static_assert(2 * GT * PT * SK <= FWD_THREADS, "one generation thread per chain");
+  const int gh = tid & 1, gt = (tid >> 1) % GT, ggk = (tid / (2 * GT)) % SK, ggi = tid / (2 * GT * SK);
+  const bool gthr = tid < 2 * GT * PT * SK;
+  int gL, gcoff, gpc = 0, gps = 0;
   double gseed = 0.0;
-  if (gq.L > 0) {
-    wigner_seed_form(gq.tl0, gq.tn, gq.tm, &gtop, &gpc, &gps, &gneg);
-    gseed = op.seedc[tile * PT + ggi];
+  {
+    const PairInfo q = p.pairs[tile * PT + (gthr ? ggi : 0)];
+    gL = gthr && q.L > 16 * gt ? q.L : 0;
+    gcoff = q.coff;
+    if (gL > 0) {
+      int top, neg;
+      wigner_seed_form(q.tl0, q.tn, q.tm, &top, &gpc, &gps, &neg);
+      gseed = op.seedc[tile * PT + ggi];
+    }
   }
+  const int gs = 16 * gt;                               // level shift of the chain
+  const int nrow = SPLIT ? min(gL - gs, 16) : gL;        // rows it writes
+  const int jend = SPLIT && gt == 0 ? min(gL, 18) : nrow;  // steps it runs
   auto generate = [&](int g0) {
-    if (gq.L > 0) {
+    if (gL > 0) {
       const int k = g0 + ggk;
       const bool kin = k < N;
       const int kc = kin ? k : N - 1;
       const double x = sX[kc];
-      const double* rc = sC + 3 * gq.coff;
-      const double d0 = kin ? gseed * powi_d(sX[G::NX + kc], gpc) * powi_d(sX[2 * G::NX + kc], gps) : 0.0;
-      const double d1 = gq.L > 1 ? (rc[3] * x - rc[4]) * d0 : 0.0;
-      sD[(ggk * PT + ggi) * 2 + gh] = gh ? d0 : d1;
-      double* out = sG + (ggk * 2 + gh) * lsum + gq.coff;
+      const double* rc = sC + 3 * (gcoff + gs);
+      double* dd = sD + (ggk * PT + ggi) * DS;
+      if (gt == 0) {
+        const double d0 = kin ? gseed * powi_d(sX[G::NX + kc], gpc) * powi_d(sX[2 * G::NX + kc], gps) : 0.0;
+        const double d1 = gL > 1 ? (rc[3] * x - rc[4]) * d0 : 0.0;
+        dd[gh] = gh ? d0 : d1;
+        if (SPLIT) dd[2 + gh] = dd[4 + gh] = 0.0;  // A_16, A_15 (B_16, B_15) where the chain stops short
+      }
+      double* out = sG + (gcoff + gs) * G::GS + 2 * ggk + gh;
       double xm = gh ? 1.0 : 0.0, xc = gh ? 0.0 : 1.0;
       out[0] = xm;
-      if (gq.L > 1) out[1] = xc;
-      if (gq.L > 2) {
-        // coefficients of step r + 1 are read while step r computes
+      if (nrow > 1) out[G::GS] = xc;
+      if (jend > 2) {
+        // coefficients of step j + 1 are read while step j computes
         double c0 = rc[6], c1 = rc[7], c2 = rc[8];
-        for (int r = 2; r < gq.L; r++) {
-          const int rn = r + 1 < gq.L ? r + 1 : r;
-          const double n0 = rc[3 * rn], n1 = rc[3 * rn + 1], n2 = rc[3 * rn + 2];
+        for (int j = 2; j < jend; j++) {
+          const int jn = j + 1 < jend ? j + 1 : j;
+          const double n0 = rc[3 * jn], n1 = rc[3 * jn + 1], n2 = rc[3 * jn + 2];
           const double xn = (c0 * x - c1) * xc - c2 * xm;
           xm = xc;
           xc = xn;
-          out[r] = xn;
+          if (j < nrow) out[j * G::GS] = xn;
+          if (SPLIT && j >= 16) dd[(j == 16 ? 4 : 2) + gh] = xn;  // X_15, X_16
           c0 = n0;
           c1 = n1;
           c2 = n2;
@@ -199,18 +231,25 @@ __device__ __forceinline__ void beta_forward_shifted_mfma_body(const cpx<T>* __r
         // K index lk: node ks + lk / 2, polynomial lk % 2
         const int kk = ks + (lk >> 1), h = lk & 1;
         const bool kin = c * SK + kk < N;
-        const double ds = sD[(kk * PT + pp) * 2 + h];
-        double bop[CT];
-#pragma unroll
-        for (int ct = 0; ct < CT; ct++) {
-          const int cc = ct * 16 + lrow;
-          bop[ct] = (double)sS[kk * PK + (cc >> 1) * PB + 2 * pp + (cc & 1)] * ds;
-        }
+        const double* dd = sD + (kk * PT + pp) * DS;
+        const double d1 = dd[0], d0 = dd[1];
 #pragma unroll
         for (int rt = 0; rt < RTMAX; rt++) {
           if (rt * 16 < L) {
+            // B operand: the stored products s^{Lb} (A rows) or s^{Lb-1} (B
+            // rows); for the second tile at depth 2 the shifted ones,
+            // u = A_16 s^{Lb} + B_16 s^{Lb-1} (A rows) and
+            // v = A_15 s^{Lb} + B_15 s^{Lb-1} (B rows), formed with the
+            // spectrum factored out: S (A d^{l0+1} + B d^{l0})
+            const double sc = (SPLIT && rt == 1) ? dd[2 + 2 * h] * d1 + dd[3 + 2 * h] * d0 : (h ? d0 : d1);
+            double bop[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ct++) {
+              const int cc = ct * 16 + lrow;
+              bop[ct] = (double)sS[kk * PK + (cc >> 1) * PB + 2 * pp + (cc & 1)] * sc;
+            }
             const int rho = rt * 16 + lrow;
-            const double a = (rho < L && kin) ? sG[(kk * 2 + h) * lsum + coff + rho] : 0.0;
+            const double a = (rho < L && kin) ? sG[(coff + rho) * G::GS + 2 * kk + h] : 0.0;
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = mfma16x16x4(a, bop[ct], acc[i][rt][ct]);
           }
@@ -251,15 +290,15 @@ __device__ __forceinline__ void beta_forward_shifted_mfma_body(const cpx<T>* __r
   }
 }
 
-template <class T, int RTMAX>
+template <class T, int RTMAX, bool SPLIT>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_shifted_mfma_kernel(const cpx<T>* __restrict__ S,
                                                                                 cpx<T>* __restrict__ coeffs,
                                                                                 OtfParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_shifted_mfma_body<T, RTMAX>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  beta_forward_shifted_mfma_body<T, RTMAX, SPLIT>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
-// ---- depth 2: one thread per (pair, signal) ----
+// ---- depth 2, coarse steps 2, 4, 8: one thread per (pair, signal) ----
 
 constexpr int SH_THREADS = 512;  // 16 pairs x 32 signals
 constexpr int SH_BT = SH_THREADS / PT;
@@ -342,14 +381,21 @@ __global__ __launch_bounds__(SH_THREADS) void beta_forward_shifted_kernel(const 
 template <class T, int LMAX>
 static hipError_t launch_shifted_l(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, int depth, int blk,
                                    hipStream_t s) {
-  if (depth == 1) {
+  if (depth == 1 || blk == 16) {
     constexpr int RT = (LMAX + 15) / 16;
     typedef ShMfma<T, RT> G;
     if (p.b.N > G::NX) return hipErrorInvalidValue;
-    hipError_t e = set_smem(beta_forward_shifted_mfma_kernel<T, RT>, G::SMEM);
-    if (e != hipSuccess) return e;
     const dim3 grid(p.b.ntiles, (p.b.batch + G::BT - 1) / G::BT);
-    hipLaunchKernelGGL((beta_forward_shifted_mfma_kernel<T, RT>), grid, dim3(FWD_THREADS), G::SMEM, s, S, coeffs, p);
+    hipError_t e;
+    if (depth == 1) {
+      if ((e = set_smem(beta_forward_shifted_mfma_kernel<T, RT, false>, G::SMEM)) != hipSuccess) return e;
+      hipLaunchKernelGGL((beta_forward_shifted_mfma_kernel<T, RT, false>), grid, dim3(FWD_THREADS), G::SMEM, s, S,
+                         coeffs, p);
+    } else {
+      if ((e = set_smem(beta_forward_shifted_mfma_kernel<T, RT, true>, G::SMEM)) != hipSuccess) return e;
+      hipLaunchKernelGGL((beta_forward_shifted_mfma_kernel<T, RT, true>), grid, dim3(FWD_THREADS), G::SMEM, s, S,
+                         coeffs, p);
+    }
     return hipGetLastError();
   }
   const dim3 grid(p.b.ntiles, (p.b.batch + SH_BT - 1) / SH_BT);
@@ -368,7 +414,7 @@ template <class T>
 hipError_t launch_beta_forward_shifted(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, int depth, int blk,
                                        hipStream_t s) {
   const int lmax = (p.b.B + 1) / 2;
-  if ((depth != 1 && depth != 2) || (depth == 2 && blk != 2 && blk != 4 && blk != 8) || lmax > 32)
+  if ((depth != 1 && depth != 2) || (depth == 2 && blk != 2 && blk != 4 && blk != 8 && blk != 16) || lmax > 32)
     return hipErrorInvalidValue;
   if (lmax <= 8) return launch_shifted_l<T, 8>(p, S, coeffs, depth, blk, s);
   if (lmax <= 16) return launch_shifted_l<T, 16>(p, S, coeffs, depth, blk, s);

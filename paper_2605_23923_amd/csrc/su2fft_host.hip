@@ -706,7 +706,7 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
 su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream) {
   if (!plan || plan->mixed || plan->real || plan->so3 || !d_coeffs) return SU2_ERR_INVALID_VALUE;
   if (depth != 1 && depth != 2) return SU2_ERR_INVALID_VALUE;
-  if (depth == 2 && block != 2 && block != 4 && block != 8) return SU2_ERR_INVALID_VALUE;
+  if (depth == 2 && block != 2 && block != 4 && block != 8 && block != 16) return SU2_ERR_INVALID_VALUE;
   if (!shifted_supported(plan->B)) return SU2_ERR_UNSUPPORTED;
   hipError_t e;
   if (plan->dtype == SU2_C128)

@@ -41,7 +41,7 @@ def _shifted(plan, x, depth, block):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("B", [1, 2, 3, 4, 8, 12, 16])
-@pytest.mark.parametrize("depth,block", [(1, 4), (2, 2), (2, 4), (2, 8)])
+@pytest.mark.parametrize("depth,block", [(1, 4), (2, 2), (2, 4), (2, 8), (2, 16)])
 def test_shifted_forward_matches_oracle(B, dtype, depth, block):
     batch = 3
     x = synth.samples_uniform(B, batch, seed=1000 + B, dtype=NPDT[dtype])
@@ -54,7 +54,7 @@ def test_shifted_forward_matches_oracle(B, dtype, depth, block):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("depth,block", [(1, 4), (2, 4), (2, 8)])
+@pytest.mark.parametrize("depth,block", [(1, 4), (2, 4), (2, 8), (2, 16)])
 def test_shifted_equals_table_contraction_b64(dtype, depth, block):
     B, batch = 64, 32
     x = synth.samples_uniform(B, batch, seed=1064, dtype=NPDT[dtype])
@@ -70,17 +70,21 @@ def test_shifted_equals_table_contraction_b64(dtype, depth, block):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("B,batch", [(24, 37), (36, 5), (64, 1)])
-def test_shifted_depth1_ragged_batches(dtype, B, batch):
-    """Depth 1 on the matrix cores takes 32 signals per workgroup: a second,
-    partial signal tile (37), a batch far below one tile (5, 1), one and two
-    row tiles of degrees (B = 24: L <= 12; B = 36, 64: L up to 18 and 32)."""
+@pytest.mark.parametrize("B,batch", [(24, 37), (36, 5), (48, 3), (64, 1)])
+@pytest.mark.parametrize("depth,block", [(1, 4), (2, 16)])
+def test_shifted_matrix_core_forms_ragged(dtype, B, batch, depth, block):
+    """Depth 1 and depth 2 with block 16 on the matrix cores take 32 signals
+    per workgroup: a second, partial signal tile (37), a batch far below one
+    tile (5, 3, 1), one and two row tiles of degrees (B = 24: L <= 12;
+    B = 36: L up to 18, with the pairs of L = 17 whose second tile is one row,
+    fine polynomials A_{-1} = 0 and B_{-1} = 1 alone; B = 48, 64: L up to 24
+    and 32)."""
     x = synth.samples_uniform(B, batch, seed=2000 + B, dtype=NPDT[dtype])
     plan = su2.Plan(B, batch, dtype)
     table = _host(plan.forward(_dev(x)))
-    got = _host(_shifted(plan, _dev(x), 1, 4))
+    got = _host(_shifted(plan, _dev(x), depth, block))
     rel = _rel(got, table)
-    print(f"shifted depth 1 vs table B={B} batch={batch} {dtype}: rel {rel:.3e}", flush=True)
+    print(f"shifted depth {depth} block {block} vs table B={B} batch={batch} {dtype}: rel {rel:.3e}", flush=True)
     assert rel <= (1e-12 if dtype == "c128" else 1e-6)
     rng = np.random.default_rng(B)
     sel = rng.choice(oracle.num_coeffs(B), 32, replace=False)
@@ -125,6 +129,8 @@ def test_shifted_argument_errors():
         plan.beta_forward_shifted(depth=3)
     with pytest.raises(su2.SU2Error):
         plan.beta_forward_shifted(depth=2, block=3)
+    with pytest.raises(su2.SU2Error):
+        plan.beta_forward_shifted(depth=2, block=32)
     big = su2.Plan(128, 1, "c64")
     with pytest.raises(su2.SU2Error) as ei:
         big.beta_forward_shifted(depth=1)
