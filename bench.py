@@ -489,7 +489,14 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes three times (reference for "
                          "the HBM byte counters) and exit")
+    ap.add_argument("--shifted-forms", action="store_true",
+                    help="only time the forward contraction in its table and shifted-recurrence forms at B=64 "
+                         "batch 32 (c64 plan), print that JSON object and exit")
     args = ap.parse_args()
+
+    if args.shifted_forms:
+        print(json.dumps(shifted_forms(args.steps)))
+        return
 
     if args.copy_calibration:
         import torch
