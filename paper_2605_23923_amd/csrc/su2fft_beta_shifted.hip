@@ -41,17 +41,18 @@
 
 namespace su2 {
 
-// ---- depth 1: matrix cores ----
+// ---- depth 1, and depth 2 with coarse step 16: matrix cores ----
 //
 // Workgroup: 16 pairs (one tile) x 32 signals, 8 waves; wave w owns pairs w
 // and w + 8.  Per chunk of SK nodes the workgroup stages the ring spectra of
 // its pairs and signals in LDS, and generates into LDS the rows A_{rho-1},
-// B_{rho-1} (one FP64 chain per (pair, node, polynomial) and thread) and
-// d^{l0}, d^{l0+1} of every (pair, node).  The generation is the serial part
-// (L dependent steps between barriers), so a workgroup takes as many signals
-// as its accumulators allow and reads nothing but LDS while generating.  The B operand of a product is the
-// spectrum value times d^{l0+1} (K index of an A row) or d^{l0} (of a B row):
-// the method's stored products, formed as they are loaded.
+// B_{rho-1} (FP64 chains per (pair, node, polynomial)) and d^{l0}, d^{l0+1}
+// of every (pair, node).  The generation runs between barriers and does not
+// depend on the signals, so a workgroup takes as many signals as its
+// accumulators allow, and reads nothing but LDS while generating.  The B
+// operand of a product is the spectrum value times d^{l0+1} (K index of an
+// A row) or d^{l0} (of a B row): the method's stored products, formed as
+// they are loaded.
 template <class T, int RTMAX>
 struct ShMfma {
   static constexpr int BT = 32;  // signals per workgroup (64 real columns)
