@@ -46,8 +46,12 @@ struct OtfFwd {
   static constexpr int GK0 = (65536 / (int)sizeof(T)) / TMAX;
   static constexpr int GK = GK0 >= 32 ? 32 : GK0;   // nodes generated at a time (64 KB of rows)
   static_assert(GK % KC == 0 && PT * GK <= FWD_THREADS, "generation geometry");
-  // S chunk, GK table rows, then the tile's recurrence coefficients (3 doubles per row element)
-  static constexpr size_t SMEM_C = (size_t)KC * PK * sizeof(T) + (size_t)GK * TMAX * sizeof(T);
+  // generated values: (degree row j of the tile, node gk) at j * GS + gk; the
+  // odd stride spreads a chain step's writes (GK nodes side by side) and the
+  // operand reads (16 consecutive degrees) over distinct banks
+  static constexpr int GS = GK + 1;
+  // S chunk, the generated values, then the tile's recurrence coefficients (3 doubles per row element)
+  static constexpr size_t SMEM_C = (size_t)KC * PK * sizeof(T) + (size_t)TMAX * GS * sizeof(T);
   static constexpr size_t SMEM = SMEM_C + (size_t)TMAX * 3 * sizeof(double);
 };
 
@@ -70,7 +74,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
   constexpr int SPT = SV / FWD_THREADS;
   static_assert(SV % FWD_THREADS == 0, "chunk split");
   T* sS = reinterpret_cast<T*>(smem);
-  T* sT = sS + KC * PK;  // GK node rows of lsum values
+  T* sT = sS + KC * PK;  // GK nodes of the tile's lsum degree rows
   double* sC = reinterpret_cast<double*>(smem + G::SMEM_C);
 
   const int b0 = bt * BT;
@@ -103,7 +107,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
     if (gi < PT && k < N) {
       const PairInfo q = p.pairs[tile * PT + gi];
       if (q.L > 0) {
-        T* out = sT + gk * lsum + q.coff;
+        T* out = sT + q.coff * G::GS + gk;
         double d = otf_seed(op, q, tile * PT + gi, k), dm1 = 0.0;
         const double x = op.xk[k];
         const double* rc = sC + 3 * q.coff;
@@ -112,7 +116,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
           const double dn = (rc[3 * i] * x - rc[3 * i + 1]) * d - rc[3 * i + 2] * dm1;
           dm1 = d;
           d = dn;
-          out[i] = (T)d;
+          out[i * G::GS] = (T)d;
         }
       }
     }
@@ -157,7 +161,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
       generate(g0);
       __syncthreads();
     }
-    const int toff = (c * KC - g0) * lsum;
+    const int toff = c * KC - g0;  // first node of the chunk in the generated block
 #pragma unroll
     for (int i = 0; i < 2; i++) {
       const int L = pi[i].L;
@@ -178,7 +182,7 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
         for (int rt = 0; rt < RTMAX; rt++) {
           if (rt * 16 < L) {
             const int l = rt * 16 + lrow;
-            const T a = (l < L && kin) ? sT[toff + kk * lsum + coff + l] : T(0);
+            const T a = (l < L && kin) ? sT[(coff + l) * G::GS + toff + kk] : T(0);
 #pragma unroll
             for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = mfma16x16x4(a, bop[ct], acc[i][rt][ct]);
           }
@@ -223,6 +227,12 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_otf_kernel(const cpx
   beta_forward_otf_body<T, RTMAX, BT>(S, coeffs, p, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
 }
 
+// generated values of the inverse (GEN_LDS): (degree row j of the tile, node
+// k0 + gk) at j * INV_GS + gk, so that a chain step's writes (16 nodes of a
+// pair) and an operand read (16 nodes of one degree) are contiguous; no
+// padding, which would push the largest tiles past the LDS limit
+constexpr int INV_GS = 16;
+
 // Inverse: as beta_inverse_body, with the A operands (node k = k0 + lrow,
 // degree l = 4 s + lk) generated per lane.
 template <class T, int LQ, bool GEN_LDS, int BT_ = BetaCfg<T>::BT>
@@ -235,7 +245,7 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
   constexpr int PB = InvStage<T>::PB, NRS = InvStage<T>::NRS;
   T* stage = reinterpret_cast<T*>(smem);
   double* sC = reinterpret_cast<double*>(smem + inverse_smem<T>());  // the tile's recurrence coefficients
-  T* sT = reinterpret_cast<T*>(sC + (size_t)PT * 4 * LQ * 3);          // GEN_LDS: 16 node rows of lsum values
+  T* sT = reinterpret_cast<T*>(sC + (size_t)PT * 4 * LQ * 3);          // GEN_LDS: 16 nodes of lsum degree rows
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
   const int wave = tid >> 6, lane = tid & 63;
@@ -274,13 +284,12 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
     if constexpr (GEN_LDS) {
       // one chain per (pair, node) of the block: threads tid < 16 * PT, then
       // every lane reads its operands (node kc, degrees l = 4 s + lk)
-      const int lsum = p0.lsum;
       if (tid < 16 * PT) {
         const int gi = tid / 16, gk = tid - gi * 16;
         const int kg = k0 + gk < N ? k0 + gk : N - 1;
         const PairInfo q = p.pairs[tile * PT + gi];
         if (q.L > 0) {
-          T* out = sT + gk * lsum + q.coff;
+          T* out = sT + q.coff * INV_GS + gk;
           double dd = otf_seed(op, q, tile * PT + gi, kg), ddm1 = 0.0;
           const double xg = op.xk[kg];
           const double* rc = sC + 3 * q.coff;
@@ -289,7 +298,7 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
             const double dn = (rc[3 * i] * xg - rc[3 * i + 1]) * dd - rc[3 * i + 2] * ddm1;
             ddm1 = dd;
             dd = dn;
-            out[i] = (T)dd;
+            out[i * INV_GS] = (T)dd;
           }
         }
       }
@@ -299,7 +308,7 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
 #pragma unroll
         for (int s = 0; s < LQ; s++) {
           const int l = 4 * s + lk;
-          av[q][s] = (l < pi[q].L && k < N) ? sT[lrow * lsum + pi[q].coff + l] : T(0);
+          av[q][s] = (l < pi[q].L && k < N) ? sT[(pi[q].coff + l) * INV_GS + lrow] : T(0);
         }
     } else {
       // this lane's chains for both pairs, advanced together (independent FP64
@@ -392,7 +401,7 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_otf_kernel(const cpx
 template <class T, int LQ, bool GEN_LDS>
 constexpr size_t inverse_otf_smem() {
   return inverse_smem<T>() + (size_t)PT * 4 * LQ * 3 * sizeof(double) +
-         (GEN_LDS ? (size_t)16 * PT * 4 * LQ * sizeof(T) : 0);
+         (GEN_LDS ? (size_t)INV_GS * PT * 4 * LQ * sizeof(T) : 0);
 }
 // generated rows in LDS where they fit next to the staging buffer (all but
 // FP64 at B = 128, which generates per lane)
