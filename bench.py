@@ -494,6 +494,11 @@ def main():
                          "batch 32 (c64 plan), print that JSON object and exit")
     args = ap.parse_args()
 
+    if args.gpus != 1:
+        print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); signals are independent, so a "
+              "multi-GPU run would shard the batch by signal with no communication.", file=sys.stderr)
+        sys.exit(2)
+
     if args.shifted_forms:
         print(json.dumps(shifted_forms(args.steps)))
         return
@@ -508,11 +513,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 3}))
         return
-
-    if args.gpus != 1:
-        print(f"bench.py: runs on one GPU only (got --gpus {args.gpus}); signals are independent, so a "
-              "multi-GPU run would shard the batch by signal with no communication.", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     if not torch.cuda.is_available():
