@@ -62,8 +62,9 @@ def test_useful_flops_per_contraction():
     assert bench.useful_flops("ring_forward", 64, 1) == 0.0
 
 
-def test_more_than_one_gpu_is_refused():
-    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+@pytest.mark.parametrize("extra", [[], ["--shifted-forms"], ["--copy-calibration", "1"]])
+def test_more_than_one_gpu_is_refused(extra):
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", *extra], capture_output=True,
                          text=True, timeout=120, cwd=ROOT)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
