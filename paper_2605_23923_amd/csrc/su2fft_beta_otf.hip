@@ -101,23 +101,33 @@ __device__ __forceinline__ void beta_forward_otf_body(const cpx<T>* __restrict__
         for (int r = 0; r < 4; r++) acc[i][rt][ct][r] = T(0);
 
   // table rows of nodes g0 .. g0 + GK - 1: thread (pair gi, node gk) runs one chain
+  // the generating thread's pair (gi) and seed, fixed for the launch
+  const int gi = tid / GK, gk = tid - gi * GK;
+  int gL = 0, gcoff = 0, gpc = 0, gps = 0;
+  double gseed = 0.0;
+  if (gi < PT) {
+    const PairInfo q = p.pairs[tile * PT + gi];
+    gL = q.L;
+    gcoff = q.coff;
+    if (gL > 0) {
+      int top, neg;
+      wigner_seed_form(q.tl0, q.tn, q.tm, &top, &gpc, &gps, &neg);
+      gseed = op.seedc[tile * PT + gi];
+    }
+  }
   auto generate = [&](int g0) {
-    const int gi = tid / GK, gk = tid - gi * GK;
     const int k = g0 + gk;
-    if (gi < PT && k < N) {
-      const PairInfo q = p.pairs[tile * PT + gi];
-      if (q.L > 0) {
-        T* out = sT + q.coff * G::GS + gk;
-        double d = otf_seed(op, q, tile * PT + gi, k), dm1 = 0.0;
-        const double x = op.xk[k];
-        const double* rc = sC + 3 * q.coff;
-        out[0] = (T)d;
-        for (int i = 1; i < q.L; i++) {
-          const double dn = (rc[3 * i] * x - rc[3 * i + 1]) * d - rc[3 * i + 2] * dm1;
-          dm1 = d;
-          d = dn;
-          out[i * G::GS] = (T)d;
-        }
+    if (gL > 0 && k < N) {
+      T* out = sT + gcoff * G::GS + gk;
+      double d = gseed * powi_d(op.ck[k], gpc) * powi_d(op.sk[k], gps), dm1 = 0.0;
+      const double x = op.xk[k];
+      const double* rc = sC + 3 * gcoff;
+      out[0] = (T)d;
+      for (int i = 1; i < gL; i++) {
+        const double dn = (rc[3 * i] * x - rc[3 * i + 1]) * d - rc[3 * i + 2] * dm1;
+        dm1 = d;
+        d = dn;
+        out[i * G::GS] = (T)d;
       }
     }
   };
@@ -276,6 +286,22 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
     __syncthreads();
   }
 
+  // GEN_LDS: thread (pair gi, node k0 + gk) of each block runs one chain;
+  // its pair and seed are fixed for the launch
+  const int gi = tid / 16, gk = tid - gi * 16;
+  int gL = 0, gcoff = 0, gpc = 0, gps = 0;
+  double gseed = 0.0;
+  if (GEN_LDS && tid < 16 * PT) {
+    const PairInfo q = p.pairs[tile * PT + gi];
+    gL = q.L;
+    gcoff = q.coff;
+    if (gL > 0) {
+      int top, neg;
+      wigner_seed_form(q.tl0, q.tn, q.tm, &top, &gpc, &gps, &neg);
+      gseed = op.seedc[tile * PT + gi];
+    }
+  }
+
   __syncthreads();
   for (int k0 = 0; k0 < N; k0 += 16) {
     const int k = k0 + lrow;
@@ -284,22 +310,18 @@ __device__ __forceinline__ void beta_inverse_otf_body(const cpx<T>* __restrict__
     if constexpr (GEN_LDS) {
       // one chain per (pair, node) of the block: threads tid < 16 * PT, then
       // every lane reads its operands (node kc, degrees l = 4 s + lk)
-      if (tid < 16 * PT) {
-        const int gi = tid / 16, gk = tid - gi * 16;
+      if (gL > 0) {
         const int kg = k0 + gk < N ? k0 + gk : N - 1;
-        const PairInfo q = p.pairs[tile * PT + gi];
-        if (q.L > 0) {
-          T* out = sT + q.coff * INV_GS + gk;
-          double dd = otf_seed(op, q, tile * PT + gi, kg), ddm1 = 0.0;
-          const double xg = op.xk[kg];
-          const double* rc = sC + 3 * q.coff;
-          out[0] = (T)dd;
-          for (int i = 1; i < q.L; i++) {
-            const double dn = (rc[3 * i] * xg - rc[3 * i + 1]) * dd - rc[3 * i + 2] * ddm1;
-            ddm1 = dd;
-            dd = dn;
-            out[i * INV_GS] = (T)dd;
-          }
+        T* out = sT + gcoff * INV_GS + gk;
+        double dd = gseed * powi_d(op.ck[kg], gpc) * powi_d(op.sk[kg], gps), ddm1 = 0.0;
+        const double xg = op.xk[kg];
+        const double* rc = sC + 3 * gcoff;
+        out[0] = (T)dd;
+        for (int i = 1; i < gL; i++) {
+          const double dn = (rc[3 * i] * xg - rc[3 * i + 1]) * dd - rc[3 * i + 2] * ddm1;
+          ddm1 = dd;
+          dd = dn;
+          out[i * INV_GS] = (T)dd;
         }
       }
       __syncthreads();
