@@ -160,10 +160,11 @@ struct CoefRound {
   }
 };
 
-// Forward contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
-// pairs w and w + 8 of the tile.  The workgroup streams the tile's S slab and
-// table rows through LDS in chunks of KC nodes, fetching chunk c+1 into
-// registers (16-byte loads) while the matrix cores work on chunk c.
+// Forward contraction.  One workgroup per (pair tile, signal tile), in the
+// order of contraction_slot; 8 waves; wave w owns pairs w and w + 8 of the
+// tile.  The workgroup streams the tile's S slab and table rows through LDS
+// in chunks of KC nodes, fetching chunk c+1 into registers (16-byte loads)
+// while the matrix cores work on chunk c.
 constexpr int FWD_THREADS = 512;
 
 // KC: beta nodes per streamed chunk.  4 in FP32 when the grid has at least
@@ -354,16 +355,19 @@ template <class T, int RTMAX, int KC, int BT>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ coeffs, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_body<T, RTMAX, KC, BT>(S, coeffs, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
+  if (!sl.valid) return;
+  beta_forward_body<T, RTMAX, KC, BT>(S, coeffs, p, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
-// Inverse contraction.  Grid: (pair tiles, signal tiles), 8 waves; wave w owns
-// pairs w and w + 8.  Each wave keeps its pairs' scaled coefficients as
-// matrix-core B operands in registers, then sweeps the N nodes in blocks of
-// 16; a block's outputs for all 16 pairs are gathered in LDS and written as
-// full PT-pair rows of S.  The table values of the next block are requested
-// before the current block's products (see fetch_a), and the stores of S stay
-// in flight while the next block's products run.
+// Inverse contraction.  One workgroup per (pair tile, signal tile), in the
+// order of contraction_slot; 8 waves; wave w owns pairs w and w + 8.  Each
+// wave keeps its pairs' scaled coefficients as matrix-core B operands in
+// registers, then sweeps the N nodes in blocks of 16; a block's outputs for
+// all 16 pairs are gathered in LDS and written as full PT-pair rows of S.
+// The table values of the next block are requested before the current
+// block's products (see fetch_a), and the stores of S stay in flight while
+// the next block's products run.
 constexpr int INV_THREADS = 512;
 
 // staging buffer: 16 node rows of BT (signal) rows of PB reals, each node row
@@ -516,7 +520,9 @@ template <class T, int LQ, int BT>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
                                                                    cpx<T>* __restrict__ S, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_body<T, LQ, BT>(coeffs, S, p, p.tile0 + blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
+  if (!sl.valid) return;
+  beta_inverse_body<T, LQ, BT>(coeffs, S, p, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
 // allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)
@@ -548,7 +554,7 @@ static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx
                                                    hipSuccess || cus < 1)
         cus = 256;
     }
-    if (2LL * grid.x * grid.y >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
+    if (2LL * grid.x >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
   }
   return launch_forward_shape<T, RTMAX, 8, BT>(p, grid, S, coeffs, s);
 }
@@ -559,12 +565,12 @@ hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* 
   constexpr int BTN = BTW > 16 ? 16 : BTW;  // for batches of at most 16
   const int rt = beta_rtmax(p.B);
   if (BTN != BTW && p.batch <= BTN) {
-    dim3 grid(p.ntiles - p.tile0, (p.batch + BTN - 1) / BTN);
+    const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + BTN - 1) / BTN));
     if (rt == 1) return launch_forward_rt<T, 1, BTN>(p, grid, S, coeffs, s);
     if (rt == 2) return launch_forward_rt<T, 2, BTN>(p, grid, S, coeffs, s);
     return launch_forward_rt<T, 4, BTN>(p, grid, S, coeffs, s);
   }
-  dim3 grid(p.ntiles - p.tile0, (p.batch + BTW - 1) / BTW);
+  const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + BTW - 1) / BTW));
   if (rt == 1) return launch_forward_rt<T, 1, BTW>(p, grid, S, coeffs, s);
   if (rt == 2) return launch_forward_rt<T, 2, BTW>(p, grid, S, coeffs, s);
   return launch_forward_rt<T, 4, BTW>(p, grid, S, coeffs, s);
@@ -575,7 +581,7 @@ hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx
   constexpr int BTW = BetaCfg<T>::BT;                             // widest signal tile
   constexpr int BTN = BTW > 16 ? 16 : BTW;                         // for batches of at most 16
   const int bt = p.batch <= BTN ? BTN : BTW;
-  dim3 grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt);
+  const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt));
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);
   hipError_t e;

@@ -58,7 +58,8 @@ constexpr int XB_BT = 32;   // inverse: signals per workgroup (64 real columns)
 constexpr int XBF_BT = 16;  // forward: signals per workgroup (a 32-node S chunk is 64 KB)
 constexpr int XB_KC = 32;   // nodes per chunk = K of one matrix instruction
 
-// Forward.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8.
+// Forward.  One workgroup per (pair tile, signal tile), in the order of
+// contraction_slot; wave w owns pairs w and w + 8.
 // S streams through LDS in chunks of 32 nodes with register prefetch; the
 // table operand is read straight from the node-interleaved layout.
 constexpr size_t XBF_SMEM = (size_t)XB_KC * (XBF_BT * (2 * PT + 2) + 16) * sizeof(float);
@@ -234,10 +235,13 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT);
+  if (!sl.valid) return;
+  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
-// Inverse.  Grid (pair tiles, signal tiles); wave w owns pairs w and w + 8 and
+// Inverse.  One workgroup per (pair tile, signal tile), in the order of
+// contraction_slot; wave w owns pairs w and w + 8 and
 // keeps their split, scaled coefficients as B operands (32 degrees per
 // instruction), gathered through LDS like the FP32 path's; the nodes are swept
 // in blocks of 16 (the table words of the next block requested before the
@@ -386,7 +390,9 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, blockIdx.x, blockIdx.y, smem_raw, threadIdx.x);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + BT - 1) / BT);
+  if (!sl.valid) return;
+  beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
 // Reorder the tile-major split table into the node-interleaved forward layout.
@@ -415,7 +421,7 @@ static hipError_t set_smem_bf(K kern, size_t smem) {
 
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s) {
-  dim3 grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT);
+  const dim3 grid(contraction_grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT));
   const int rt = beta_rtmax(p.B);
   hipError_t e;
 #define SU2_XBF_CASE(R)                                                                                           \
@@ -435,7 +441,7 @@ hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned
                                       cpx<float>* S, hipStream_t s) {
   const bool narrow = p.batch <= 16;  // 16-signal tiles
   const int bt = narrow ? 16 : XB_BT;
-  dim3 grid(p.ntiles, (p.batch + bt - 1) / bt);
+  const dim3 grid(contraction_grid(p.ntiles, (p.batch + bt - 1) / bt));
   const int lq2 = beta_bf16_lq(p.B);
   hipError_t e;
 #define SU2_XBI_CASE(Q, BTC)                                                                                  \

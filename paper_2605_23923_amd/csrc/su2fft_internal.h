@@ -192,6 +192,33 @@ __host__ __device__ inline size_t coef_offset(const long long* coff, int b, long
   return coff ? (size_t)coff[b] : (size_t)b * ncoef;
 }
 
+// Launch order of the contraction workgroups.  The dispatcher hands
+// workgroup ids to the eight XCDs round robin (id % 8), and the ids one XCD
+// receives start in order, side by side.  Every workgroup that reads the same
+// table block (the signal tiles of one pair tile) therefore gets consecutive
+// slots of one XCD: the first brings the block into that XCD's L2 and the
+// others read it there at about the same time.  Pair tiles go to the XCDs
+// round robin (tile % 8), so the ragged per-tile costs stay balanced over
+// them.  A one-dimensional grid of contraction_grid() workgroups covers
+// ntl pair tiles x nbt signal tiles; the few slots past the last tile
+// return at once.
+constexpr int NXCD = 8;
+struct TileSlot {
+  int tile, bt;
+  bool valid;
+};
+__host__ __device__ inline TileSlot contraction_slot(int id, int ntl, int nbt) {
+  const int x = id % NXCD, r = id / NXCD;
+  TileSlot s;
+  s.tile = (r / nbt) * NXCD + x;
+  s.bt = r % nbt;
+  s.valid = s.tile < ntl;
+  return s;
+}
+__host__ __device__ inline unsigned contraction_grid(int ntl, int nbt) {
+  return (unsigned)(((ntl + NXCD - 1) / NXCD) * NXCD * nbt);
+}
+
 // bf16 split table entry (hi, lo) for the split-precision contraction
 struct bf16x2_t {
   unsigned short hi, lo;
