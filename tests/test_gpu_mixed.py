@@ -14,11 +14,12 @@ import torch
 import oracle
 import paper_2605_23923_amd as su2
 import synth
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
 NPDT = {"c128": np.complex128, "c64": np.complex64, "c64_bf16x3": np.complex64}
-TOL = {"c128": 1e-10, "c64": 2e-5, "c64_bf16x3": 1e-5}
+TOL = {"c128": 1e-10, "c64": 1e-6, "c64_bf16x3": 1e-5}
 
 
 def _dev(a):
@@ -79,10 +80,14 @@ def test_mixed_matches_oracle_one_signal_per_bandlimit(dtype):
         ref = oracle.forward(B, xs[s].astype(np.complex128), sel)
         got = f[s][sel]
         rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        record(f"mixed forward B={B} {dtype} sampled", rel, np.max(np.abs(got - ref)) / np.max(np.abs(ref)),
+               tol=TOL[dtype])
         assert rel <= TOL[dtype], (B, rel)
         pts = rng.choice((2 * B) ** 3, 100, replace=False)
         ref = oracle.inverse(B, cs[s].astype(np.complex128), pts)
         rel = np.linalg.norm(inv[s][pts] - ref) / np.linalg.norm(ref)
+        record(f"mixed inverse B={B} {dtype} sampled", rel, np.max(np.abs(inv[s][pts] - ref)) / np.max(np.abs(ref)),
+               tol=TOL[dtype])
         assert rel <= TOL[dtype], (B, rel)
 
 
@@ -156,5 +161,7 @@ def test_mixed_batch_configuration_320_signals():
             sel = rng.choice(C, 64, replace=False)
             ref = oracle.forward(B, xs[s].astype(np.complex128), sel)
             rel = np.linalg.norm(f[s][sel] - ref) / np.linalg.norm(ref)
+            record(f"mixed 320-signal forward B={B} c64 sampled", rel,
+                   np.max(np.abs(f[s][sel] - ref)) / np.max(np.abs(ref)), tol=TOL["c64"])
             assert rel <= TOL["c64"], (B, rel)
     assert checked == set(Bs[256:])

@@ -2,7 +2,7 @@
 contraction kernels (tables="on_the_fly"), against the CPU oracle and against
 the stored-table plans.
 
-Tolerances as in test_gpu_parity.py (1e-10 FP64, 2e-5 FP32; the recurrence
+Tolerances as in test_gpu_parity.py (1e-10 FP64, 1e-6 FP32; the recurrence
 runs in FP64 either way).  Stored and generated tables come from the same
 FP64 recurrence with coefficients rounded differently (device FP64 vs host
 long double), so the two plans agree to rounding of the table values."""
@@ -13,10 +13,12 @@ import torch
 import oracle
 import paper_2605_23923_amd as su2
 import synth
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-10, "c64": 2e-5}
+TOL = {"c128": 1e-10, "c64": 1e-6}
+WORST = 10  # the worst element may be this many times the normwise bound
 NPDT = {"c128": np.complex128, "c64": np.complex64}
 
 
@@ -35,7 +37,8 @@ def _check(got, ref, tol, what):
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     worst = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     print(f"{what}: rel {rel:.3e} worst {worst:.3e}", flush=True)
-    assert rel <= tol and worst <= 30 * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
+    record(what, rel, worst, tol=tol)
+    assert rel <= tol and worst <= WORST * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -78,7 +81,7 @@ def test_otf_b128_round_trip_and_samples(dtype):
     plan = su2.Plan(B, batch, dtype, tables="on_the_fly")
     c = synth.coeffs(B, batch, seed=4, dtype=NPDT[dtype])
     x = plan.inverse(_dev(c))
-    _check(_host(plan.forward(x)), c, 1e-11 if dtype == "c128" else 1e-4, f"otf round trip B=128 {dtype}")
+    _check(_host(plan.forward(x)), c, 1e-11 if dtype == "c128" else 2e-6, f"otf round trip B=128 {dtype}")
     rng = np.random.default_rng(5)
     pts = rng.choice((2 * B) ** 3, 16, replace=False)
     xs = _host(x)

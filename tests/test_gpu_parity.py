@@ -5,9 +5,12 @@ relative to the largest reference element):
 * c128 (FP64 everywhere): 1e-10, the target the transform is specified to;
   observed values are near 1e-14.
 * c64 (FP32 FFT, FP32 matrix-core contraction, tables rounded from FP64):
-  2e-5.  FP32 unit roundoff is 6e-8; the ring FFT has 2 log2 N <= 16 radix
+  1e-6.  FP32 unit roundoff is 6e-8; the ring FFT has 2 log2 N <= 16 radix
   stages and the beta sum runs over N <= 256 terms, so the expected normwise
-  error is a few 1e-7 with a margin of roughly 30x for the worst element.
+  error is a few 1e-7.  Observed on MI355X (every comparison of the GPU
+  suite, B <= 128): at most 3.2e-7 normwise (B = 128) and a worst element at
+  most 2.4x the normwise figure; the bar keeps a 3x margin on the normwise
+  error and allows the worst element 10x the bar (WORST).
 The oracle runs on the same inputs (FP32 inputs are upcast exactly).
 """
 import numpy as np
@@ -17,10 +20,12 @@ import torch
 import oracle
 import paper_2605_23923_amd as su2
 import synth
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-10, "c64": 2e-5}
+TOL = {"c128": 1e-10, "c64": 1e-6}
+WORST = 10  # the worst element may be this many times the normwise bound
 NPDT = {"c128": np.complex128, "c64": np.complex64}
 
 
@@ -40,7 +45,8 @@ def _check(got, ref, tol, what):
     rel = np.linalg.norm(got - ref) / nrm
     worst = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     print(f"{what}: rel {rel:.3e} worst {worst:.3e}", flush=True)
-    assert rel <= tol and worst <= 30 * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
+    record(what, rel, worst, tol=tol)
+    assert rel <= tol and worst <= WORST * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
 
 
 SMALL_B = [1, 2, 3, 4, 6, 8, 12, 16, 24]
@@ -198,7 +204,7 @@ def test_max_bandlimit_b128_sampled(dtype):
     c = synth.coeffs(B, batch, seed=4, dtype=NPDT[dtype])
     x = plan.inverse(_dev(c))
     back = _host(plan.forward(x))
-    tol_rt = 1e-11 if dtype == "c128" else 1e-4
+    tol_rt = 1e-11 if dtype == "c128" else 2e-6  # observed 2.8e-7 (FP32)
     _check(back, c, tol_rt, f"round trip B=128 {dtype}")
     xs = _host(x)
     del x
@@ -252,6 +258,15 @@ def test_wrong_tensor_arguments_are_rejected():
         plan.forward(torch.zeros((2, 8, 8, 8), dtype=torch.complex128, device="cuda"))
     with pytest.raises(ValueError):
         plan.forward(torch.zeros((1, 8, 8, 8), dtype=torch.complex64, device="cuda"))
+    # single stages check the tensor they read or write before any launch
+    with pytest.raises(ValueError):
+        plan.run_stage("ring_forward", None, None)
+    with pytest.raises(TypeError):
+        plan.run_stage("beta_forward", None, torch.zeros(plan.coeff_shape, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.run_stage("beta_inverse", torch.zeros((1, plan.ncoef), dtype=torch.complex64, device="cuda"), None)
+    with pytest.raises(ValueError):
+        plan.run_stage("ring_adjoint", None, torch.zeros((2, 8, 8, 4), dtype=torch.complex64, device="cuda"))
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

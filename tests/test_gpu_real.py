@@ -10,10 +10,12 @@ import torch
 import oracle
 import paper_2605_23923_amd as su2
 import synth
+from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-10, "c64": 2e-5}
+TOL = {"c128": 1e-10, "c64": 1e-6}
+WORST = 10  # the worst element may be this many times the normwise bound
 RDT = {"c128": np.float64, "c64": np.float32}
 CDT = {"c128": np.complex128, "c64": np.complex64}
 
@@ -33,7 +35,8 @@ def _check(got, ref, tol, what):
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     worst = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     print(f"{what}: rel {rel:.3e} worst {worst:.3e}", flush=True)
-    assert rel <= tol and worst <= 30 * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
+    record(what, rel, worst, tol=tol)
+    assert rel <= tol and worst <= WORST * tol, f"{what}: rel {rel:.3e} worst {worst:.3e} tol {tol}"
 
 
 def _real_samples(B, batch, seed, dtype):
