@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
+# (B, batch) of the shapes bench.py can time stage by stage
+WORKLOADS = {"b64_batch32": (64, 32), "b128_batch16": (128, 16)}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
 # a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf"
 # (Wigner-d values generated inside the contraction kernels instead of stored)
@@ -489,6 +491,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes three times (reference for "
                          "the HBM byte counters) and exit")
+    ap.add_argument("--workload", default="b64_batch32", choices=sorted(WORKLOADS),
+                    help="b64_batch32 (default): the headline line.  b128_batch16: only the B=128 batch 16 shape "
+                         "(256^3 grid), stage by stage for --mode and --other-modes, printed as one JSON object "
+                         "(for profiling; not the headline line)")
     ap.add_argument("--shifted-forms", action="store_true",
                     help="only time the forward contraction in its table and shifted-recurrence forms at B=64 "
                          "batch 32 (c64 plan), print that JSON object and exit")
@@ -519,10 +525,20 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
 
-    B, batch = 64, 32
+    B, batch = WORKLOADS[args.workload]
     digest = source_digest()
     import paper_2605_23923_amd as su2
     su2.Plan(4, 1, "c64").close()   # loads the code objects, so that plan_ms is set-up alone
+    if args.workload != "b64_batch32":
+        modes = {}
+        for m in [args.mode] + [m for m in args.other_modes.split(",") if m and m != args.mode]:
+            modes[m] = run_mode(m, B, batch, args.steps, args.warmup, False)
+            print(f"bench.py: {args.workload} {m} done", file=sys.stderr, flush=True)
+        print(json.dumps({"workload": args.workload, "B": B, "batch": batch, "steps": args.steps,
+                          "modes": {m: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+                                    for m, r in modes.items()},
+                          "source_digest": digest}), flush=True)
+        return
     head = run_mode(args.mode, B, batch, args.steps, args.warmup, True)
     modes = {args.mode: head}
     for m in [m for m in args.other_modes.split(",") if m and m != args.mode]:

@@ -178,17 +178,32 @@ typedef enum {
 } su2_stage_t;
 su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream);
 
-/* Sizes and indexing (pure host functions, no device needed). */
-int64_t su2_num_samples(int32_t B);                                    /* (2B)^3, or -1 if B < 1 */
-int64_t su2_num_coeffs(int32_t B);                                     /* B(B+1)(2B+1)/6, or -1   */
-int64_t su2_coeff_index(int32_t two_l, int32_t two_m, int32_t two_n);  /* -1 if not a valid triple */
+/* Sizes and indexing (pure host functions, no device needed).
+ * su2_num_samples: points of the grid of Definition 4.1 (read with N = 2B
+ * periodic nodes per angle): (2B)^3, or -1 if B < 1.
+ * su2_num_coeffs: entries of the coefficient matrices fhat(l) of Definition
+ * 3.4 over every l with 2l < B, i.e. sum over 2l = 0..B-1 of (2l+1)^2 =
+ * B(B+1)(2B+1)/6, or -1 if B < 1.
+ * su2_coeff_index: flat index of fhat(l)_{mn} (doubled indices, the matrix
+ * entry of Definition 3.4 at row m, column n) in the layout described at the
+ * top of this file; -1 unless 0 <= two_l, |two_m|, |two_n| <= two_l and
+ * two_l - two_m, two_l - two_n are even. */
+int64_t su2_num_samples(int32_t B);
+int64_t su2_num_coeffs(int32_t B);
+int64_t su2_coeff_index(int32_t two_l, int32_t two_m, int32_t two_n);
 /* SO(3) plans (SU2_PLAN_SO3): coefficients per signal (integer l, 2l < B), and
  * the flat index of fhat(l)_{mn} from plain integers l, m, n (-1 if invalid). */
 int64_t su2_so3_num_coeffs(int32_t B);
 int64_t su2_so3_coeff_index(int32_t l, int32_t m, int32_t n);
 
-/* Grid nodes and beta weights of the plan's quadrature (host arrays of 2B
- * doubles each; any pointer may be NULL to skip it).  w_beta receives W_k. */
+/* Grid nodes and beta weights of the plan's quadrature: Definition 4.1 read
+ * as an exact rule (periodic alpha and gamma nodes, the printed theta nodes
+ * beta_k = pi k / (2B - 1), Clenshaw-Curtis weights on cos(beta_k), gamma over
+ * [-2 pi, 2 pi) so that half-integer l are resolved; see the grid formula at
+ * the top of this file).  Host arrays of 2B doubles each; any pointer may be
+ * NULL to skip it.  w_beta receives W_k = w_k / (2 N^2).  SU2_ERR_INVALID_VALUE
+ * if B < 1, SU2_ERR_UNSUPPORTED where su2_plan_create would refuse B (B > 128,
+ * or 2B not of the form 2^a 3^b). */
 su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, double* w_beta);
 
 /* Mixed plans: the persistent grid size, in workgroups per compute unit, that

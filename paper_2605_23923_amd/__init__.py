@@ -240,6 +240,18 @@ class _PlanBase:
         """Launch one kernel stage (see su2_run_stage); the ring spectra stay in
         the plan workspace between stages."""
         code = self.STAGES[stage]
+        # the tensor each stage reads or writes is checked like forward/inverse's
+        # arguments: a wrong size or dtype would otherwise reach the kernels
+        needs = {"ring_forward": ("inp", self.total_samples, self.sample_dtype),
+                 "beta_forward": ("out", self.total_coeffs, self.torch_dtype),
+                 "beta_inverse": ("inp", self.total_coeffs, self.torch_dtype),
+                 "beta_adjoint": ("inp", self.total_coeffs, self.torch_dtype),
+                 "ring_inverse": ("out", self.total_samples, self.sample_dtype),
+                 "ring_adjoint": ("out", self.total_samples, self.sample_dtype)}[stage]
+        t = inp if needs[0] == "inp" else out
+        if t is None:
+            raise ValueError(f"run_stage({stage!r}) needs the {needs[0]} tensor")
+        self._check_tensor(t, needs[1], f"run_stage({stage!r}) {needs[0]}", needs[2])
         pin = ctypes.c_void_p(inp.data_ptr()) if inp is not None else ctypes.c_void_p()
         pout = ctypes.c_void_p(out.data_ptr()) if out is not None else ctypes.c_void_p()
         _check(_load().su2_run_stage(self._handle, code, pin, pout, _stream_handle(self.device)), "su2_run_stage")
