@@ -47,6 +47,7 @@
 #ifndef SU2FFT_H
 #define SU2FFT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -156,6 +157,29 @@ su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples,
  * weight W_k in place of (2l+1).  This is the backward map of the forward
  * transform for gradient computation. */
 su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+
+/* su2_forward for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Same
+ * plan, kernels and result as su2_forward (bitwise); the ring spectra between
+ * the two stages go to the library's static device scratch instead of the
+ * plan's workspace, and the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  The scratch is a file-scope device array of
+ * SU2_NOALLOC_SCRATCH_BYTES (64 MiB), one per GPU the library runs on, held
+ * until the process ends; its address on a device is looked up once, at the
+ * first plan creation on that device.  The plan's ring spectra must fit:
+ * bytes = 16 (SU2_C128) or 8 (other dtypes) x 2B x batch x P16, P16 being the
+ * retained (m, n) pairs rounded up to a multiple of 16 (SU(2): P = 2B^2 - 2B + 1;
+ * SO(3) plans: (2L - 1)^2 with L = floor((B - 1) / 2) + 1), e.g. B = 64 in
+ * SU2_C64 up to batch 8.  Larger plans and the B = 128 plans (which use a
+ * second workspace) return SU2_ERR_UNSUPPORTED before any device work.
+ * SU2_ERR_INVALID_VALUE for a null argument, a mixed plan, or a current
+ * device other than the plan's.  Every call on a GPU shares that GPU's
+ * scratch: calls that overlap in time on one GPU (different streams, or
+ * threads) race and must be serialised by the caller.  Nothing in the scratch
+ * needs clearing: a call reads only values it wrote itself.  The scratch keeps
+ * the last call's ring spectra. */
+#define SU2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
 
 /* The kernels behind su2_forward / su2_inverse / su2_adjoint, one at a time,
  * for timing and profiling a single stage.  The intermediate ring spectra stay

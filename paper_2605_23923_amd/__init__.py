@@ -70,6 +70,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp, vp]
         f.restype = i32
+    lib.su2_forward_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.su2_forward_noalloc.restype = i32
     lib.su2_run_stage.argtypes = [vp, i32, vp, vp, vp]
     lib.su2_beta_forward_shifted.argtypes = [vp, i32, i32, vp, vp]
     lib.su2_beta_forward_shifted.restype = i32
@@ -215,6 +217,15 @@ class _PlanBase:
             out = torch.empty(self.coeff_shape, dtype=self.torch_dtype, device=self.device)
         self._check_tensor(out, self.total_coeffs, "out")
         self._call("su2_forward", samples, out)
+        return out
+
+    def forward_noalloc(self, samples: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """su2_forward_noalloc: the forward transform with the ring spectra in
+        the library's static device scratch; `out` must be given (the call
+        allocates nothing)."""
+        self._check_tensor(samples, self.total_samples, "samples", self.sample_dtype)
+        self._check_tensor(out, self.total_coeffs, "out")
+        self._call("su2_forward_noalloc", samples, out)
         return out
 
     def inverse(self, coeffs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -13,6 +14,33 @@
 using namespace su2;
 
 static thread_local int32_t g_last_hip_error = 0;
+
+// ---- scratch of the allocation-free forward (su2_forward_noalloc) ----
+// The ring spectra of a su2_forward_noalloc call live in this file-scope
+// device array: one copy per GPU, held while the process runs.  On the host
+// the array's name only stands for the symbol; host code uses the device
+// address hipGetSymbolAddress returns on each GPU (scratch_address), never
+// the name itself.
+static __device__ __align__(256) unsigned char scratch[SU2_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+// Resolved once per device (at the first plan creation or noalloc call on it).
+static hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 namespace su2 {
 
@@ -208,6 +236,11 @@ su2_status_t build_plan(su2_plan_s* pl) {
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
   pl->device = dev;
+  {
+    // set-up of the noalloc scratch on this device (once per device)
+    void* scr = nullptr;
+    if ((e = scratch_address(dev, &scr)) != hipSuccess) return hip_fail(e);
+  }
   int max_lds = 0;
   if ((e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
     return hip_fail(e);
@@ -442,47 +475,47 @@ const T* table_of(const su2_plan_s* pl) {
 }
 
 template <class T>
-su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s) {
+su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s, void* S) {
   hipError_t e = hipSuccess;
   switch (stage) {
     case SU2_STAGE_RING_FORWARD:
       if (pl->real)
-        e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)pl->d_S, s);
+        e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)S, s);
       else if (pl->large)
-        e = launch_ring_forward_large<T>(large_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+        e = launch_ring_forward_large<T>(large_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
       else if (pl->fast)
-        e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+        e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
       else
-        e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+        e = launch_ring_forward<T>(ring_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
       break;
     case SU2_STAGE_BETA_FORWARD:
       if (pl->otf)
-        e = launch_beta_forward_otf<T>(otf_params<T>(pl, 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+        e = launch_beta_forward_otf<T>(otf_params<T>(pl, 0), (const cpx<T>*)S, (cpx<T>*)out, s);
       else
-        e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+        e = launch_beta_forward<T>(beta_params<T>(pl, table_of<T>(pl), 0), (const cpx<T>*)S, (cpx<T>*)out, s);
       break;
     case SU2_STAGE_BETA_INVERSE:
     case SU2_STAGE_BETA_ADJOINT:
       if (pl->otf)
         e = launch_beta_inverse_otf<T>(otf_params<T>(pl, stage == SU2_STAGE_BETA_ADJOINT), (const cpx<T>*)in,
-                                       (cpx<T>*)pl->d_S, s);
+                                       (cpx<T>*)S, s);
       else
         e = launch_beta_inverse<T>(beta_params<T>(pl, table_of<T>(pl), stage == SU2_STAGE_BETA_ADJOINT),
-                                   (const cpx<T>*)in, (cpx<T>*)pl->d_S, s);
+                                   (const cpx<T>*)in, (cpx<T>*)S, s);
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
       if (pl->real)
         e = launch_ring_inverse_fast_real<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
-                                             (const cpx<T>*)pl->d_S, (T*)out, s);
+                                             (const cpx<T>*)S, (T*)out, s);
       else if (pl->large)
         e = launch_ring_inverse_large<T>(large_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
-                                         (const cpx<T>*)pl->d_S, (cpx<T>*)out, s);
+                                         (const cpx<T>*)S, (cpx<T>*)out, s);
       else if (pl->fast)
-        e = launch_ring_inverse_fast<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
+        e = launch_ring_inverse_fast<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)S,
                                         (cpx<T>*)out, s);
       else
-        e = launch_ring_inverse<T>(ring_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)pl->d_S,
+        e = launch_ring_inverse<T>(ring_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)S,
                                    (cpx<T>*)out, s);
       break;
     default:
@@ -492,30 +525,34 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
   return SU2_OK;
 }
 
-su2_status_t run_stage(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s) {
-  if (pl->dtype == SU2_C128) return run_stage_t<double>(pl, stage, in, out, s);
+// `S` holds the ring spectra between the two stages of a call: the plan's
+// workspace, or (su2_forward_noalloc) the library's static scratch
+su2_status_t run_stage(su2_plan_s* pl, su2_stage_t stage, const void* in, void* out, hipStream_t s,
+                       void* S = nullptr) {
+  if (!S) S = pl->d_S;
+  if (pl->dtype == SU2_C128) return run_stage_t<double>(pl, stage, in, out, s, S);
   if (pl->dtype == SU2_C64_BF16X3) {
     hipError_t e = hipSuccess;
     if (stage == SU2_STAGE_BETA_FORWARD) {
       e = launch_beta_forward_bf16x3(beta_params<float>(pl, nullptr, 0), pl->d_tabbf_fwd,
-                                     (const cpx<float>*)pl->d_S, (cpx<float>*)out, s);
+                                     (const cpx<float>*)S, (cpx<float>*)out, s);
     } else if (stage == SU2_STAGE_BETA_INVERSE || stage == SU2_STAGE_BETA_ADJOINT) {
       e = launch_beta_inverse_bf16x3(beta_params<float>(pl, nullptr, stage == SU2_STAGE_BETA_ADJOINT),
-                                     (const unsigned*)pl->d_tabbf, (const cpx<float>*)in, (cpx<float>*)pl->d_S, s);
+                                     (const unsigned*)pl->d_tabbf, (const cpx<float>*)in, (cpx<float>*)S, s);
     } else {
-      return run_stage_t<float>(pl, stage, in, out, s);
+      return run_stage_t<float>(pl, stage, in, out, s, S);
     }
     if (e != hipSuccess) return hip_fail(e);
     return SU2_OK;
   }
-  return run_stage_t<float>(pl, stage, in, out, s);
+  return run_stage_t<float>(pl, stage, in, out, s, S);
 }
 
 su2_status_t run_pair(su2_plan_s* pl, su2_stage_t first, su2_stage_t second, const void* in, void* out,
-                      hipStream_t s) {
-  su2_status_t st = run_stage(pl, first, in, nullptr, s);
+                      hipStream_t s, void* S = nullptr) {
+  su2_status_t st = run_stage(pl, first, in, nullptr, s, S);
   if (st != SU2_OK) return st;
-  return run_stage(pl, second, nullptr, out, s);
+  return run_stage(pl, second, nullptr, out, s, S);
 }
 
 su2_status_t check_device() {
@@ -672,6 +709,21 @@ su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples,
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
   if (plan->mixed) return run_mixed(plan, 2, d_coeffs, d_samples, (hipStream_t)stream);
   return run_pair(plan, SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT, d_coeffs, d_samples, (hipStream_t)stream);
+}
+
+su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+  if (!plan || !d_samples || !d_coeffs || plan->mixed) return SU2_ERR_INVALID_VALUE;
+  // the two-pass ring kernels (N = 256) keep a second plan-owned buffer
+  if (plan->large) return SU2_ERR_UNSUPPORTED;
+  const size_t need = (plan->dtype == SU2_C128 ? 16 : 8) * (size_t)plan->P_pad * plan->N * plan->batch;
+  if (need > SU2_NOALLOC_SCRATCH_BYTES) return SU2_ERR_UNSUPPORTED;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev != plan->device) return SU2_ERR_INVALID_VALUE;
+  void* S = nullptr;
+  if ((e = scratch_address(dev, &S)) != hipSuccess) return hip_fail(e);
+  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, (hipStream_t)stream, S);
 }
 
 su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream) {

@@ -79,6 +79,7 @@ def test_argument_validation_before_any_device_call():
     assert lib.su2_forward(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
     assert lib.su2_inverse(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
     assert lib.su2_adjoint(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
+    assert lib.su2_forward_noalloc(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 1
     assert lib.su2_plan_destroy(None) == 0
     bs = (ctypes.c_int32 * 2)(8, 5)
     h = ctypes.c_void_p()
