@@ -170,8 +170,9 @@ su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples,
  * bytes = 16 (SU2_C128) or 8 (other dtypes) x 2B x batch x P16, P16 being the
  * retained (m, n) pairs rounded up to a multiple of 16 (SU(2): P = 2B^2 - 2B + 1;
  * SO(3) plans: (2L - 1)^2 with L = floor((B - 1) / 2) + 1), e.g. B = 64 in
- * SU2_C64 up to batch 8.  Larger plans and the B = 128 plans (which use a
- * second workspace) return SU2_ERR_UNSUPPORTED before any device work.
+ * SU2_C64 up to batch 8, B = 128 in SU2_C64 at batch 1.  Larger plans, and
+ * B = 128 plans in SU2_C128 (whose two-pass rings use a second workspace),
+ * return SU2_ERR_UNSUPPORTED before any device work.
  * SU2_ERR_INVALID_VALUE for a null argument, a mixed plan, or a current
  * device other than the plan's.  Every call on a GPU shares that GPU's
  * scratch: calls that overlap in time on one GPU (different streams, or

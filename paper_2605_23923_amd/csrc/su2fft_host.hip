@@ -256,8 +256,10 @@ su2_status_t build_plan(su2_plan_s* pl) {
   // the register-resident ring kernels handle the whole ring themselves and
   // want the pairs ordered by 2m alone
   pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
-  pl->large = !pl->fast && pl->allow_large && large_ring_supported(N);
-  if (pl->fast || pl->large) split = 1;
+  const bool n256 = !pl->fast && pl->allow_large && large_ring_supported(N);
+  pl->sliced = n256 && pl->dtype != SU2_C128;
+  pl->large = n256;
+  if (pl->fast || n256) split = 1;
   pl->split = split;
   pl->Nc = N / split;
   pl->nrad_c = radix_plan(pl->Nc, pl->rad_c);
@@ -481,7 +483,12 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
     case SU2_STAGE_RING_FORWARD:
       if (pl->real)
         e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)S, s);
-      else if (pl->large)
+      else if (pl->sliced) {
+        if constexpr (std::is_same<T, float>::value)
+          e = launch_ring_forward_sliced(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
+        else
+          e = hipErrorInvalidValue;
+      } else if (pl->large)
         e = launch_ring_forward_large<T>(large_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
       else if (pl->fast)
         e = launch_ring_forward_fast<T>(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
@@ -713,8 +720,8 @@ su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples,
 
 su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
   if (!plan || !d_samples || !d_coeffs || plan->mixed) return SU2_ERR_INVALID_VALUE;
-  // the two-pass ring kernels (N = 256) keep a second plan-owned buffer
-  if (plan->large) return SU2_ERR_UNSUPPORTED;
+  // the two-pass forward ring (N = 256 in FP64) keeps a second plan-owned buffer
+  if (plan->large && !plan->sliced) return SU2_ERR_UNSUPPORTED;
   const size_t need = (plan->dtype == SU2_C128 ? 16 : 8) * (size_t)plan->P_pad * plan->N * plan->batch;
   if (need > SU2_NOALLOC_SCRATCH_BYTES) return SU2_ERR_UNSUPPORTED;
   int dev = -1;

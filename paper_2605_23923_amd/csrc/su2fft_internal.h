@@ -283,6 +283,10 @@ hipError_t launch_ring_forward_fast_real(const FastRingParams<T>& p, const T* sa
 template <class T>
 hipError_t launch_ring_inverse_fast_real(const FastRingParams<T>& p, const cpx<T>* S, T* samples, hipStream_t s);
 
+// single-pass N = 256 forward ring in FP32: four workgroups per ring, each
+// holding a quarter of the transform in LDS (no intermediate buffer)
+hipError_t launch_ring_forward_sliced(const FastRingParams<float>& p, const cpx<float>* samples, cpx<float>* S,
+                                      hipStream_t s);
 bool large_ring_supported(int N);
 int large_ring_block();           // gamma frequencies per block (pair ranges are given per block)
 int large_ring_slice_capacity();  // pairs of one block the kernels can stage in LDS

@@ -48,7 +48,8 @@ struct su2_plan_s {
   double* d_seedc = nullptr;
   double* d_rcoef = nullptr;
   double* d_nodes = nullptr;  // [3][N]: cos(beta_k), cos(beta_k / 2), sin(beta_k / 2)
-  bool large = false;
+  bool large = false;            // N = 256: two-pass ring kernels through an intermediate (d_G)
+  bool sliced = false;          // N = 256 in FP32: the forward ring runs in one pass, four workgroups per ring
   bool allow_large = true;  // mixed-plan groups use the generic kernels instead
   int* d_qrange = nullptr;
   void* d_G = nullptr;

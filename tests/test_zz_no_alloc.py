@@ -2,10 +2,10 @@
 spectra in the library's static device scratch.  Its output equals
 su2_forward's on the same plan and input bitwise (the same kernels run on the
 same values; only the buffer between the two stages differs), on two calls in
-a row, the second with a smaller input, so that the second call reads only
-what it wrote over the first call's leftovers.  Plans whose ring spectra do
-not fit the scratch, and plans with a second workspace (B = 128), are refused
-before any device work."""
+a row, each with a smaller input than the one before, so that a call reads
+only what it wrote over the previous call's leftovers.  Plans whose ring
+spectra do not fit the scratch, and plans with a second workspace (B = 128 in
+FP64), are refused before any device work."""
 import ctypes
 
 import numpy as np
@@ -36,9 +36,11 @@ def _noalloc(plan, x, out):
 def test_noalloc_forward_equals_forward_two_calls(dtype):
     npdt = np.complex64 if dtype == "c64" else np.complex128
     cb = 8 if dtype == "c64" else 16
-    # first call: B = 64 (c64: batch 3, 24.8 MB of spectra; c128: batch 1);
-    # second: B = 16, batch 2 (a smaller input over the first call's leftovers)
-    for B, batch in ((64, 3 if dtype == "c64" else 1), (16, 2)):
+    # calls in a row, each with a smaller input than the one before (over the
+    # previous call's leftovers): c64 B = 128 batch 1 (66.6 MB of spectra),
+    # then B = 64 (c64: batch 3, 24.8 MB; c128: batch 1), then B = 16 batch 2
+    shapes = ([(128, 1)] if dtype == "c64" else []) + [(64, 3 if dtype == "c64" else 1), (16, 2)]
+    for B, batch in shapes:
         assert _spectra_bytes(B, batch, cb) <= SCRATCH_BYTES
         print(f"noalloc forward {dtype} B={B} batch {batch}", flush=True)
         plan = su2.Plan(B, batch, dtype)
@@ -61,12 +63,12 @@ def test_noalloc_refuses_what_does_not_fit():
     assert _noalloc(plan, x, out) == 2
     plan.close()
     del x, out
-    # B = 128 batch 1 (66.6 MB of spectra, within the scratch) runs the
-    # two-pass rings, which keep a second plan-owned buffer
-    assert _spectra_bytes(128, 1, 8) <= SCRATCH_BYTES
-    plan = su2.Plan(128, 1, "c64")
-    x = torch.zeros(plan.sample_shape, dtype=torch.complex64, device="cuda")
-    out = torch.zeros(plan.coeff_shape, dtype=torch.complex64, device="cuda")
+    # B = 128 in FP64: 133 MB of spectra, and two-pass rings with a second
+    # plan-owned buffer
+    assert _spectra_bytes(128, 1, 16) > SCRATCH_BYTES
+    plan = su2.Plan(128, 1, "c128")
+    x = torch.zeros(plan.sample_shape, dtype=torch.complex128, device="cuda")
+    out = torch.zeros(plan.coeff_shape, dtype=torch.complex128, device="cuda")
     assert _noalloc(plan, x, out) == 2
     plan.close()
     del x, out
