@@ -78,12 +78,16 @@ def num_coeffs(B: int, mode: str) -> int:
 def table_bytes(B: int, mode: str) -> int:
     """Table bytes a contraction launch reads: the stored table, or the
     scalars of the generated one (3 recurrence coefficients per degree, a
-    seed constant per pair, 3 values per node, all FP64)."""
+    seed constant per pair, 3 values per node, all FP64).  The stored table
+    is symmetry-reduced: the pairs (m, n) and (-m, -n) share one column up to
+    the sign (-1)^{m-n}, so it holds (C + C0) / 2 columns of 2B nodes, C0
+    being the coefficients with m = n = 0 (one per integer l)."""
     C = num_coeffs(B, mode)
     if mode.endswith("_otf"):
         return 8 * (3 * C + retained_pairs(B) + 3 * 2 * B)
     es = {"c128": 8, "c64": 4, "c64_bf16x3": 4}[base_mode(mode)]
-    return C * 2 * B * es
+    C0 = (B - 1) // 2 + 1
+    return (C + C0) // 2 * 2 * B * es
 
 
 def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
@@ -106,12 +110,13 @@ def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     if mode.endswith("_real"):
         # real samples; spectra of the (P + 1) / 2 pairs with 2m >= 0 (mirrors
         # excluded); every coefficient written (forward) or read (inverse);
-        # the table rows of those pairs
+        # the table columns of those pairs (one per (m, n), (-m, -n) couple:
+        # the whole symmetry-reduced table)
         ring = N ** 3 * cb // 2
         spec = (retained_pairs(B) + 1) // 2 * N * cb
         if stage.startswith("ring"):
             return batch * (ring + spec)
-        return batch * (spec + coef) + table_bytes(B, base_mode(mode)) // 2
+        return batch * (spec + coef) + table_bytes(B, base_mode(mode))
     if stage.startswith("ring"):
         return batch * (ring + spec)
     return batch * (spec + coef) + table_bytes(B, mode)

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT, p.paired);
   if (!sl.valid) return;
   beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + BT - 1) / BT);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + BT - 1) / BT);  // natural order
   if (!sl.valid) return;
   beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
@@ -401,6 +401,7 @@ __global__ void interleave_bf16_table_kernel(int N, const PairInfo* __restrict__
                                              unsigned* __restrict__ dst) {
   const int NB8 = (N + 7) / 8;
   const PairInfo p0 = pairs[blockIdx.y * PT];
+  if (!p0.towner) return;  // a mirror tile: its block is its mirror's
   const long long cnt = (long long)NB8 * 8 * p0.lsum;
   const long long base = (p0.tab / N) * (long long)NB8 * 8;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (long long)gridDim.x * blockDim.x) {
@@ -421,7 +422,7 @@ static hipError_t set_smem_bf(K kern, size_t smem) {
 
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s) {
-  const dim3 grid(contraction_grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT));
+  const dim3 grid(contraction_grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT, p.paired));
   const int rt = beta_rtmax(p.B);
   hipError_t e;
 #define SU2_XBF_CASE(R)                                                                                           \

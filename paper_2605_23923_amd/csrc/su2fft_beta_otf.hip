@@ -234,7 +234,7 @@ template <class T, int RTMAX, int BT>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_otf_kernel(const cpx<T>* __restrict__ S,
                                                                        cpx<T>* __restrict__ coeffs, OtfParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.b.ntiles, (p.b.batch + BT - 1) / BT, p.b.paired);
   if (!sl.valid) return;
   beta_forward_otf_body<T, RTMAX, BT>(S, coeffs, p, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
@@ -417,7 +417,7 @@ template <class T, int LQ, bool GEN_LDS, int BT>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_otf_kernel(const cpx<T>* __restrict__ coeffs,
                                                                        cpx<T>* __restrict__ S, OtfParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.b.ntiles, (p.b.batch + BT - 1) / BT);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.b.ntiles, (p.b.batch + BT - 1) / BT, p.b.paired);
   if (!sl.valid) return;
   beta_inverse_otf_body<T, LQ, GEN_LDS, BT>(coeffs, S, p, sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
@@ -438,7 +438,7 @@ template <class T>
 hipError_t launch_beta_forward_otf(const OtfParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
   constexpr int BTW = BetaCfg<T>::BT, BTN = BTW > 16 ? 16 : BTW;  // widest tile; batches of at most 16
   const int bt = p.b.batch <= BTN ? BTN : BTW;
-  const dim3 grid(contraction_grid(p.b.ntiles, (p.b.batch + bt - 1) / bt));
+  const dim3 grid(contraction_grid(p.b.ntiles, (p.b.batch + bt - 1) / bt, p.b.paired));
   const int rt = beta_rtmax(p.b.B);
   hipError_t e;
 #define SU2_OTF_FWD(R, BTC)                                                                                     \
@@ -464,7 +464,7 @@ template <class T>
 hipError_t launch_beta_inverse_otf(const OtfParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
   constexpr int BTW = BetaCfg<T>::BT, BTN = BTW > 16 ? 16 : BTW;  // widest tile; batches of at most 16
   const int bt = p.b.batch <= BTN ? BTN : BTW;
-  const dim3 grid(contraction_grid(p.b.ntiles, (p.b.batch + bt - 1) / bt));
+  const dim3 grid(contraction_grid(p.b.ntiles, (p.b.batch + bt - 1) / bt, p.b.paired));
   const int lq = beta_lq(p.b.B);
   hipError_t e;
 #define SU2_OTF_INV(Q, BTC)                                                                                   \

@@ -298,32 +298,133 @@ su2_status_t build_plan(su2_plan_s* pl) {
     pl->cls_end[r] = (int)pairs.size();
   }
   pl->P = (int)pairs.size();
-  pl->P_pad = (pl->P + PT - 1) / PT * PT;
-  pl->ntiles = pl->P_pad / PT;
-  while ((int)pairs.size() < pl->P_pad) {
+  // Layout of the pair list.  Point-symmetric where the ring kernels take the
+  // pairs in one class ordered by (2m, 2n) (the list is then centrally
+  // symmetric: its mirror (-m, -n) of position i sits at P - 1 - i), the plan
+  // keeps a table (the on-the-fly plans keep none) and the padding fits the
+  // ring kernels' slices: the pairs with 2m < 0, padded to whole tiles; the
+  // 2m = 0 run with one pad right after (0, 0) and as many pads on both ends
+  // as whole tiles need; the pads of the first part again; the pairs with
+  // 2m > 0.  Position i then mirrors position P_pad - 1 - i, tile t mirrors
+  // tile ntiles - 1 - t, and the upper tiles share the lower tiles' table
+  // blocks (PairInfo::tsign).  Otherwise the pairs keep their order and the
+  // list is padded at the end.
+  auto pad_pair = []() {
     PairInfo pi;
     pi.tm = 0; pi.tn = 0; pi.tl0 = 0; pi.L = 0; pi.tab = 0; pi.lsum = 0; pi.coff = 0; pi.itab = 0;
-    pairs.push_back(pi);
-    fftpos.push_back(0);
-    rho_e.push_back(0);
+    pi.tsign = 1; pi.towner = 1;
+    return pi;
+  };
+  std::vector<int> order;  // index into `pairs` per position, -1 for a pad
+  bool sym = split == 1 && !pl->otf && (pl->fast || n256);  // not the generic ring kernel (class ranges)
+  if (sym) {
+    int nA = 0, R0 = 0;
+    for (const PairInfo& q : pairs) { nA += q.tm < 0; R0 += q.tm == 0; }
+    const int nA16 = (nA + PT - 1) / PT * PT;
+    int R16 = R0 + 1;                       // R0 is odd: the run is symmetric about (0, 0)
+    while (R16 % PT) R16 += 2;
+    const int a2 = (R16 - R0 - 1) / 2;
+    for (int i = 0; i < nA; i++) order.push_back(i);
+    for (int i = nA; i < nA16 + a2; i++) order.push_back(-1);
+    for (int i = 0; i <= R0 / 2; i++) order.push_back(nA + i);      // (0, n <= 0)
+    order.push_back(-1);                                            // the mirror of (0, 0)
+    for (int i = R0 / 2 + 1; i < R0; i++) order.push_back(nA + i);  // (0, n > 0)
+    for (int i = 0; i < a2 + nA16 - nA; i++) order.push_back(-1);
+    for (int i = nA + R0; i < pl->P; i++) order.push_back(i);
+    // check the mirror property position by position (pads pair with pads or (0, 0))
+    const int T = (int)order.size();
+    for (int i = 0; i < T && sym; i++) {
+      const int a = order[i], b = order[T - 1 - i];
+      if (a < 0 || b < 0) {
+        const int o = a < 0 ? b : a;
+        sym = o < 0 || (pairs[o].tm == 0 && pairs[o].tn == 0);
+      } else {
+        sym = pairs[a].tm == -pairs[b].tm && pairs[a].tn == -pairs[b].tn;
+      }
+    }
+    if (T % PT) sym = false;
+    // the slices of the register-resident ring kernels must still fit
+    if (sym && pl->fast) {
+      const int cap = pl->dtype == SU2_C128 ? fast_ring_slice_capacity<double>(N) : fast_ring_slice_capacity<float>(N);
+      int rb[FAST_ROUNDS], re[FAST_ROUNDS];
+      for (int r = 0; r < FAST_ROUNDS; r++) { rb[r] = T; re[r] = 0; }
+      for (int i = 0; i < T; i++) {
+        if (order[i] < 0) continue;
+        const int r = bin_q(pairs[order[i]].tm) / (N / FAST_ROUNDS);
+        rb[r] = std::min(rb[r], i);
+        re[r] = std::max(re[r], i + 1);
+      }
+      for (int r = 0; r < FAST_ROUNDS; r++)
+        if (re[r] > rb[r] && re[r] - rb[r] > cap) sym = false;
+    }
   }
-  // tile-major table blocks
-  for (int t0 = 0; t0 < pl->P_pad; t0 += PT) {
+  if (!sym) {
+    order.clear();
+    for (int i = 0; i < pl->P; i++) order.push_back(i);
+    while (order.size() % PT) order.push_back(-1);
+  }
+  pl->sym = sym;
+  {
+    std::vector<PairInfo> np;
+    std::vector<int> nf, nr;
+    for (int o : order) {
+      if (o < 0) {
+        np.push_back(pad_pair());
+        nf.push_back(0);
+        nr.push_back(0);
+      } else {
+        PairInfo q = pairs[o];
+        q.tsign = 1;
+        q.towner = 1;
+        np.push_back(q);
+        nf.push_back(fftpos[o]);
+        nr.push_back(rho_e[o]);
+      }
+    }
+    pairs.swap(np);
+    fftpos.swap(nf);
+    rho_e.swap(nr);
+  }
+  pl->P_pad = (int)pairs.size();
+  pl->ntiles = pl->P_pad / PT;
+  // tile-major table blocks; with the symmetric layout the upper tiles point
+  // at their mirrors' blocks
+  long long itab = 0;
+  for (int t = 0; t < pl->ntiles; t++) {
+    const int t0 = t * PT, tm_ = pl->ntiles - 1 - t;
+    if (sym && tm_ < t) {
+      const int m0 = tm_ * PT;
+      for (int i = 0; i < PT; i++) {
+        PairInfo& q = pairs[t0 + i];
+        const PairInfo& mq = pairs[m0 + PT - 1 - i];
+        q.tab = mq.tab;
+        q.lsum = mq.lsum;
+        q.coff = mq.coff;
+        q.itab = mq.itab;
+        q.towner = 0;
+        q.tsign = (q.L > 0 && (((q.tm - q.tn) / 2) & 1)) ? -1 : 1;
+      }
+      continue;
+    }
     int lsum = 0;
     for (int i = 0; i < PT; i++) { pairs[t0 + i].coff = lsum; lsum += pairs[t0 + i].L; }
-    for (int i = 0; i < PT; i++) { pairs[t0 + i].tab = tab; pairs[t0 + i].lsum = lsum; }
+    for (int i = 0; i < PT; i++) {
+      pairs[t0 + i].tab = tab;
+      pairs[t0 + i].lsum = lsum;
+      pairs[t0 + i].itab = itab;
+      itab += inverse_table_elems(pairs[t0 + i].L, N);
+    }
     tab += (long long)N * lsum;
   }
   pl->tab_elems = tab;
-  long long itab = 0;
-  for (auto& pi : pairs) { pi.itab = itab; itab += inverse_table_elems(pi.L, N); }
   pl->itab_elems = itab;
   pl->h_pairs = pairs;
   // bin -> pair map for the register-resident ring kernels, and the pair range
   // of each slice of q values they process together
   std::vector<int> bins((size_t)N * N, -1);
-  for (int r = 0; r < FAST_ROUNDS; r++) { pl->rbeg[r] = pl->P; pl->rend[r] = 0; }
-  for (int pidx = 0; pidx < pl->P; pidx++) {
+  for (int r = 0; r < FAST_ROUNDS; r++) { pl->rbeg[r] = pl->P_pad; pl->rend[r] = 0; }
+  for (int pidx = 0; pidx < pl->P_pad; pidx++) {
+    if (pairs[pidx].L == 0) continue;  // padding
     const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
     const int q = bin_q(tm);
     const int palpha = bin_p(tn);
@@ -337,10 +438,11 @@ su2_status_t build_plan(su2_plan_s* pl) {
   std::vector<int> bins_real;
   if (pl->real) {
     std::vector<int> at((size_t)(2 * B - 1) * (2 * B - 1), -1);
-    for (int pidx = 0; pidx < pl->P; pidx++)
-      at[(size_t)(pairs[pidx].tm + B - 1) * (2 * B - 1) + pairs[pidx].tn + B - 1] = pidx;
+    for (int pidx = 0; pidx < pl->P_pad; pidx++)
+      if (pairs[pidx].L > 0) at[(size_t)(pairs[pidx].tm + B - 1) * (2 * B - 1) + pairs[pidx].tn + B - 1] = pidx;
     bins_real.assign((size_t)N * N, -1);
-    for (int pidx = 0; pidx < pl->P; pidx++) {
+    for (int pidx = 0; pidx < pl->P_pad; pidx++) {
+      if (pairs[pidx].L == 0) continue;
       const int tm = pairs[pidx].tm, tn = pairs[pidx].tn;
       const int q = imod(tm, N);
       const int palpha = imod((tn & 1) ? (tn - 1) / 2 : tn / 2, N);
@@ -360,8 +462,9 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if (pl->large) {
     const int qb = large_ring_block(), nblk = N / qb;
     qrange.assign(2 * nblk, 0);
-    for (int blk = 0; blk < nblk; blk++) { qrange[2 * blk] = pl->P; qrange[2 * blk + 1] = 0; }
-    for (int pidx = 0; pidx < pl->P; pidx++) {
+    for (int blk = 0; blk < nblk; blk++) { qrange[2 * blk] = pl->P_pad; qrange[2 * blk + 1] = 0; }
+    for (int pidx = 0; pidx < pl->P_pad; pidx++) {
+      if (pairs[pidx].L == 0) continue;
       const int blk = imod(pairs[pidx].tm, N) / qb;
       qrange[2 * blk] = std::min(qrange[2 * blk], pidx);
       qrange[2 * blk + 1] = std::max(qrange[2 * blk + 1], pidx + 1);
@@ -745,9 +848,9 @@ su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, v
 su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L) {
   if (!plan || plan->mixed || (!host_out && !L)) return SU2_ERR_INVALID_VALUE;
   if (plan->otf && host_out) return SU2_ERR_UNSUPPORTED;
-  for (int p = 0; p < plan->P; p++) {
+  for (int p = 0; p < plan->P_pad; p++) {
     const PairInfo& pi = plan->h_pairs[p];
-    if (pi.tm != two_m || pi.tn != two_n) continue;
+    if (pi.L == 0 || pi.tm != two_m || pi.tn != two_n) continue;
     if (L) *L = pi.L;
     if (host_out) {
       std::vector<double> rows((size_t)plan->N * pi.lsum);
@@ -755,7 +858,8 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
                                hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(e);
       for (int k = 0; k < plan->N; k++)
-        for (int i = 0; i < pi.L; i++) host_out[(size_t)k * pi.L + i] = rows[(size_t)k * pi.lsum + pi.coff + i];
+        for (int i = 0; i < pi.L; i++)
+          host_out[(size_t)k * pi.L + i] = pi.tsign * rows[(size_t)k * pi.lsum + pi.coff + i];
     }
     return SU2_OK;
   }

@@ -45,6 +45,15 @@ __host__ __device__ inline cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im
 // tile-major: the PT pairs of a tile share rows k of length lsum = sum of
 // their L, so that the table slice of one tile and one node range is a single
 // contiguous block:  d^{l0 + i}_{nm}(beta_k) = tab[tab + k * lsum + coff + i].
+//
+// Symmetry-reduced tables.  d^l_{-n,-m} = d^l_{mn} = (-1)^{m-n} d^l_{nm}: the
+// pair (-m, -n) has the table of (m, n) times (-1)^{m-n}.  Plans whose pair
+// list is laid out point-symmetrically (position i holds the mirror of
+// position P_pad - 1 - i, so tile t is the mirror of tile ntiles - 1 - t with
+// its pairs in reverse order) store the blocks of the lower tiles only; a
+// pair of an upper tile points at its mirror's column (tab, lsum, coff, itab)
+// with tsign = (-1)^{m-n}, and the contractions multiply the values they
+// read from a stored table by tsign.
 struct PairInfo {
   int tm, tn;     // doubled m, n
   int tl0;        // doubled lowest degree: max(|tm|, |tn|)
@@ -53,6 +62,8 @@ struct PairInfo {
   int lsum;       // row length of the tile block
   int coff;       // column offset of this pair inside a row
   long long itab; // offset of the pair's values in the inverse-layout table (elements)
+  int tsign;      // the stored column holds tsign x this pair's values (+1 or -1)
+  int towner;     // 1: the column was generated for this pair; 0: it is its mirror's
 };
 
 // Inverse-layout table: the values one wave of the inverse contraction loads
@@ -140,6 +151,8 @@ struct BetaParams {
   int real;
   int tile0;                // first pair tile launched (grid x = ntiles - tile0)
   int so3;                  // SO(3) plan: integer-l coefficient layout
+  int table_signs;          // stored tables with mirror columns: multiply read values by PairInfo::tsign
+  int paired;               // mirror tiles t, ntiles - 1 - t share a table block: the forward launches them side by side
 };
 
 // flat coefficient index of (2l, 2m, 2n): the SU(2) layout (2l-major blocks of
@@ -195,28 +208,34 @@ __host__ __device__ inline size_t coef_offset(const long long* coff, int b, long
 // Launch order of the contraction workgroups.  The dispatcher hands
 // workgroup ids to the eight XCDs round robin (id % 8), and the ids one XCD
 // receives start in order, side by side.  Every workgroup that reads the same
-// table block (the signal tiles of one pair tile) therefore gets consecutive
-// slots of one XCD: the first brings the block into that XCD's L2 and the
-// others read it there at about the same time.  Pair tiles go to the XCDs
-// round robin (tile % 8), so the ragged per-tile costs stay balanced over
-// them.  A one-dimensional grid of contraction_grid() workgroups covers
-// ntl pair tiles x nbt signal tiles; the few slots past the last tile
-// return at once.
+// table block (the signal tiles of one pair tile, and with `paired` those of
+// its mirror tile ntl - 1 - tile as well) therefore gets consecutive slots of
+// one XCD: the first brings the block into that XCD's L2 and the others read
+// it there at about the same time.  Units (tiles, or mirror pairs of tiles)
+// go to the XCDs round robin (unit % 8), so the ragged per-tile costs stay
+// balanced over them.  A one-dimensional grid of contraction_grid()
+// workgroups covers ntl pair tiles x nbt signal tiles; the few slots past the
+// last unit (and the mirror slot of a self-mirror middle tile) return at once.
 constexpr int NXCD = 8;
 struct TileSlot {
   int tile, bt;
   bool valid;
 };
-__host__ __device__ inline TileSlot contraction_slot(int id, int ntl, int nbt) {
+__host__ __device__ inline TileSlot contraction_slot(int id, int ntl, int nbt, int paired = 0) {
+  const int per = paired ? 2 * nbt : nbt;
+  const int nunits = paired ? (ntl + 1) / 2 : ntl;
   const int x = id % NXCD, r = id / NXCD;
+  const int u = (r / per) * NXCD + x, w = r % per;
+  const int member = w / nbt;
   TileSlot s;
-  s.tile = (r / nbt) * NXCD + x;
-  s.bt = r % nbt;
-  s.valid = s.tile < ntl;
+  s.tile = member ? ntl - 1 - u : u;
+  s.bt = w - member * nbt;
+  s.valid = u < nunits && !(member && s.tile == u);
   return s;
 }
-__host__ __device__ inline unsigned contraction_grid(int ntl, int nbt) {
-  return (unsigned)(((ntl + NXCD - 1) / NXCD) * NXCD * nbt);
+__host__ __device__ inline unsigned contraction_grid(int ntl, int nbt, int paired = 0) {
+  const int nunits = paired ? (ntl + 1) / 2 : ntl;
+  return (unsigned)(((nunits + NXCD - 1) / NXCD) * NXCD * (paired ? 2 * nbt : nbt));
 }
 
 // bf16 split table entry (hi, lo) for the split-precision contraction

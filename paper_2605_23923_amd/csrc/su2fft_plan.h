@@ -42,6 +42,7 @@ struct su2_plan_s {
   // tables generated inside the contraction kernels: per-pair seed constants,
   // recurrence coefficients, node values
   bool otf = false;
+  bool sym = false;             // point-symmetric pair layout, upper tiles share the lower tiles' table blocks
   bool real = false;            // real-signal plan (pairs with 2m >= 0 carry the spectra)
   bool so3 = false;             // SO(3) plan: integer l, gamma over [-pi, pi)
   int* d_bins_real = nullptr;
@@ -143,6 +144,10 @@ OtfParams<T> otf_params(const su2_plan_s* pl, int scale_mode) {
   OtfParams<T> r;
   memset(&r, 0, sizeof(r));
   r.b = beta_params<T>(pl, nullptr, scale_mode);
+  // kernels on these parameters generate each pair's own values (its own
+  // seed): no stored column, no mirror sign, no shared blocks to pair up
+  r.b.table_signs = 0;
+  r.b.paired = 0;
   r.seedc = pl->d_seedc;
   r.rcoef = pl->d_rcoef;
   r.xk = pl->d_nodes;
@@ -166,6 +171,8 @@ BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
   b.real = pl->real ? 1 : 0;
   b.tile0 = pl->real ? pl->rbeg[0] / PT : 0;
   b.so3 = pl->so3 ? 1 : 0;
+  b.table_signs = pl->sym ? 1 : 0;
+  b.paired = (pl->sym && b.tile0 == 0) ? 1 : 0;
   return b;
 }
 

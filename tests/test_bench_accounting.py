@@ -36,20 +36,30 @@ def test_pair_and_coefficient_counts(B):
     assert bench.num_coeffs(B, "c64_so3") == len(so3) == oracle.so3.num_coeffs(B)
 
 
+def _table_columns(B):
+    """Distinct Wigner-d columns up to sign: d^l_{-n,-m} = (-1)^{m-n} d^l_{nm}
+    pairs (m, n) with (-m, -n), so one column per degree of every pair with
+    (2m, 2n) >= (0, 0) in lexicographic order."""
+    return len([1 for tl, tm, tn in _degrees(B) if (tm, tn) >= (0, 0)])
+
+
 def test_algorithmic_bytes_at_the_bench_workload():
     B, batch, N = 64, 32, 128
     samples = N ** 3 * 8                      # 16.78 MB per signal (complex float)
     spectra = len(_pairs(B)) * N * 8          # 8.26 MB per signal
     coeffs = len(_degrees(B)) * 8             # 0.72 MB per signal
-    table = len(_degrees(B)) * N * 4          # FP32 table, read once per launch
+    table = _table_columns(B) * N * 4         # symmetry-reduced FP32 table, read once per launch
+    assert _table_columns(B) == (len(_degrees(B)) + 32) // 2
     assert bench.algorithmic_bytes("ring_forward", B, batch, "c64") == batch * (samples + spectra) == 801144832
     assert bench.algorithmic_bytes("ring_inverse", B, batch, "c64") == batch * (samples + spectra)
     assert bench.algorithmic_bytes("beta_forward", B, batch, "c64") == batch * (spectra + coeffs) + table
     assert bench.algorithmic_bytes("beta_inverse", B, batch, "c128") == \
-        batch * 2 * (spectra + coeffs) + len(_degrees(B)) * N * 8
-    # real signals: real samples, half of the pairs (2m >= 0 without mirrors), half of the table
+        batch * 2 * (spectra + coeffs) + _table_columns(B) * N * 8
+    # real signals: real samples, half of the pairs (2m >= 0 without mirrors), the reduced table
     half = len([1 for tm, tn in _pairs(B) if tm > 0 or (tm == 0 and tn >= 0)])
     assert bench.algorithmic_bytes("ring_forward", B, batch, "c64_real") == batch * (samples // 2 + half * N * 8)
+    assert bench.algorithmic_bytes("beta_forward", B, batch, "c64_real") == \
+        batch * (half * N * 8 + coeffs) + table
     # SO(3): integer (m, n), |m|, |n| <= 31
     so3_pairs = len([1 for tm, tn in _pairs(B) if tm % 2 == 0])
     assert bench.algorithmic_bytes("ring_inverse", B, batch, "c64_so3") == batch * (samples + so3_pairs * N * 8)

@@ -134,11 +134,15 @@ def test_round_trip_bandlimited(B):
 @pytest.mark.parametrize("B", [8, 24, 64, 128])
 def test_dtable_matches_oracle(B):
     """The FP64 Wigner-d table generated on the GPU by the l-recurrence against the
-    oracle's Jacobi-form values, on sampled pairs (including the extreme ones)."""
+    oracle's Jacobi-form values, on sampled pairs (including the extreme ones and
+    mirror couples (m, n), (-m, -n) that share one stored column)."""
     plan = su2.Plan(B, 1, "c128")
     _, beta, _, _ = oracle.grid(B)
     rng = np.random.default_rng(B)
-    pairs = [(B - 1, B - 1), (-(B - 1), B - 1), (0 if B % 2 else 1, 0 if B % 2 else 1)]
+    # the extreme pairs, and pairs whose mirror (-m, -n) shares their stored
+    # column (the upper half of the symmetric layout reads it with (-1)^{m-n})
+    pairs = [(B - 1, B - 1), (-(B - 1), B - 1), (0 if B % 2 else 1, 0 if B % 2 else 1),
+             (-(B - 1), -(B - 1)), (B - 1, -(B - 1)), (0, 2), (0, -2), (1, -3), (-1, 3)]
     for _ in range(12):
         tm = int(rng.integers(-(B - 1), B))
         tn = int(rng.integers(-(B - 1), B))
