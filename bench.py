@@ -258,6 +258,7 @@ def run_whole(make_plan, x, c, steps: int, warmup: int, batch: int):
     info = {"ms_per_step": round(dt * 1e3, 4), "transforms_per_s": round(3 * batch / dt, 2)}
     if hasattr(plan, "tuning"):
         info["workgroups_per_cu"] = plan.tuning()
+        info["tile_shapes_B_fwd_inv_kc"] = [list(s) for s in plan.tile_shapes()]
     plan.close()
     return info
 
@@ -349,6 +350,16 @@ def secondary_configs(steps: int, warmup: int):
     c = torch.from_numpy(((rng.standard_normal(nc) + 1j * rng.standard_normal(nc)) / np.sqrt(2)).astype(np.complex64)).to("cuda")
     out["mixed_320_signals_c64"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup, len(Bs))
     out["mixed_320_signals_c64"]["signals"] = "256 x B=32 + 64 x B in {16,24,32,48,64} (seed 33)"
+    # the same step with the autotuner off (default tile shapes, 2 workgroups per CU)
+    prev = os.environ.get("SU2_AUTOTUNE")
+    os.environ["SU2_AUTOTUNE"] = "0"
+    try:
+        out["mixed_320_signals_c64_untuned"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup, len(Bs))
+    finally:
+        if prev is None:
+            del os.environ["SU2_AUTOTUNE"]
+        else:
+            os.environ["SU2_AUTOTUNE"] = prev
     del x, c
     torch.cuda.empty_cache()
     out["b64_batch32_beta_forward_shifted_c64"] = shifted_forms(steps)

@@ -241,6 +241,24 @@ su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, dou
  * single-B plan. */
 su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu);
 
+/* Mixed plans: the contraction tile shapes the autotuner chose at plan
+ * creation, four int32 per bandlimit group in increasing B: B, signals per
+ * forward contraction tile, signals per inverse/adjoint contraction tile, beta
+ * nodes per forward chunk.  The search times, per group, 16-signal tiles
+ * against the widest (32 in FP32 forward and inverse, 32 in the split-BF16
+ * inverse; FP64 tiles are 16 wide, the split-BF16 forward 16) and, per plan,
+ * 4-node against 8-node forward chunks (FP32 and FP64; split BF16 works in
+ * 32-node chunks).  No shape changes any result: every signal's sums over beta
+ * run in node order whatever the tile.  out receives at most capacity int32
+ * (whole groups only; out may be NULL to query the count), *count the number of
+ * groups.  Environment, read at plan creation: SU2_AUTOTUNE=0 keeps the default
+ * shapes (16-signal tiles for FP32 groups of at most 16 signals, the widest
+ * otherwise; 4-node FP32 and 8-node FP64 chunks); SU2_TILE_SHAPES="kc,fwd,inv"
+ * pins chunk and tile widths wherever the mode has them.  Results are cached
+ * with the grid sizes of su2_plan_tuning.  SU2_ERR_INVALID_VALUE for a single-B
+ * plan or a NULL count. */
+su2_status_t su2_plan_tile_shapes(su2_plan_t plan, int32_t* out, int32_t capacity, int32_t* count);
+
 /* Plan queries: bandlimit (-1 for mixed plans), batch, dtype, device bytes held. */
 su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype,
                            int64_t* device_bytes);

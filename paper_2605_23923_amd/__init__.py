@@ -95,6 +95,8 @@ def _load():
     lib.su2_plan_dtable.restype = i32
     lib.su2_plan_tuning.argtypes = [vp, ctypes.POINTER(i32)]
     lib.su2_plan_tuning.restype = i32
+    lib.su2_plan_tile_shapes.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+    lib.su2_plan_tile_shapes.restype = i32
     lib.su2_status_string.argtypes = [i32]
     lib.su2_status_string.restype = ctypes.c_char_p
     lib.su2_last_hip_error.argtypes = []
@@ -398,6 +400,17 @@ class MixedPlan(_PlanBase):
         arr = (ctypes.c_int32 * 4)()
         _check(_load().su2_plan_tuning(self._handle, arr), "su2_plan_tuning")
         return list(arr)
+
+    def tile_shapes(self):
+        """Contraction tile shapes the autotuner chose, per bandlimit group in
+        increasing B: (B, forward signals per tile, inverse signals per tile,
+        forward nodes per chunk)."""
+        lib = _load()
+        n = ctypes.c_int32()
+        _check(lib.su2_plan_tile_shapes(self._handle, None, 0, ctypes.byref(n)), "su2_plan_tile_shapes")
+        arr = (ctypes.c_int32 * (4 * n.value))()
+        _check(lib.su2_plan_tile_shapes(self._handle, arr, 4 * n.value, ctypes.byref(n)), "su2_plan_tile_shapes")
+        return [tuple(arr[4 * g:4 * g + 4]) for g in range(n.value)]
 
 
 class SU2Transform(torch.autograd.Function):

@@ -794,6 +794,12 @@ su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu) {
   return SU2_OK;
 }
 
+su2_status_t su2_plan_tile_shapes(su2_plan_t plan, int32_t* out, int32_t capacity, int32_t* count) {
+  if (!plan || !count || !plan->mixed || capacity < 0) return SU2_ERR_INVALID_VALUE;
+  *count = mixed_shapes(plan, out, capacity);
+  return SU2_OK;
+}
+
 su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t* dtype, int64_t* device_bytes) {
   if (!plan) return SU2_ERR_INVALID_VALUE;
   if (B) *B = plan->B;

@@ -47,7 +47,7 @@ template <class T>
 struct GroupDev {
   int fast;               // register-resident ring kernels
   int rtmax, lq, lq2;     // contraction shapes of the group's bandlimit
-  int narrow;             // FP32 group of at most 16 signals: 16-signal contraction tiles
+  int narrow_f, narrow_i; // 16-signal contraction tiles (forward, inverse) instead of the widest
   RingParams<T> rp[3];    // generic ring kernels: forward, inverse, adjoint
   FastRingParams<T> fp[3];
   BetaParams<T> bp[3];    // contraction: forward, inverse, adjoint
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_generic_worklist_kernel(cons
   }
 }
 
-template <class T, int RTMAX_MAX>
+template <class T, int RTMAX_MAX, int KC>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             cpx<T>* __restrict__ coeffs) {
@@ -123,8 +123,7 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    constexpr int KC = fwd_kc_default<T>();
-    if (g.narrow) {
+    if (g.narrow_f) {
       if constexpr (BetaCfg<T>::BT > 16) {
         if (g.rtmax == 1) beta_forward_body<T, 1, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
         if constexpr (RTMAX_MAX >= 2)
@@ -133,11 +132,11 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
           if (g.rtmax == 4) beta_forward_body<T, 4, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
       }
     } else {
-      if (g.rtmax == 1) beta_forward_body<T, 1>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      if (g.rtmax == 1) beta_forward_body<T, 1, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
       if constexpr (RTMAX_MAX >= 2)
-        if (g.rtmax == 2) beta_forward_body<T, 2>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+        if (g.rtmax == 2) beta_forward_body<T, 2, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
       if constexpr (RTMAX_MAX >= 4)
-        if (g.rtmax == 4) beta_forward_body<T, 4>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+        if (g.rtmax == 4) beta_forward_body<T, 4, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -154,7 +153,7 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
     const BetaParams<T>& p = g.bp[dir];
-    if (g.narrow) {
+    if (g.narrow_i) {
       if constexpr (BetaCfg<T>::BT > 16) {
         if (g.lq == 2) beta_inverse_body<T, 2, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
         if constexpr (LQ_MAX >= 4)
@@ -205,7 +204,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.narrow) {
+    if (g.narrow_i) {
       if (g.lq2 == 1) beta_inverse_bf16x3_body<1, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
       if constexpr (LQ2_MAX >= 2)
         if (g.lq2 == 2) beta_inverse_bf16x3_body<2, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
@@ -244,6 +243,11 @@ struct MixedState {
   int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
   int num_cu = 0;
   int knob[4] = {2, 2, 2, 2};       // workgroups per CU: ring forward, contraction forward, contraction inverse, ring inverse
+  // tile shapes (autotuned): nodes per forward chunk, and per group 16-signal
+  // contraction tiles (1) or the widest (0) in the forward and the inverse
+  int kc = 4;
+  std::vector<int> narrow_f, narrow_i;
+  int max_betaf = 0, max_betai = 0;  // work-list capacities (every group in 16-signal tiles)
   hipStream_t cap = nullptr;          // capture stream
   hipStream_t side = nullptr;         // second branch: generic ring tasks run beside the fast ones
   hipEvent_t fork = nullptr, join = nullptr;
@@ -272,10 +276,21 @@ void* ringg_kernel_ptr(bool fwd) {
 }
 
 template <class T>
-void* betaf_kernel_ptr(int rtmax) {
-  if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1>;
-  if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2>;
-  return (void*)beta_forward_worklist_kernel<T, 4>;
+void* betaf_kernel_ptr(int rtmax, int kc) {
+  if (kc == 8) {
+    if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1, 8>;
+    if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2, 8>;
+    return (void*)beta_forward_worklist_kernel<T, 4, 8>;
+  }
+  if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1, 4>;
+  if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2, 4>;
+  return (void*)beta_forward_worklist_kernel<T, 4, 4>;
+}
+template <class T>
+size_t betaf_smem(int rtmax, int kc) {
+  if (kc == 8)
+    return rtmax <= 1 ? FwdGeom<T, 1, 8>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 8>::SMEM : FwdGeom<T, 4, 8>::SMEM);
+  return rtmax <= 1 ? FwdGeom<T, 1, 4>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 4>::SMEM : FwdGeom<T, 4, 4>::SMEM);
 }
 template <class T>
 void* betai_kernel_ptr(int lq) {
@@ -344,7 +359,7 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
         void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
         return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(XB_THREADS), args, ms->smem_betaf, s);
       } else {
-        void* k = betaf_kernel_ptr<T>(ms->rtmax);
+        void* k = betaf_kernel_ptr<T>(ms->rtmax, ms->kc);
         void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
         return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(FWD_THREADS), args, ms->smem_betaf, s);
       }
@@ -391,7 +406,7 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
   if (ms->smem_ringf > (size_t)max_lds || ms->smem_ringg > (size_t)max_lds || ms->smem_betaf > (size_t)max_lds ||
       ms->smem_betai > (size_t)max_lds)
     return hipErrorInvalidValue;
-  void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax);
+  void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax, ms->kc);
   void* ki = bf ? betai_bf16_kernel_ptr(ms->lq2) : betai_kernel_ptr<T>(ms->lq);
   for (int fwd = 0; fwd < 2; fwd++) {
     if ((e = hipFuncSetAttribute(ringf_kernel_ptr<T>(fwd), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) !=
@@ -405,14 +420,32 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
   return hipFuncSetAttribute(ki, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
-// build the per-group device descriptors, work lists and LDS sizes
+// build the per-group device descriptors, work lists and LDS sizes from the
+// plan's tile shapes (ms->kc, ms->narrow_f, ms->narrow_i); only_group >= 0
+// keeps only that group's contraction tasks (the autotuner times one group's
+// shapes at a time).  The device lists are allocated once, at the capacity of
+// every group in 16-signal tiles, and refilled on later calls.
 template <class T>
-su2_status_t build_worklists(su2_plan_s* pl) {
+su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   MixedState* ms = pl->mixed;
   const bool bf = pl->dtype == SU2_C64_BF16X3;
   const int ng = (int)ms->groups.size();
+  const bool first = ms->d_groups == nullptr;
+  if (first) {
+    // default shapes: FP32 groups of at most 16 signals take 16-signal tiles
+    // (as single-B plans do); FP32 forward chunks of 4 nodes, FP64 of 8
+    ms->narrow_f.assign(ng, 0);
+    ms->narrow_i.assign(ng, 0);
+    for (int gi = 0; gi < ng; gi++)
+      ms->narrow_f[gi] = ms->narrow_i[gi] = sizeof(T) == 4 && ms->groups[gi]->batch <= 16 ? 1 : 0;
+    ms->kc = fwd_kc_default<T>();
+  }
   std::vector<GroupDev<T>> hg(ng);
   std::vector<std::pair<double, WorkItem>> ringf, ringg, betaf, betai;
+  int cap_f = 0, cap_i = 0;
+  ms->rtmax = 1;
+  ms->lq = 2;
+  ms->lq2 = 1;
   for (int gi = 0; gi < ng; gi++) {
     su2_plan_s* gp = ms->groups[gi];
     GroupDev<T>& d = hg[gi];
@@ -421,8 +454,8 @@ su2_status_t build_worklists(su2_plan_s* pl) {
     d.rtmax = beta_rtmax(gp->B);
     d.lq = beta_lq(gp->B);
     d.lq2 = beta_bf16_lq(gp->B);
-    // as single-B plans: FP32 groups of at most 16 signals take 16-signal tiles
-    d.narrow = sizeof(T) == 4 && gp->batch <= 16 ? 1 : 0;
+    d.narrow_f = ms->narrow_f[gi];
+    d.narrow_i = ms->narrow_i[gi];
     const T* tab = std::is_same<T, double>::value ? (const T*)gp->d_tab64 : (const T*)gp->d_tab32;
     for (int dir = 0; dir < 3; dir++) {
       d.rp[dir] = ring_params<T>(gp, dir == 2);
@@ -449,8 +482,11 @@ su2_status_t build_worklists(su2_plan_s* pl) {
       for (int i = 0; i < gp->batch; i++)
         for (int k = 0; k < N; k++) ringg.push_back({ring_cost, WorkItem{gi, i, k}});
     }
-    const int btf = bf ? XBF_BT : (d.narrow ? 16 : BetaCfg<T>::BT);
-    const int bti = d.narrow ? 16 : (bf ? XB_BT : BetaCfg<T>::BT);
+    const int btf = bf ? XBF_BT : (d.narrow_f ? 16 : BetaCfg<T>::BT);
+    const int bti = d.narrow_i ? 16 : (bf ? XB_BT : BetaCfg<T>::BT);
+    cap_f += gp->ntiles * ((gp->batch + 15) / 16);
+    cap_i += gp->ntiles * ((gp->batch + 15) / 16);
+    if (only_group >= 0 && gi != only_group) continue;
     for (int t = 0; t < gp->ntiles; t++) {
       const double tile_cost = (double)N * std::max(1, gp->h_pairs[t * PT].lsum);
       for (int b = 0; b * btf < gp->batch; b++)
@@ -463,40 +499,73 @@ su2_status_t build_worklists(su2_plan_s* pl) {
     ms->smem_betaf = XBF_SMEM;
     ms->smem_betai = XBI_SMEM;
   } else {
-    ms->smem_betaf = ms->rtmax <= 1 ? FwdGeom<T, 1>::SMEM : (ms->rtmax <= 2 ? FwdGeom<T, 2>::SMEM : FwdGeom<T, 4>::SMEM);
+    ms->smem_betaf = betaf_smem<T>(ms->rtmax, ms->kc);
     ms->smem_betai = inverse_smem<T>();
   }
   auto by_cost = [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
     return x.first > y.first;
   };
   hipError_t e;
-  if ((e = mixed_alloc(ms, &ms->d_groups, sizeof(GroupDev<T>) * ng)) != hipSuccess) return hip_fail(e);
+  if (first) {
+    ms->max_betaf = cap_f;
+    ms->max_betai = cap_i;
+    if ((e = mixed_alloc(ms, &ms->d_groups, sizeof(GroupDev<T>) * ng)) != hipSuccess) return hip_fail(e);
+    if ((e = mixed_alloc(ms, (void**)&ms->d_ringf, sizeof(WorkItem) * ringf.size())) != hipSuccess) return hip_fail(e);
+    if ((e = mixed_alloc(ms, (void**)&ms->d_ringg, sizeof(WorkItem) * ringg.size())) != hipSuccess) return hip_fail(e);
+    if ((e = mixed_alloc(ms, (void**)&ms->d_betaf, sizeof(WorkItem) * cap_f)) != hipSuccess) return hip_fail(e);
+    if ((e = mixed_alloc(ms, (void**)&ms->d_betai, sizeof(WorkItem) * cap_i)) != hipSuccess) return hip_fail(e);
+  }
+  if ((int)betaf.size() > ms->max_betaf || (int)betai.size() > ms->max_betai) return SU2_ERR_INVALID_VALUE;
   if ((e = hipMemcpy(ms->d_groups, hg.data(), sizeof(GroupDev<T>) * ng, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
   // each list: sorted by decreasing cost, uploaded
-  auto upload = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem** dst, int* n) -> hipError_t {
+  auto upload = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem* dst, int* n) -> hipError_t {
     std::stable_sort(lst.begin(), lst.end(), by_cost);
     std::vector<WorkItem> v;
     for (auto& x : lst) v.push_back(x.second);
     *n = (int)v.size();
-    hipError_t err = mixed_alloc(ms, (void**)dst, sizeof(WorkItem) * v.size());
-    if (err == hipSuccess && !v.empty())
-      err = hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice);
-    return err;
+    return v.empty() ? hipSuccess : hipMemcpy(dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice);
   };
-  if ((e = upload(ringf, &ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
-  if ((e = upload(ringg, &ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
-  if ((e = upload(betaf, &ms->d_betaf, &ms->n_betaf)) != hipSuccess) return hip_fail(e);
-  if ((e = upload(betai, &ms->d_betai, &ms->n_betai)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(ringf, ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(ringg, ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(betaf, ms->d_betaf, &ms->n_betaf)) != hipSuccess) return hip_fail(e);
+  if ((e = upload(betai, ms->d_betai, &ms->n_betai)) != hipSuccess) return hip_fail(e);
   if ((e = set_worklist_smem<T>(pl)) != hipSuccess) return hip_fail(e);
   return SU2_OK;
 }
 
-// ---- autotuner: persistent grid size (workgroups per CU) of each work-list kernel ----
+su2_status_t rebuild_worklists(su2_plan_s* pl, int only_group = -1) {
+  return pl->dtype == SU2_C128 ? build_worklists<double>(pl, only_group) : build_worklists<float>(pl, only_group);
+}
+
+// ---- autotuner: tile shapes and persistent grid sizes ----
+//
+// At plan creation each mixed plan chooses, by timing its own work lists on
+// scratch buffers (HIP events, best of two after a warm-up):
+//   1. per bandlimit group, the signals per contraction tile: 16 or the
+//      widest (32 in FP32) in the forward (FP32) and in the inverse (FP32 and
+//      split BF16), timing that group's contraction tasks alone;
+//   2. the nodes per forward chunk, 4 or 8 (FP32 and FP64);
+//   3. the persistent grid of each of the four work-list kernels, 1, 2, 3, 4,
+//      6 or 8 workgroups per CU.
+// None of them changes a result (every signal's sums run in the same order).
+// Choices are cached per (device, mode, bandlimit mix) in the process and,
+// with SU2_AUTOTUNE_CACHE naming a text file, across processes.
+// SU2_AUTOTUNE=0 keeps the defaults (16-signal tiles for FP32 groups of at
+// most 16 signals, the widest otherwise; 4-node FP32 and 8-node FP64 chunks;
+// 2 workgroups per CU).  SU2_TILE_SHAPES="kc,fwd,inv" (e.g. "8,16,32") pins
+// the shapes of every group where they apply and skips steps 1 and 2.
 
 std::mutex g_tune_mu;
 std::map<std::string, std::vector<int>> g_tune_cache;
-bool g_tune_file_loaded = false;
+std::string g_tune_file_loaded;   // cache file already read into g_tune_cache
+
+// shapes pinned through SU2_TILE_SHAPES ("kc,fwd,inv"); false if unset or malformed
+bool pinned_shapes(int* kc, int* fwd, int* inv) {
+  const char* env = getenv("SU2_TILE_SHAPES");
+  if (!env) return false;
+  return sscanf(env, "%d,%d,%d", kc, fwd, inv) == 3;
+}
 
 std::string tune_key(const su2_plan_s* pl) {
   hipDeviceProp_t prop;
@@ -506,43 +575,86 @@ std::string tune_key(const su2_plan_s* pl) {
   const MixedState* ms = pl->mixed;
   for (size_t g = 0; g < ms->groups.size(); g++)
     k += ":" + std::to_string(ms->group_B[g]) + "x" + std::to_string(ms->groups[g]->batch);
+  int kc, f, i;
+  if (pinned_shapes(&kc, &f, &i)) k += ":pinned" + std::to_string(kc) + "," + std::to_string(f) + "," + std::to_string(i);
   return k;
 }
 
 void load_tune_file() {
-  if (g_tune_file_loaded) return;
-  g_tune_file_loaded = true;
   const char* path = getenv("SU2_AUTOTUNE_CACHE");
-  if (!path) return;
+  if (!path || g_tune_file_loaded == path) return;
+  g_tune_file_loaded = path;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  char key[4096];
-  int a, b, c, d;
-  while (fscanf(f, "%4095s %d %d %d %d", key, &a, &b, &c, &d) == 5) g_tune_cache[key] = {a, b, c, d};
+  static char line[1 << 16];
+  while (fgets(line, sizeof(line), f)) {
+    char* p = line;
+    while (*p && *p != ' ' && *p != '\n') p++;
+    if (*p != ' ') continue;
+    *p++ = 0;
+    std::vector<int> v;
+    char* end = nullptr;
+    for (long x = strtol(p, &end, 10); end != p; x = strtol(p, &end, 10)) {
+      v.push_back((int)x);
+      p = end;
+    }
+    if (v.size() >= 5) g_tune_cache[line] = v;
+  }
   fclose(f);
 }
 
-void store_tune_file(const std::string& key, const int* k) {
+void store_tune_file(const std::string& key, const std::vector<int>& v) {
   const char* path = getenv("SU2_AUTOTUNE_CACHE");
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %d\n", key.c_str(), k[0], k[1], k[2], k[3]);
+  fprintf(f, "%s", key.c_str());
+  for (int x : v) fprintf(f, " %d", x);
+  fprintf(f, "\n");
   fclose(f);
 }
 
 su2_status_t autotune(su2_plan_s* pl) {
   MixedState* ms = pl->mixed;
+  const bool bf = pl->dtype == SU2_C64_BF16X3, dbl = pl->dtype == SU2_C128;
+  const int ng = (int)ms->groups.size();
+  su2_status_t st;
+  int pk = 0, pf = 0, pi = 0;
+  const bool pinned = pinned_shapes(&pk, &pf, &pi);
+  if (pinned) {
+    if (!bf && (pk == 4 || pk == 8)) ms->kc = pk;
+    for (int g = 0; g < ng; g++) {
+      if (!bf && !dbl && (pf == 16 || pf == 32)) ms->narrow_f[g] = pf == 16;
+      if (!dbl && (pi == 16 || pi == 32)) ms->narrow_i[g] = pi == 16;
+    }
+    if ((st = rebuild_worklists(pl)) != SU2_OK) return st;
+  }
   const char* env = getenv("SU2_AUTOTUNE");
-  if (env && env[0] == '0') return SU2_OK;  // keep the defaults
+  if (env && env[0] == '0') return SU2_OK;  // keep the defaults (or the pinned shapes)
   const std::string key = tune_key(pl);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     load_tune_file();
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      for (int i = 0; i < 4; i++) ms->knob[i] = it->second[i];
-      return SU2_OK;
+    // an entry is used only if every value is one the search could have chosen
+    auto valid = [&](const std::vector<int>& v) {
+      if (v.size() != (size_t)(5 + 2 * ng)) return false;
+      for (int i = 0; i < 4; i++)
+        if (v[i] < 1 || v[i] > 8) return false;
+      if (v[4] != 4 && v[4] != 8) return false;
+      for (int g = 0; g < 2 * ng; g++)
+        if (v[5 + g] != 0 && (v[5 + g] != 1 || dbl)) return false;
+      return true;
+    };
+    if (it != g_tune_cache.end() && valid(it->second)) {
+      const std::vector<int>& v = it->second;
+      for (int i = 0; i < 4; i++) ms->knob[i] = v[i];
+      ms->kc = v[4];
+      for (int g = 0; g < ng; g++) {
+        ms->narrow_f[g] = v[5 + g];
+        ms->narrow_i[g] = v[5 + ng + g];
+      }
+      return rebuild_worklists(pl);
     }
   }
   const size_t cb = pl->dtype == SU2_C128 ? 16 : 8;
@@ -562,30 +674,67 @@ su2_status_t autotune(su2_plan_s* pl) {
   const void* ins[4] = {din, nullptr, dout, nullptr};
   void* outs[4] = {nullptr, dout, nullptr, din};
   const int dirs[4] = {0, 0, 1, 1};
-  su2_status_t st = SU2_OK;
+  st = SU2_OK;
+  // fastest of two timed launches after a warm-up; 1e30 on an error (st set)
+  auto time_launch = [&](int which, int kn) -> float {
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3 && st == SU2_OK; rep++) {
+      (void)hipEventRecord(e0, ms->cap);
+      if ((e = enqueue_any(pl, which, dirs[which], ins[which], outs[which], ms->cap, kn)) != hipSuccess) {
+        st = hip_fail(e);
+        break;
+      }
+      (void)hipEventRecord(e1, ms->cap);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        st = hip_fail(e);
+        break;
+      }
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) tmin = std::min(tmin, t);
+    }
+    return tmin;
+  };
+  if (!pinned) {
+    // 1. per group: signals per contraction tile (forward, then inverse)
+    for (int g = 0; g < ng && st == SU2_OK; g++) {
+      for (int which = 1; which <= 2 && st == SU2_OK; which++) {
+        if (dbl || (bf && which == 1)) continue;  // one tile width only
+        std::vector<int>& nar = which == 1 ? ms->narrow_f : ms->narrow_i;
+        float best = 1e30f;
+        int best_c = nar[g];
+        for (int cand = 1; cand >= 0 && st == SU2_OK; cand--) {
+          nar[g] = cand;
+          if ((st = rebuild_worklists(pl, g)) != SU2_OK) break;
+          const float t = time_launch(which, 2);
+          if (t < best) { best = t; best_c = cand; }
+        }
+        nar[g] = best_c;
+      }
+    }
+    // 2. nodes per forward chunk
+    if (!bf && st == SU2_OK) {
+      float best = 1e30f;
+      int best_c = ms->kc;
+      for (int cand : {4, 8}) {
+        ms->kc = cand;
+        if ((st = rebuild_worklists(pl)) != SU2_OK) break;
+        const float t = time_launch(1, 2);
+        if (t < best) { best = t; best_c = cand; }
+      }
+      ms->kc = best_c;
+    }
+  }
+  if (st == SU2_OK) st = rebuild_worklists(pl);
+  // 3. persistent grid size of each work-list kernel
   for (int which = 0; which < 4 && st == SU2_OK; which++) {
     float best = 1e30f;
     int best_k = ms->knob[which];
     static const int cand[] = {1, 2, 3, 4, 6, 8};
     for (int kn : cand) {
-      float tmin = 1e30f;
-      for (int rep = 0; rep < 3; rep++) {
-        (void)hipEventRecord(e0, ms->cap);
-        if ((e = enqueue_any(pl, which, dirs[which], ins[which], outs[which], ms->cap, kn)) != hipSuccess) {
-          st = hip_fail(e);
-          break;
-        }
-        (void)hipEventRecord(e1, ms->cap);
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-          st = hip_fail(e);
-          break;
-        }
-        float ms_t = 0.f;
-        (void)hipEventElapsedTime(&ms_t, e0, e1);
-        if (rep > 0) tmin = std::min(tmin, ms_t);
-      }
+      const float t = time_launch(which, kn);
       if (st != SU2_OK) break;
-      if (tmin < best) { best = tmin; best_k = kn; }
+      if (t < best) { best = t; best_k = kn; }
     }
     ms->knob[which] = best_k;
   }
@@ -594,9 +743,12 @@ su2_status_t autotune(su2_plan_s* pl) {
   (void)hipFree(din);
   (void)hipFree(dout);
   if (st != SU2_OK) return st;
+  std::vector<int> v = {ms->knob[0], ms->knob[1], ms->knob[2], ms->knob[3], ms->kc};
+  v.insert(v.end(), ms->narrow_f.begin(), ms->narrow_f.end());
+  v.insert(v.end(), ms->narrow_i.begin(), ms->narrow_i.end());
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tune_cache[key] = {ms->knob[0], ms->knob[1], ms->knob[2], ms->knob[3]};
-  store_tune_file(key, ms->knob);
+  g_tune_cache[key] = v;
+  store_tune_file(key, v);
   return SU2_OK;
 }
 
@@ -672,7 +824,7 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
     if (st != SU2_OK) return st;
     pl->bytes += gp->bytes;
   }
-  su2_status_t st = dtype == SU2_C128 ? build_worklists<double>(pl) : build_worklists<float>(pl);
+  su2_status_t st = rebuild_worklists(pl);
   if (st != SU2_OK) return st;
   if ((e = hipStreamCreateWithFlags(&ms->cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
   if ((e = hipStreamCreateWithFlags(&ms->side, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
@@ -718,6 +870,20 @@ su2_status_t run_mixed(su2_plan_s* pl, int dir, const void* in, void* out, hipSt
 
 void mixed_tuning(const su2_plan_s* pl, int32_t* knobs) {
   for (int i = 0; i < 4; i++) knobs[i] = pl->mixed ? pl->mixed->knob[i] : 0;
+}
+
+int mixed_shapes(const su2_plan_s* pl, int32_t* out, int32_t capacity) {
+  const MixedState* ms = pl->mixed;
+  const int ng = (int)ms->groups.size();
+  const bool bf = pl->dtype == SU2_C64_BF16X3;
+  const int wide = pl->dtype == SU2_C128 ? BetaCfg<double>::BT : BetaCfg<float>::BT;
+  for (int g = 0; g < ng && out && 4 * g + 3 < capacity; g++) {
+    out[4 * g] = ms->group_B[g];
+    out[4 * g + 1] = bf ? XBF_BT : (ms->narrow_f[g] ? 16 : wide);
+    out[4 * g + 2] = ms->narrow_i[g] ? 16 : (bf ? XB_BT : wide);
+    out[4 * g + 3] = bf ? XB_KC : ms->kc;
+  }
+  return ng;
 }
 
 }  // namespace su2

@@ -90,6 +90,7 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
 void release_mixed(su2_plan_s* pl);
 su2_status_t run_mixed(su2_plan_s* pl, int dir, const void* in, void* out, hipStream_t stream);
 void mixed_tuning(const su2_plan_s* pl, int32_t* knobs);
+int mixed_shapes(const su2_plan_s* pl, int32_t* out, int32_t capacity);  // groups; fills 4 int32 per group
 
 template <class T>
 RingParams<T> ring_params(const su2_plan_s* pl, int adjoint) {

@@ -6,6 +6,8 @@ so its results must be bit-identical to a batch-1 single-B plan of that
 signal; the oracle then pins one signal per distinct bandlimit.
 """
 import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -135,6 +137,104 @@ def test_autotuner_choice_does_not_change_results():
     assert plain.tuning() == [2, 2, 2, 2]
     assert np.array_equal(_host(tuned.forward(x)), _host(plain.forward(x)))
     assert np.array_equal(_host(tuned.adjoint(c)), _host(plain.adjoint(c)))
+
+
+class _env:
+    """Set environment variables for the plan creations inside the block."""
+
+    def __init__(self, **kv):
+        self.kv = kv
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kv}
+        os.environ.update(self.kv)
+
+    def __exit__(self, *exc):
+        for k, v in self.old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+# groups of at most 16 signals and larger ones, every B class of the contraction
+SHAPE_BS = [8] * 3 + [24] * 20 + [32] * 5 + [48] * 17 + [64] * 2
+
+
+def test_tile_shapes_defaults_reported():
+    with _env(SU2_AUTOTUNE="0"):
+        mp = su2.MixedPlan(SHAPE_BS, "c64")
+        md = su2.MixedPlan(SHAPE_BS, "c128")
+        mb = su2.MixedPlan(SHAPE_BS, "c64_bf16x3")
+    counts = {B: SHAPE_BS.count(B) for B in set(SHAPE_BS)}
+    assert [s[0] for s in mp.tile_shapes()] == sorted(counts)
+    for B, f, i, kc in mp.tile_shapes():
+        w = 16 if counts[B] <= 16 else 32
+        assert (f, i, kc) == (w, w, 4), B
+    assert all(s[1:] == (16, 16, 8) for s in md.tile_shapes())
+    for B, f, i, kc in mb.tile_shapes():
+        assert (f, i, kc) == (16, 16 if counts[B] <= 16 else 32, 32), B
+
+
+@pytest.mark.parametrize("dtype,shapes", [
+    ("c64", "4,16,16"), ("c64", "8,32,32"), ("c64", "8,16,32"), ("c64", "4,32,16"),
+    ("c128", "4,16,16"), ("c128", "8,16,16"),
+    ("c64_bf16x3", "32,16,16"), ("c64_bf16x3", "32,16,32"),
+])
+def test_pinned_tile_shapes_bitwise_equal_default(dtype, shapes):
+    """Every tile shape gives the default shape's bits in all three directions
+    (sums over beta run in node order whatever the tile), and is reported."""
+    xs, cs = _mixed_inputs(SHAPE_BS, dtype, 7)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    with _env(SU2_AUTOTUNE="0"):
+        ref = su2.MixedPlan(SHAPE_BS, dtype)
+    with _env(SU2_AUTOTUNE="0", SU2_TILE_SHAPES=shapes):
+        mp = su2.MixedPlan(SHAPE_BS, dtype)
+    kc, fw, iw = (int(v) for v in shapes.split(","))
+    for B, f, i, k in mp.tile_shapes():
+        assert k == kc and i == iw, (B, k, i)
+        assert f == (16 if dtype != "c64" else fw), (B, f)
+    for fn in ("forward", "inverse", "adjoint"):
+        a = ref.forward(x) if fn == "forward" else getattr(ref, fn)(c)
+        b = mp.forward(x) if fn == "forward" else getattr(mp, fn)(c)
+        assert np.array_equal(_host(a), _host(b)), fn
+
+
+def test_autotuned_tile_shapes_valid_and_cached(tmp_path):
+    """The search picks a valid shape per group and changes no result; a fresh
+    process reads the choice back from the disk cache instead of searching."""
+    cache = tmp_path / "tune.txt"
+    xs, cs = _mixed_inputs(SHAPE_BS, "c64", 8)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    with _env(SU2_AUTOTUNE_CACHE=str(cache), SU2_TILE_SHAPES="4,16,32"):
+        pinned = su2.MixedPlan(SHAPE_BS, "c64")       # pinned shapes: a cache key of their own
+    assert pinned.tile_shapes() == [(B, 16, 32, 4) for B in sorted(set(SHAPE_BS))]
+    with _env(SU2_AUTOTUNE_CACHE=str(cache)):
+        tuned = su2.MixedPlan(SHAPE_BS, "c64")
+    shapes = tuned.tile_shapes()
+    assert all(f in (16, 32) and i in (16, 32) and k in (4, 8) for _, f, i, k in shapes)
+    assert len(set(k for *_, k in shapes)) == 1
+    lines = cache.read_text().splitlines()
+    assert any("pinned4,16,32" in ln for ln in lines)
+    with _env(SU2_AUTOTUNE="0"):
+        plain = su2.MixedPlan(SHAPE_BS, "c64")
+    for fn in ("forward", "adjoint"):
+        a = plain.forward(x) if fn == "forward" else plain.adjoint(c)
+        b = tuned.forward(x) if fn == "forward" else tuned.adjoint(c)
+        assert np.array_equal(_host(a), _host(b)), fn
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2605_23923_amd as su2; "
+            f"mp = su2.MixedPlan({SHAPE_BS!r}, 'c64'); print(mp.tile_shapes(), mp.tuning())")
+    env = dict(os.environ, SU2_AUTOTUNE_CACHE=str(cache), PYTHONPATH=root)
+    env.pop("SU2_TILE_SHAPES", None)
+    env.pop("SU2_AUTOTUNE", None)
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip() == f"{shapes} {tuned.tuning()}"
+    assert cache.read_text().splitlines() == lines       # nothing searched, nothing appended
 
 
 def test_mixed_batch_configuration_320_signals():
