@@ -95,17 +95,21 @@ enum {
    * only (SU2_ERR_UNSUPPORTED for SU2_C64_BF16X3). */
   SU2_PLAN_TABLES_ON_THE_FLY = 1u,
   /* Real signals.  The samples are real (double for SU2_C128, float for
-   * SU2_C64; N^3 values per signal, same order), the coefficients complex as
-   * usual.  A real f has fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn})
-   * (Definition 3.4 with conj(t^l_{nm}) = (-1)^{m-n} t^l_{-n,-m}), so both
-   * stages run only for the pairs with 2m > 0, or 2m = 0 and 2n >= 0:
-   * su2_forward writes every coefficient (the others by the symmetry);
-   * su2_inverse and su2_adjoint return the real part of the complex result,
-   * i.e. they read the Hermitian part (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2
-   * of the coefficients (the adjoint is then the adjoint of the real-input
-   * forward map).  SU2_C128 and SU2_C64 with B in {8, 16, 32, 64}, without
-   * SU2_PLAN_TABLES_ON_THE_FLY; SU2_ERR_UNSUPPORTED otherwise.
-   * su2_beta_forward_shifted does not accept real-signal plans. */
+   * SU2_C64 and SU2_C64_BF16X3; N^3 values per signal, same order), the
+   * coefficients complex as usual.  A real f has
+   * fhat(l)_{-m,-n} = (-1)^{m-n} conj(fhat(l)_{mn}) (Definition 3.4 with
+   * conj(t^l_{nm}) = (-1)^{m-n} t^l_{-n,-m}).  su2_forward writes every
+   * coefficient; su2_inverse and su2_adjoint return the real part of the
+   * complex result, i.e. of the transform of the Hermitian part
+   * (c_{mn} + (-1)^{m-n} conj(c_{-m,-n})) / 2 of the coefficients (the adjoint
+   * is then the adjoint of the real-input forward map).  At B in
+   * {8, 16, 32, 64} both stages run only for the pairs with 2m > 0, or 2m = 0
+   * and 2n >= 0 (the forward writes the others by the symmetry, exactly); at
+   * other bandlimits the complex kernels run with real samples in and the real
+   * part out (the forward then computes both halves, Hermitian to rounding).
+   * Every mode and bandlimit; SU2_ERR_UNSUPPORTED with
+   * SU2_PLAN_TABLES_ON_THE_FLY or SU2_PLAN_SO3.  su2_beta_forward_shifted does
+   * not accept real-signal plans. */
   SU2_PLAN_REAL_SIGNALS = 2u,
   /* SO(3) transform: the group the paper's grid (Definition 4.1, phi and psi
    * both over [-pi, pi]) covers, on which only integer l occur.  Integer
@@ -115,8 +119,8 @@ enum {
    * inverse and adjoint with t^l_{nm} for integer l, m, n.  Samples: N^3
    * complex values as for SU(2); coefficients: blocks of integer l only, the
    * block of l starting at l(2l-1)(2l+1)/3, row-major over m then n
-   * (su2_so3_num_coeffs, su2_so3_coeff_index).  SU2_C128 and SU2_C64 with B in
-   * {8, 16, 32, 64}, no other flag; SU2_ERR_UNSUPPORTED otherwise. */
+   * (su2_so3_num_coeffs, su2_so3_coeff_index).  Every mode and bandlimit;
+   * SU2_ERR_UNSUPPORTED with any other flag. */
   SU2_PLAN_SO3 = 4u
 };
 
@@ -137,6 +141,15 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
  * call.  su2_run_stage and su2_plan_dtable do not accept mixed plans. */
 su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype,
                                    su2_plan_t* out);
+
+/* su2_plan_create_mixed with options: flags SU2_PLAN_REAL_SIGNALS (real
+ * samples, N^3 per signal at the same offsets as complex ones, with
+ * su2_plan_create_ex's real-signal semantics per signal) or SU2_PLAN_SO3
+ * (coefficients of each signal: su2_so3_num_coeffs of its B, concatenated);
+ * 0 gives su2_plan_create_mixed's plan.  SU2_PLAN_TABLES_ON_THE_FLY, or both
+ * flags together: SU2_ERR_UNSUPPORTED; unknown bits: SU2_ERR_INVALID_VALUE. */
+su2_status_t su2_plan_create_mixed_ex(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype, uint32_t flags,
+                                      su2_plan_t* out);
 
 /* Release the plan's device memory.  Waits for work the plan enqueued.
  * NULL is accepted and ignored. */

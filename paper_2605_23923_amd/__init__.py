@@ -64,6 +64,8 @@ def _load():
     lib.su2_plan_create_ex.restype = i32
     lib.su2_plan_create_mixed.argtypes = [ctypes.POINTER(i32), i32, i32, ctypes.POINTER(vp)]
     lib.su2_plan_create_mixed.restype = i32
+    lib.su2_plan_create_mixed_ex.argtypes = [ctypes.POINTER(i32), i32, i32, ctypes.c_uint32, ctypes.POINTER(vp)]
+    lib.su2_plan_create_mixed_ex.restype = i32
     lib.su2_plan_destroy.argtypes = [vp]
     lib.su2_plan_destroy.restype = i32
     for name in ("su2_forward", "su2_inverse", "su2_adjoint"):
@@ -323,15 +325,15 @@ class Plan(_PlanBase):
     at plan creation); "on_the_fly" generates the values inside the
     contraction kernels on every call (c128 and c64 only).
 
-    real: real-signal plan (c128 / c64, B in {8, 16, 32, 64}): samples are
-    float64 / float32 tensors; forward returns every coefficient, inverse and
-    adjoint return the real part of the complex result (see
+    real: real-signal plan (any mode and bandlimit, stored tables): samples
+    are float64 / float32 tensors; forward returns every coefficient, inverse
+    and adjoint return the real part of the complex result (see
     SU2_PLAN_REAL_SIGNALS).
 
-    group: "su2" (default), or "so3" for the transform on SO(3) (c128 / c64,
-    B in {8, 16, 32, 64}, stored tables, complex samples): integer l with
-    2l < B on the same N = 2B grid with gamma over [-pi, pi) (see
-    SU2_PLAN_SO3); coefficients indexed by so3_coeff_index."""
+    group: "su2" (default), or "so3" for the transform on SO(3) (any mode and
+    bandlimit, stored tables, complex samples): integer l with 2l < B on the
+    same N = 2B grid with gamma over [-pi, pi) (see SU2_PLAN_SO3);
+    coefficients indexed by so3_coeff_index."""
 
     def __init__(self, B: int, batch: int = 1, dtype="c128", device=None, tables="stored", real=False,
                  group="su2"):
@@ -370,26 +372,36 @@ class Plan(_PlanBase):
 
 class MixedPlan(_PlanBase):
     """Plan for a batch of signals with individual bandlimits, concatenated
-    in order (flat sample and coefficient buffers)."""
+    in order (flat sample and coefficient buffers).  real and group as for
+    Plan (see su2_plan_create_mixed_ex)."""
 
-    def __init__(self, Bs, dtype="c64", device=None):
+    def __init__(self, Bs, dtype="c64", device=None, real=False, group="su2"):
+        if group not in ("su2", "so3"):
+            raise ValueError(f"group must be 'su2' or 'so3', got {group!r}")
         lib = _load()
         self.Bs = [int(b) for b in Bs]
         self.batch = len(self.Bs)
         self.dtype = _DTYPES[dtype]
         self.torch_dtype = _TORCH_DTYPE[self.dtype]
+        self.real = bool(real)
+        self.group = group
+        if self.real:
+            self._sample_dtype = torch.float64 if self.torch_dtype == torch.complex128 else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
+        flags = (PLAN_REAL_SIGNALS if real else 0) | (PLAN_SO3 if group == "so3" else 0)
         arr = (ctypes.c_int32 * self.batch)(*self.Bs)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.su2_plan_create_mixed(arr, self.batch, self.dtype, ctypes.byref(h)), "su2_plan_create_mixed")
+            _check(lib.su2_plan_create_mixed_ex(arr, self.batch, self.dtype, flags, ctypes.byref(h)),
+                   "su2_plan_create_mixed_ex")
         self._handle = h
         self.sample_offsets = [0]
         self.coeff_offsets = [0]
+        ncoef = so3_num_coeffs if group == "so3" else num_coeffs
         for b in self.Bs:
             self.sample_offsets.append(self.sample_offsets[-1] + num_samples(b))
-            self.coeff_offsets.append(self.coeff_offsets[-1] + num_coeffs(b))
+            self.coeff_offsets.append(self.coeff_offsets[-1] + ncoef(b))
         self.total_samples = self.sample_offsets[-1]
         self.total_coeffs = self.coeff_offsets[-1]
         self.sample_shape = (self.total_samples,)

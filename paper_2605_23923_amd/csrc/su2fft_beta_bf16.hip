@@ -97,7 +97,10 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
 
   PairInfo pi[2];
 #pragma unroll
-  for (int i = 0; i < 2; i++) pi[i] = p.pairs[tile * PT + wave + 8 * i];
+  for (int i = 0; i < 2; i++) {
+    pi[i] = p.pairs[tile * PT + wave + 8 * i];
+    if (p.real && mirrored_pair(pi[i].tm, pi[i].tn)) pi[i].L = 0;  // its coefficients come from the mirror
+  }
 
   floatx4 acc[2][RTMAX][CT];
 #pragma unroll
@@ -235,9 +238,9 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT, p.paired);
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles - p.tile0, (p.batch + XBF_BT - 1) / XBF_BT, p.paired);
   if (!sl.valid) return;
-  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, sl.tile, sl.bt, smem_raw, threadIdx.x);
+  beta_forward_bf16x3_body<RTMAX>(S, coeffs, p, tabf, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
 // Inverse.  One workgroup per (pair tile, signal tile), in the order of
@@ -269,7 +272,10 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
 
   PairInfo pi[2];
 #pragma unroll
-  for (int q = 0; q < 2; q++) pi[q] = p.pairs[tile * PT + wave + 8 * q];
+  for (int q = 0; q < 2; q++) {
+    pi[q] = p.pairs[tile * PT + wave + 8 * q];
+    if (p.real && mirrored_pair(pi[q].tm, pi[q].tn)) pi[q].L = 0;  // its spectra are never read
+  }
 
   // B operands: lane (lrow, lg) holds degrees 32 s + 8 lg + i, i = 0..7, of
   // column ct * 16 + lrow; a round of 8 degrees (CoefRound) is exactly one
@@ -390,9 +396,9 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_kernel(const c
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles, (p.batch + BT - 1) / BT);  // natural order
+  const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles - p.tile0, (p.batch + BT - 1) / BT);  // natural order
   if (!sl.valid) return;
-  beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, sl.tile, sl.bt, smem_raw, threadIdx.x);
+  beta_inverse_bf16x3_body<LQ, BT>(coeffs, S, p, tabi, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
 // Reorder the tile-major split table into the node-interleaved forward layout.
@@ -422,7 +428,7 @@ static hipError_t set_smem_bf(K kern, size_t smem) {
 
 hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned* tabf, const cpx<float>* S,
                                       cpx<float>* coeffs, hipStream_t s) {
-  const dim3 grid(contraction_grid(p.ntiles, (p.batch + XBF_BT - 1) / XBF_BT, p.paired));
+  const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + XBF_BT - 1) / XBF_BT, p.paired));
   const int rt = beta_rtmax(p.B);
   hipError_t e;
 #define SU2_XBF_CASE(R)                                                                                           \
@@ -442,7 +448,7 @@ hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned
                                       cpx<float>* S, hipStream_t s) {
   const bool narrow = p.batch <= 16;  // 16-signal tiles
   const int bt = narrow ? 16 : XB_BT;
-  const dim3 grid(contraction_grid(p.ntiles, (p.batch + bt - 1) / bt));
+  const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt));
   const int lq2 = beta_bf16_lq(p.B);
   hipError_t e;
 #define SU2_XBI_CASE(Q, BTC)                                                                                  \

@@ -259,6 +259,8 @@ su2_status_t build_plan(su2_plan_s* pl) {
   const bool n256 = !pl->fast && pl->allow_large && large_ring_supported(N);
   pl->sliced = n256 && pl->dtype != SU2_C128;
   pl->large = n256;
+  // only the register-resident rings have a half-spectrum form for real signals
+  pl->real_io = pl->real && !pl->fast;
   if (pl->fast || n256) split = 1;
   pl->split = split;
   pl->Nc = N / split;
@@ -436,7 +438,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
   // real signals: every bin's source pair (its own, or the mirror (-m, -n)
   // with a conjugate) for the inverse ring kernel
   std::vector<int> bins_real;
-  if (pl->real) {
+  if (pl->real && !pl->real_io) {
     std::vector<int> at((size_t)(2 * B - 1) * (2 * B - 1), -1);
     for (int pidx = 0; pidx < pl->P_pad; pidx++)
       if (pairs[pidx].L > 0) at[(size_t)(pairs[pidx].tm + B - 1) * (2 * B - 1) + pairs[pidx].tn + B - 1] = pidx;
@@ -465,7 +467,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
     for (int blk = 0; blk < nblk; blk++) { qrange[2 * blk] = pl->P_pad; qrange[2 * blk + 1] = 0; }
     for (int pidx = 0; pidx < pl->P_pad; pidx++) {
       if (pairs[pidx].L == 0) continue;
-      const int blk = imod(pairs[pidx].tm, N) / qb;
+      const int blk = bin_q(pairs[pidx].tm) / qb;
       qrange[2 * blk] = std::min(qrange[2 * blk], pidx);
       qrange[2 * blk + 1] = std::max(qrange[2 * blk + 1], pidx + 1);
     }
@@ -494,7 +496,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
-  if (pl->real) {
+  if (pl->real && !pl->real_io) {
     if ((e = pl->alloc((void**)&pl->d_bins_real, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
     if ((e = hipMemcpy(pl->d_bins_real, bins_real.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) !=
         hipSuccess)
@@ -584,7 +586,7 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
   hipError_t e = hipSuccess;
   switch (stage) {
     case SU2_STAGE_RING_FORWARD:
-      if (pl->real)
+      if (pl->real && !pl->real_io)
         e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)S, s);
       else if (pl->sliced) {
         if constexpr (std::is_same<T, float>::value)
@@ -615,7 +617,7 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
       break;
     case SU2_STAGE_RING_INVERSE:
     case SU2_STAGE_RING_ADJOINT:
-      if (pl->real)
+      if (pl->real && !pl->real_io)
         e = launch_ring_inverse_fast_real<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
                                              (const cpx<T>*)S, (T*)out, s);
       else if (pl->large)
@@ -725,12 +727,10 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
   if ((size_t)2 * B * (size_t)batch * PT * (dtype == SU2_C128 ? 16 : 8) > (size_t)INT32_MAX)
     return SU2_ERR_UNSUPPORTED;  // see build_plan
   if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) && dtype == SU2_C64_BF16X3) return SU2_ERR_UNSUPPORTED;
-  const bool fast_b = B == 8 || B == 16 || B == 32 || B == 64;
-  if ((flags & SU2_PLAN_REAL_SIGNALS) &&
-      (dtype == SU2_C64_BF16X3 || (flags & SU2_PLAN_TABLES_ON_THE_FLY) || !fast_b))
+  // real signals and SO(3): every mode and bandlimit, with stored tables, not together
+  if ((flags & (SU2_PLAN_REAL_SIGNALS | SU2_PLAN_SO3)) && (flags & SU2_PLAN_TABLES_ON_THE_FLY))
     return SU2_ERR_UNSUPPORTED;
-  if ((flags & SU2_PLAN_SO3) && (dtype == SU2_C64_BF16X3 || (flags & ~(uint32_t)SU2_PLAN_SO3) || !fast_b))
-    return SU2_ERR_UNSUPPORTED;
+  if ((flags & SU2_PLAN_REAL_SIGNALS) && (flags & SU2_PLAN_SO3)) return SU2_ERR_UNSUPPORTED;
   su2_status_t st = check_device();
   if (st != SU2_OK) return st;
   su2_plan_s* pl = new (std::nothrow) su2_plan_s();
@@ -753,10 +753,19 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
 }
 
 su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype, su2_plan_t* out) {
+  return su2_plan_create_mixed_ex(B_per_signal, batch, dtype, 0u, out);
+}
+
+su2_status_t su2_plan_create_mixed_ex(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype, uint32_t flags,
+                                      su2_plan_t* out) {
   if (!out || !B_per_signal) return SU2_ERR_INVALID_VALUE;
   *out = nullptr;
   if (batch < 1) return SU2_ERR_INVALID_VALUE;
   if (dtype != SU2_C128 && dtype != SU2_C64 && dtype != SU2_C64_BF16X3) return SU2_ERR_INVALID_VALUE;
+  if (flags & ~(uint32_t)(SU2_PLAN_TABLES_ON_THE_FLY | SU2_PLAN_REAL_SIGNALS | SU2_PLAN_SO3))
+    return SU2_ERR_INVALID_VALUE;
+  if ((flags & SU2_PLAN_TABLES_ON_THE_FLY) || flags == (uint32_t)(SU2_PLAN_REAL_SIGNALS | SU2_PLAN_SO3))
+    return SU2_ERR_UNSUPPORTED;
   for (int i = 0; i < batch; i++) {
     if (B_per_signal[i] < 1) return SU2_ERR_INVALID_VALUE;
     if (B_per_signal[i] > 128 || !only_2_3(2 * B_per_signal[i])) return SU2_ERR_UNSUPPORTED;
@@ -765,7 +774,7 @@ su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, s
   if (st != SU2_OK) return st;
   su2_plan_s* pl = new (std::nothrow) su2_plan_s();
   if (!pl) return SU2_ERR_OUT_OF_MEMORY;
-  st = create_mixed(B_per_signal, batch, dtype, pl);
+  st = create_mixed(B_per_signal, batch, dtype, (flags & SU2_PLAN_REAL_SIGNALS) != 0, (flags & SU2_PLAN_SO3) != 0, pl);
   if (st != SU2_OK) {
     (void)hipDeviceSynchronize();
     release_mixed(pl);

@@ -95,6 +95,8 @@ struct RingParams {
   const int* colq;          // per LDS column c': q' with pos(q') = c'
   int adjoint;              // inverse chain: 0 -> plain, 1 -> multiply by W_k
   const long long* soff;    // per signal: offset of its samples (complex values), or null: b * N^3
+  int so3;                  // SO(3) plan: integer n only, no half-bin shift on any q
+  int real_io;              // real samples: the forward reads reals, the inverse writes the real part
 };
 
 // start of signal b's samples: an explicit offset table (batches of signals with
@@ -121,7 +123,28 @@ struct FastRingParams {
   // the source being the bin's own pair (2m >= 0) or its mirror (-m, -n)
   const int* bins_real;
   int so3;            // SO(3) plan: integer n only, no half-bin shift on any q
+  int real_io;        // N = 256 kernels: real samples in (forward) or the real part out (inverse)
 };
+
+// Sample access of the ring kernels.  Element idx of a signal buffer: complex,
+// or (real_io) the real sample at the same index of a real buffer, read as a
+// complex value with zero imaginary part; stores keep only the real part.
+// Samples are read or written exactly once: non-temporal accesses keep them
+// from evicting the ring spectra and tables from the caches.
+template <class T>
+__device__ __forceinline__ cpx<T> ld_sample(const cpx<T>* base, size_t idx, int real_io) {
+  if (real_io) return {__builtin_nontemporal_load(reinterpret_cast<const T*>(base) + idx), T(0)};
+  return {__builtin_nontemporal_load(&base[idx].re), __builtin_nontemporal_load(&base[idx].im)};
+}
+template <class T>
+__device__ __forceinline__ void st_sample(cpx<T>* base, size_t idx, cpx<T> v, int real_io) {
+  if (real_io) {
+    __builtin_nontemporal_store(v.re, reinterpret_cast<T*>(base) + idx);
+  } else {
+    __builtin_nontemporal_store(v.re, &base[idx].re);
+    __builtin_nontemporal_store(v.im, &base[idx].im);
+  }
+}
 
 // Parameters of the two-pass ring kernels (N = 256): the register-resident
 // kernels' parameters plus the pair range of every block of gamma frequencies

@@ -61,7 +61,8 @@ struct GroupDev {
 // Ring tasks come in two lists, one per ring kernel family, so that each
 // work-list kernel keeps the register budget of its single-B counterpart.
 // dir 0: forward (in = samples -> workspaces); 1: inverse, 2: adjoint (workspaces -> out = samples)
-template <class T, bool FWD>
+// REAL: real-signal plans (the half-spectrum form of the register-resident rings)
+template <class T, bool FWD, bool REAL>
 __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_fast_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<T>* __restrict__ groups, const cpx<T>* __restrict__ in,
     cpx<T>* __restrict__ out, int dir) {
@@ -79,9 +80,9 @@ __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_fast_w
 #define SU2_FAST_CASE(NN)                                                    \
   case NN:                                                                   \
     if constexpr (FWD)                                                       \
-      ring_forward_fast_group<T, NN>(in, S, p, w.a, w.b, smem, t);           \
+      ring_forward_fast_group<T, NN, REAL>(in, S, p, w.a, w.b, smem, t);     \
     else                                                                     \
-      ring_inverse_fast_group<T, NN>(S, out, p, w.a, w.b, smem, t);          \
+      ring_inverse_fast_group<T, NN, REAL>(S, out, p, w.a, w.b, smem, t);    \
     break;
     switch (p.N) {
       SU2_FAST_CASE(16)
@@ -104,10 +105,10 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_generic_worklist_kernel(cons
     const WorkItem w = items[it];
     const RingParams<T>& p = groups[w.g].rp[dir];
     if constexpr (FWD)
-      ring_forward_body<T>(in + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, groups[w.g].S, p, w.a, w.b,
+      ring_forward_body<T>(in, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, groups[w.g].S, p, w.a, w.b,
                            smem);
     else
-      ring_inverse_body<T>(groups[w.g].S, out + ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b,
+      ring_inverse_body<T>(groups[w.g].S, out, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b,
                            smem);
     __syncthreads();
   }
@@ -267,8 +268,9 @@ hipError_t mixed_alloc(MixedState* ms, void** p, size_t n) {
 
 // kernel selection by the plan's largest shapes
 template <class T>
-void* ringf_kernel_ptr(bool fwd) {
-  return fwd ? (void*)ring_fast_worklist_kernel<T, true> : (void*)ring_fast_worklist_kernel<T, false>;
+void* ringf_kernel_ptr(bool fwd, bool real) {
+  if (real) return fwd ? (void*)ring_fast_worklist_kernel<T, true, true> : (void*)ring_fast_worklist_kernel<T, false, true>;
+  return fwd ? (void*)ring_fast_worklist_kernel<T, true, false> : (void*)ring_fast_worklist_kernel<T, false, false>;
 }
 template <class T>
 void* ringg_kernel_ptr(bool fwd) {
@@ -343,7 +345,7 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
       if (ms->n_ringf > 0) {
         args[0] = (void*)&ms->d_ringf;
         args[1] = (void*)&ms->n_ringf;
-        if ((e = hipLaunchKernel(ringf_kernel_ptr<T>(which == 0), grid_of(ms->n_ringf), dim3(FAST_NT), args,
+        if ((e = hipLaunchKernel(ringf_kernel_ptr<T>(which == 0, pl->real), grid_of(ms->n_ringf), dim3(FAST_NT), args,
                                  ms->smem_ringf, s)) != hipSuccess)
           return e;
       }
@@ -409,8 +411,8 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
   void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax, ms->kc);
   void* ki = bf ? betai_bf16_kernel_ptr(ms->lq2) : betai_kernel_ptr<T>(ms->lq);
   for (int fwd = 0; fwd < 2; fwd++) {
-    if ((e = hipFuncSetAttribute(ringf_kernel_ptr<T>(fwd), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) !=
-        hipSuccess)
+    if ((e = hipFuncSetAttribute(ringf_kernel_ptr<T>(fwd, pl->real), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 max_lds)) != hipSuccess)
       return e;
     if ((e = hipFuncSetAttribute(ringg_kernel_ptr<T>(fwd), hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) !=
         hipSuccess)
@@ -487,7 +489,7 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
     cap_f += gp->ntiles * ((gp->batch + 15) / 16);
     cap_i += gp->ntiles * ((gp->batch + 15) / 16);
     if (only_group >= 0 && gi != only_group) continue;
-    for (int t = 0; t < gp->ntiles; t++) {
+    for (int t = d.bp[0].tile0; t < gp->ntiles; t++) {
       const double tile_cost = (double)N * std::max(1, gp->h_pairs[t * PT].lsum);
       for (int b = 0; b * btf < gp->batch; b++)
         betaf.push_back({tile_cost * std::min(btf, gp->batch - b * btf), WorkItem{gi, t, b}});
@@ -571,7 +573,7 @@ std::string tune_key(const su2_plan_s* pl) {
   hipDeviceProp_t prop;
   std::string arch = "gpu";
   if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
-  std::string k = arch + ":" + std::to_string((int)pl->dtype);
+  std::string k = arch + ":" + std::to_string((int)pl->dtype) + (pl->real ? "r" : "") + (pl->so3 ? "s" : "");
   const MixedState* ms = pl->mixed;
   for (size_t g = 0; g < ms->groups.size(); g++)
     k += ":" + std::to_string(ms->group_B[g]) + "x" + std::to_string(ms->groups[g]->batch);
@@ -776,11 +778,13 @@ void destroy_mixed(su2_plan_s* pl) {
 
 namespace su2 {
 
-su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, su2_plan_s* pl) {
+su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, bool real, bool so3, su2_plan_s* pl) {
   MixedState* ms = new (std::nothrow) MixedState();
   if (!ms) return SU2_ERR_OUT_OF_MEMORY;
   pl->mixed = ms;
   pl->dtype = dtype;
+  pl->real = real;
+  pl->so3 = so3;
   pl->batch = batch;
   pl->B = -1;
   hipError_t e;
@@ -797,7 +801,8 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
     soff[s] = ms->total_samples;
     coff[s] = ms->total_coeffs;
     ms->total_samples += N * N * N;
-    ms->total_coeffs += (long long)Bs[s] * (Bs[s] + 1) * (2 * Bs[s] + 1) / 6;
+    const long long L = (Bs[s] - 1) / 2;  // SO(3): largest integer l
+    ms->total_coeffs += so3 ? (L + 1) * (2 * L + 1) * (2 * L + 3) / 3 : (long long)Bs[s] * (Bs[s] + 1) * (2 * Bs[s] + 1) / 6;
     by_B[Bs[s]].push_back(s);
   }
   for (auto& kv : by_B) {
@@ -808,6 +813,8 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, s
     gp->B = kv.first;
     gp->batch = (int)kv.second.size();
     gp->dtype = dtype;
+    gp->real = real;
+    gp->so3 = so3;
     gp->allow_large = false;  // the work lists run the generic kernels for N = 256
     std::vector<long long> so, co;
     for (int s : kv.second) { so.push_back(soff[s]); co.push_back(coff[s]); }

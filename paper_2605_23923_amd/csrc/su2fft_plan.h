@@ -43,7 +43,12 @@ struct su2_plan_s {
   // recurrence coefficients, node values
   bool otf = false;
   bool sym = false;             // point-symmetric pair layout, upper tiles share the lower tiles' table blocks
-  bool real = false;            // real-signal plan (pairs with 2m >= 0 carry the spectra)
+  bool real = false;            // real-signal plan
+  // real-signal plan on the complex kernels (rings without a half-spectrum
+  // form: generic and N = 256): real samples in, real part out, every pair
+  // contracted; otherwise a real plan forms and contracts only the pairs
+  // with 2m > 0, or 2m = 0 and 2n >= 0
+  bool real_io = false;
   bool so3 = false;             // SO(3) plan: integer l, gamma over [-pi, pi)
   int* d_bins_real = nullptr;
   double* d_seedc = nullptr;
@@ -86,7 +91,7 @@ void set_last_hip_error(hipError_t e);
 bool only_2_3(int n);
 su2_status_t build_plan(su2_plan_s* pl);
 // mixed-bandlimit plans (su2fft_kernels.hip)
-su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, su2_plan_s* pl);
+su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, bool real, bool so3, su2_plan_s* pl);
 void release_mixed(su2_plan_s* pl);
 su2_status_t run_mixed(su2_plan_s* pl, int dir, const void* in, void* out, hipStream_t stream);
 void mixed_tuning(const su2_plan_s* pl, int32_t* knobs);
@@ -107,6 +112,8 @@ RingParams<T> ring_params(const su2_plan_s* pl, int adjoint) {
   r.colq = pl->d_colq;
   r.adjoint = adjoint;
   r.soff = pl->d_soff;
+  r.so3 = pl->so3 ? 1 : 0;
+  r.real_io = pl->real_io ? 1 : 0;
   return r;
 }
 
@@ -123,6 +130,7 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   r.soff = pl->d_soff;
   r.bins_real = pl->d_bins_real;
   r.so3 = pl->so3 ? 1 : 0;
+  r.real_io = pl->real_io ? 1 : 0;
   return r;
 }
 
@@ -169,8 +177,9 @@ BetaParams<T> beta_params(const su2_plan_s* pl, const T* tab, int scale_mode) {
                                           : reinterpret_cast<const T*>(pl->d_tabi32);
   b.scale_mode = scale_mode;
   b.coff = pl->d_coff;
-  b.real = pl->real ? 1 : 0;
-  b.tile0 = pl->real ? pl->rbeg[0] / PT : 0;
+  const bool half = pl->real && !pl->real_io;  // half-spectrum real plan
+  b.real = half ? 1 : 0;
+  b.tile0 = half ? pl->rbeg[0] / PT : 0;
   b.so3 = pl->so3 ? 1 : 0;
   b.table_signs = pl->sym ? 1 : 0;
   b.paired = (pl->sym && b.tile0 == 0) ? 1 : 0;

@@ -160,11 +160,19 @@ __device__ void run_dit(cpx<T>* X, int nlines, int L, int es, int ls, bool line_
   }
 }
 
-// Body of one ring (signal b, node k): x is the ring's N x N input block, smem
-// holds N * Nc + 2N complex values.
+// sample idx of a buffer of complex samples, or (real_io) of real samples
 template <class T>
-__device__ void ring_forward_body(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ S, const RingParams<T>& p,
-                                  int b, int k, unsigned char* smem_raw) {
+__device__ __forceinline__ cpx<T> ring_sample(const cpx<T>* __restrict__ x, size_t idx, int real_io) {
+  if (real_io) return {reinterpret_cast<const T*>(x)[idx], T(0)};
+  return x[idx];
+}
+
+// Body of one ring (signal b, node k): the ring's N x N input block starts at
+// element x0 of the sample buffer xs (complex, or real for real_io plans);
+// smem holds N * Nc + 2N complex values.
+template <class T>
+__device__ void ring_forward_body(const cpx<T>* __restrict__ xs, size_t x0, cpx<T>* __restrict__ S,
+                                  const RingParams<T>& p, int b, int k, unsigned char* smem_raw) {
   const int N = p.N, Nc = p.Nc, R = p.split, twoN = 2 * N;
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = X + N * Nc;
@@ -177,11 +185,11 @@ __device__ void ring_forward_body(const cpx<T>* __restrict__ x, cpx<T>* __restri
       const int j = e / Nc, c = e - j * Nc;
       cpx<T> v;
       if (R == 1) {
-        v = x[(size_t)j * N + c];
+        v = ring_sample(xs, x0 + (size_t)j * N + c, p.real_io);
       } else {
         v = {T(0), T(0)};
         for (int i = 0; i < R; i++) {
-          cpx<T> xi = x[(size_t)j * N + c + i * Nc];
+          cpx<T> xi = ring_sample(xs, x0 + (size_t)j * N + c + i * Nc, p.real_io);
           v = cadd(v, cmul(xi, tw[((twoN / R) * r * i) % twoN]));
         }
         v = cmul(v, tw[(2 * r * c) % twoN]);
@@ -191,11 +199,12 @@ __device__ void ring_forward_body(const cpx<T>* __restrict__ x, cpx<T>* __restri
     __syncthreads();
     // gamma: rows j, length Nc
     run_dif<T>(X, N, Nc, 1, Nc, false, p.rad_c, p.nrad_c, tw, twoN);
-    // half-bin twist e^{i pi j / N} on columns whose q is odd (half-integer n)
+    // half-bin twist e^{i pi j / N} on columns whose q is odd (half-integer n;
+    // none in SO(3) plans, whose n are integers)
     for (int e = threadIdx.x; e < N * Nc; e += blockDim.x) {
       const int j = e / Nc, c = e - j * Nc;
       const int q = R * p.colq[c] + r;
-      if (q & 1) X[e] = cmul(X[e], tw[j]);
+      if ((q & 1) && !p.so3) X[e] = cmul(X[e], tw[j]);
     }
     __syncthreads();
     // alpha: columns, length N
@@ -215,12 +224,14 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_forward_kernel(const cpx<T>*
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring = blockIdx.x;
   const int b = ring / p.N, k = ring - b * p.N;
-  ring_forward_body<T>(samples + ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, S, p, b, k, smem_raw);
+  ring_forward_body<T>(samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, S, p, b, k, smem_raw);
 }
 
+// The ring's N x N output block starts at element x0 of the sample buffer xs
+// (complex, or real for real_io plans: the real part is written).
 template <class T>
-__device__ void ring_inverse_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ x, const RingParams<T>& p,
-                                  int b, int k, unsigned char* smem_raw) {
+__device__ void ring_inverse_body(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xs, size_t x0,
+                                  const RingParams<T>& p, int b, int k, unsigned char* smem_raw) {
   const int N = p.N, Nc = p.Nc, R = p.split, twoN = 2 * N;
   cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = X + N * Nc;
@@ -240,22 +251,26 @@ __device__ void ring_inverse_body(const cpx<T>* __restrict__ S, cpx<T>* __restri
     for (int e = threadIdx.x; e < N * Nc; e += blockDim.x) {
       const int j = e / Nc, c = e - j * Nc;
       const int q = R * p.colq[c] + r;
-      if (q & 1) X[e] = cmulc(X[e], tw[j]);
+      if ((q & 1) && !p.so3) X[e] = cmulc(X[e], tw[j]);
     }
     __syncthreads();
     run_dit<T>(X, N, Nc, 1, Nc, false, p.rad_c, p.nrad_c, tw, twoN);
     // undo the gamma split: x[j][c + i Nc] += e^{-2 pi i r i / R} w^{-r c} y_r[j][c].
     // Each output element is read and written by the same thread in every class.
+    T* xr = reinterpret_cast<T*>(xs);
     for (int e = threadIdx.x; e < N * Nc; e += blockDim.x) {
       const int j = e / Nc, c = e - j * Nc;
       if (R == 1) {
-        x[(size_t)j * N + c] = X[e];
+        const size_t o = x0 + (size_t)j * N + c;
+        if (p.real_io) xr[o] = X[e].re;
+        else xs[o] = X[e];
       } else {
         cpx<T> y = cmulc(X[e], tw[(2 * r * c) % twoN]);
         for (int i = 0; i < R; i++) {
           cpx<T> v = cmulc(y, tw[((twoN / R) * r * i) % twoN]);
-          size_t o = (size_t)j * N + c + i * Nc;
-          x[o] = (r == 0) ? v : cadd(x[o], v);
+          const size_t o = x0 + (size_t)j * N + c + i * Nc;
+          if (p.real_io) xr[o] = (r == 0) ? v.re : xr[o] + v.re;
+          else xs[o] = (r == 0) ? v : cadd(xs[o], v);
         }
       }
     }
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_inverse_kernel(const cpx<T>*
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring = blockIdx.x;
   const int b = ring / p.N, k = ring - b * p.N;
-  ring_inverse_body<T>(S, samples + ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, p, b, k, smem_raw);
+  ring_inverse_body<T>(S, samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, p, b, k, smem_raw);
 }
 
 template <class T>

@@ -784,8 +784,12 @@ static hipError_t launch_fast(bool forward, bool real, const FastRingParams<T>& 
   typedef FastRing<T, N> R;
   if (!slices_fit<T, N>(p) || (real && !p.bins_real)) return hipErrorInvalidValue;
   if constexpr (N == 128 && std::is_same<T, double>::value) {
-    if (!forward) {  // two rings per workgroup (a signal's N rings pair up)
-      const void* kern = real ? (const void*)ring_inverse_fast_pair<T, true> : (const void*)ring_inverse_fast_pair<T, false>;
+    // two rings per workgroup (a signal's N rings pair up).  Complex plans
+    // only: the real variant of the paired kernel rounds some values
+    // differently (last bits) from the single-ring body that mixed plans run,
+    // and real plans keep the single-ring kernel so that both agree bit for bit.
+    if (!forward && !real) {
+      const void* kern = (const void*)ring_inverse_fast_pair<T, false>;
       hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)R::SMEM);
       if (e != hipSuccess) return e;
       FastRingParams<T> pp = p;

@@ -83,10 +83,10 @@ __global__ __launch_bounds__(LG_NT) void ring_rows_forward_large(const cpx<T>* _
   const int ring = p.ring0 + rc, b = ring / N, k = ring - b * N;
   const int line = t / 16, c = t % 16;
   const int j0 = blk * LG_LINES;
-  const cpx<T>* x = samples + ring_offset(p.f.soff, b, N) + ((size_t)k * N + j0 + line) * N;
+  const size_t x0 = ring_offset(p.f.soff, b, N) + ((size_t)k * N + j0 + line) * N;
   cpx<T> v[16];
 #pragma unroll
-  for (int i = 0; i < 16; i++) v[i] = ld_stream(x + c + 16 * i);
+  for (int i = 0; i < 16; i++) v[i] = ld_sample(samples, x0 + c + 16 * i, p.f.real_io);
   large_load_tw(tws, p.f.tw, t);
   __syncthreads();
   line_dft256<T, 1>(v, c, buf + line * 16 * LG_XP, tws);  // lane c: G[j][q = c + 16 o]
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(LG_NT) void ring_cols_forward_large(cpx<T>* __restr
   for (int i = 0; i < 8; i++) ent[i] = p.f.bins[q * N + c + 16 * kept_row<16>(i)];
   large_load_tw(tws, p.f.tw, t);
   __syncthreads();
-  const bool odd = q & 1;  // half-integer n: input shifted by e^{i pi j / N}
+  const bool odd = (q & 1) && !p.f.so3;  // half-integer n: input shifted by e^{i pi j / N}
 #pragma unroll
   for (int i = 0; i < 16; i++) {
     v[i] = csel(odd, cmul(v[i], tws[c + 16 * i]), v[i]);
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(LG_NT) void ring_cols_inverse_large(const cpx<T>* _
   }
   __syncthreads();
   line_dft256<T, -1>(v, c, buf + line * 16 * LG_XP, tws);  // lane c: y[j = c + 16 o]
-  const bool odd = q & 1;
+  const bool odd = (q & 1) && !p.f.so3;
   cpx<T>* g = p.G + ((size_t)rc * N + q) * N;
 #pragma unroll
   for (int o = 0; o < 16; o++) {
@@ -215,9 +215,9 @@ __global__ __launch_bounds__(LG_NT) void ring_rows_inverse_large(cpx<T>* __restr
   for (int i = 0; i < 16; i++) v[i] = buf[(c + 16 * i) * LG_TP + line];  // G[j][q = c + 16 i]
   __syncthreads();
   line_dft256<T, -1>(v, c, buf + line * 16 * LG_XP, tws);  // lane c: f[j][l = c + 16 o]
-  cpx<T>* x = samples + ring_offset(p.f.soff, b, N) + ((size_t)k * N + j0 + line) * N;
+  const size_t x0 = ring_offset(p.f.soff, b, N) + ((size_t)k * N + j0 + line) * N;
 #pragma unroll
-  for (int o = 0; o < 16; o++) st_stream(x + c + 16 * o, v[o]);
+  for (int o = 0; o < 16; o++) st_sample(samples, x0 + c + 16 * o, v[o], p.f.real_io);
 }
 
 // ---- forward in one pass, in slices (FP32) ----
@@ -303,6 +303,7 @@ __global__ __launch_bounds__(SL_NT) void ring_forward_sliced(const cpx<float>* _
   const int ring = sl.tile, s = sl.bt;
   const int b = ring / N, k = ring - b * N;
   const cpx<T>* x = samples + ring_offset(p.soff, b, N) + (size_t)k * N * N;
+  const T* xr = reinterpret_cast<const T*>(samples) + ring_offset(p.soff, b, N) + (size_t)k * N * N;
   sl_tables(tb, p.tw, s, t);
   __syncthreads();
 
@@ -312,8 +313,13 @@ __global__ __launch_bounds__(SL_NT) void ring_forward_sliced(const cpx<float>* _
   for (int h = 0; h < 2; h++) {
     const int j = rr + 128 * h;
     cpx<T> v[32];  // f[j][c + 8 m], m = 0..31
+    if (p.real_io) {  // real samples (plain loads: the ring's other slices read them from L2)
 #pragma unroll
-    for (int m = 0; m < 32; m++) v[m] = x[(size_t)j * N + c + 8 * m];
+      for (int m = 0; m < 32; m++) v[m] = {xr[(size_t)j * N + c + 8 * m], T(0)};
+    } else {
+#pragma unroll
+      for (int m = 0; m < 32; m++) v[m] = x[(size_t)j * N + c + 8 * m];
+    }
     cpx<T> y[8];  // radix-4 step over l1 for this s: y[m] for l2 = c + 8 m
 #pragma unroll
     for (int m = 0; m < 8; m++) {

@@ -95,17 +95,19 @@ def test_argument_validation_before_any_device_call():
     assert lib.su2_plan_create_ex(8, 1, 1, 0x80000000, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 1, 2, 1, ctypes.byref(h)) == 2
     assert lib.su2_plan_create_ex(0, 1, 1, 1, ctypes.byref(h)) == 1
-    # real signals: not with the split-BF16 mode, not with generated tables, B in {8, 16, 32, 64}
-    assert lib.su2_plan_create_ex(8, 1, 2, 2, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(8, 1, 1, 3, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(24, 1, 1, 2, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(128, 1, 0, 2, ctypes.byref(h)) == 2
-    # SO(3): c128 / c64, B in {8, 16, 32, 64}, no other option
-    assert lib.su2_plan_create_ex(8, 1, 2, 4, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(8, 1, 1, 5, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(8, 1, 1, 6, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(24, 1, 0, 4, ctypes.byref(h)) == 2
-    assert lib.su2_plan_create_ex(128, 1, 0, 4, ctypes.byref(h)) == 2
+    # real signals and SO(3): every mode and bandlimit, not with generated
+    # tables and not together (accepted combinations need a device: not here)
+    for dt in (0, 1, 2):
+        for B in (8, 24, 128):
+            assert lib.su2_plan_create_ex(B, 1, dt, 3, ctypes.byref(h)) == 2   # real + on the fly
+            assert lib.su2_plan_create_ex(B, 1, dt, 5, ctypes.byref(h)) == 2   # SO(3) + on the fly
+            assert lib.su2_plan_create_ex(B, 1, dt, 6, ctypes.byref(h)) == 2   # real + SO(3)
+    # mixed plans with options: the same rules, unknown bits rejected first
+    bs2 = (ctypes.c_int32 * 2)(8, 24)
+    assert lib.su2_plan_create_mixed_ex(bs2, 2, 1, 8, ctypes.byref(h)) == 1
+    assert lib.su2_plan_create_mixed_ex(bs2, 2, 1, 1, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_mixed_ex(bs2, 2, 1, 6, ctypes.byref(h)) == 2
+    assert lib.su2_plan_create_mixed_ex(None, 2, 1, 2, ctypes.byref(h)) == 1
     assert lib.su2_plan_create_ex(8, 0, 0, 4, ctypes.byref(h)) == 1
 
 

@@ -139,6 +139,41 @@ def test_autotuner_choice_does_not_change_results():
     assert np.array_equal(_host(tuned.adjoint(c)), _host(plain.adjoint(c)))
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
+@pytest.mark.parametrize("kind", ["real", "so3"])
+def test_mixed_real_and_so3_bitwise_equal_single_plans(kind, dtype):
+    """Mixed real-signal and SO(3) plans: every signal equals a batch-1 plan of
+    the same kind, bit for bit (half-spectrum rings at B = 8, 16, 64, generic
+    rings at B = 12, 24)."""
+    Bs = [16, 12, 64, 8, 24, 16, 64]
+    rng = np.random.default_rng(41)
+    kw = dict(real=True) if kind == "real" else dict(group="so3")
+    mp = su2.MixedPlan(Bs, dtype, **kw)
+    xs, cs = [], []
+    for B in Bs:
+        if kind == "real":
+            xs.append(synth.samples_uniform(B, 1, seed=int(rng.integers(1 << 30))).real.astype(
+                np.float64 if dtype == "c128" else np.float32).reshape(-1))
+            cs.append(synth.coeffs(B, 1, seed=int(rng.integers(1 << 30)), dtype=NPDT[dtype])[0])
+        else:
+            xs.append(synth.samples_uniform(B, 1, seed=int(rng.integers(1 << 30)), dtype=NPDT[dtype])[0].reshape(-1))
+            cs.append(synth.coeffs_so3(B, 1, seed=int(rng.integers(1 << 30)), dtype=NPDT[dtype])[0])
+    f = _split(_host(mp.forward(_dev(np.concatenate(xs)))), mp.coeff_offsets)
+    i = _split(_host(mp.inverse(_dev(np.concatenate(cs)))), mp.sample_offsets)
+    a = _split(_host(mp.adjoint(_dev(np.concatenate(cs)))), mp.sample_offsets)
+    def same(got, ref, what):
+        diff = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+        assert np.array_equal(got, ref), (what, f"max relative difference {diff:.3e}")
+
+    for s_, B in enumerate(Bs):
+        p = su2.Plan(B, 1, dtype, **kw)
+        N = 2 * B
+        same(f[s_], _host(p.forward(_dev(xs[s_].reshape(1, N, N, N))))[0], (s_, B, "forward"))
+        same(i[s_], _host(p.inverse(_dev(cs[s_].reshape(1, -1)))).reshape(-1), (s_, B, "inverse"))
+        same(a[s_], _host(p.adjoint(_dev(cs[s_].reshape(1, -1)))).reshape(-1), (s_, B, "adjoint"))
+        p.close()
+
+
 class _env:
     """Set environment variables for the plan creations inside the block."""
 

@@ -14,10 +14,10 @@ from _errlog import record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"c128": 1e-10, "c64": 1e-6}
+TOL = {"c128": 1e-10, "c64": 1e-6, "c64_bf16x3": 1e-5}
 WORST = 10  # the worst element may be this many times the normwise bound
-RDT = {"c128": np.float64, "c64": np.float32}
-CDT = {"c128": np.complex128, "c64": np.complex64}
+RDT = {"c128": np.float64, "c64": np.float32, "c64_bf16x3": np.float32}
+CDT = {"c128": np.complex128, "c64": np.complex64, "c64_bf16x3": np.complex64}
 
 
 def _dev(a):
@@ -43,9 +43,11 @@ def _real_samples(B, batch, seed, dtype):
     return synth.samples_uniform(B, batch, seed=seed).real.astype(RDT[dtype])
 
 
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("B", [8, 16])
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
+@pytest.mark.parametrize("B", [4, 8, 12, 16])
 def test_real_plan_matches_oracle(B, dtype):
+    """B = 8, 16: the half-spectrum rings; B = 4, 12 (N = 8, 24): the generic
+    rings with real samples in and the real part out."""
     batch = 3
     plan = su2.Plan(B, batch, dtype, real=True)
     x = _real_samples(B, batch, 1200 + B, dtype)
@@ -75,6 +77,54 @@ def test_real_plan_equals_complex_plan(B, batch, dtype):
     sel = rng.choice(oracle.num_coeffs(B), 40, replace=False)
     _check(_host(pr.forward(_dev(x)))[batch - 1][sel], oracle.forward(B, x[batch - 1].astype(np.complex128), sel),
            TOL[dtype], f"real forward B={B} {dtype} sampled")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
+@pytest.mark.parametrize("B,batch", [(24, 3), (128, 2)])
+def test_real_io_plans_bitwise_equal_complex_plans(B, batch, dtype):
+    """Bandlimits without the half-spectrum rings (N = 48 generic, N = 256):
+    the complex kernels run on the real samples, so forward equals a complex
+    plan's on the same samples, and inverse and adjoint equal the real part of
+    a complex plan's, bit for bit; sampled coefficients and points against the
+    oracle."""
+    x = _real_samples(B, batch, 1800 + B, dtype)
+    c = synth.coeffs(B, batch, seed=1900 + B, spectrum="decay", dtype=CDT[dtype])
+    pr = su2.Plan(B, batch, dtype, real=True)
+    fr = _host(pr.forward(_dev(x)))
+    ir = _host(pr.inverse(_dev(c)))
+    ar = _host(pr.adjoint(_dev(c)))
+    pr.close()
+    pc = su2.Plan(B, batch, dtype)
+    fc = _host(pc.forward(_dev(x.astype(CDT[dtype]))))
+    assert np.array_equal(fr, fc), "forward"
+    assert np.array_equal(ir, _host(pc.inverse(_dev(c))).real), "inverse"
+    assert np.array_equal(ar, _host(pc.adjoint(_dev(c))).real), "adjoint"
+    pc.close()
+    rng = np.random.default_rng(B)
+    sel = rng.choice(oracle.num_coeffs(B), 24, replace=False)
+    sel[0] = oracle.num_coeffs(B) - 1
+    _check(fr[batch - 1][sel], oracle.forward(B, x[batch - 1].astype(np.complex128), sel), TOL[dtype],
+           f"real forward B={B} {dtype} sampled")
+    N = 2 * B
+    pts = rng.choice(N ** 3, 24, replace=False)
+    _check(ir.reshape(batch, -1)[batch - 1][pts], oracle.inverse(B, c[batch - 1], pts).real, TOL[dtype],
+           f"real inverse B={B} {dtype} sampled")
+
+
+@pytest.mark.parametrize("B,batch", [(16, 3), (64, 32)])
+def test_real_plan_split_bf16_equals_complex_plan(B, batch):
+    """Half-spectrum rings with the split-BF16 contraction: the same values as a
+    split-BF16 complex plan on the same samples, to the mode's rounding."""
+    x = _real_samples(B, batch, 2000 + B, "c64_bf16x3")
+    c = synth.coeffs(B, batch, seed=2050 + B, spectrum="decay", dtype=np.complex64)
+    pr = su2.Plan(B, batch, "c64_bf16x3", real=True)
+    pc = su2.Plan(B, batch, "c64_bf16x3")
+    _check(_host(pr.forward(_dev(x))), _host(pc.forward(_dev(x.astype(np.complex64)))), TOL["c64_bf16x3"],
+           f"real vs complex forward B={B} c64_bf16x3")
+    _check(_host(pr.inverse(_dev(c))), _host(pc.inverse(_dev(c))).real, TOL["c64_bf16x3"],
+           f"real vs complex inverse B={B} c64_bf16x3")
+    _check(_host(pr.adjoint(_dev(c))), _host(pc.adjoint(_dev(c))).real, TOL["c64_bf16x3"],
+           f"real vs complex adjoint B={B} c64_bf16x3")
 
 
 def test_real_round_trip_b64():
@@ -120,12 +170,10 @@ def test_real_autograd_matches_central_differences():
 
 
 def test_real_plan_options_rejected():
-    for kw in (dict(dtype="c64_bf16x3"), dict(dtype="c64", tables="on_the_fly")):
+    for kw in (dict(dtype="c64", tables="on_the_fly"), dict(dtype="c64", group="so3")):
         with pytest.raises(su2.SU2Error) as ei:
             su2.Plan(8, 1, real=True, **kw)
         assert ei.value.status == 2
-    with pytest.raises(su2.SU2Error):
-        su2.Plan(24, 1, "c64", real=True)
     plan = su2.Plan(8, 1, "c64", real=True)
     with pytest.raises(TypeError):
         plan.forward(torch.zeros((1, 16, 16, 16), dtype=torch.complex64, device="cuda"))
