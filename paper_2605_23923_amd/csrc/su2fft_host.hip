@@ -459,6 +459,40 @@ su2_status_t build_plan(su2_plan_s* pl) {
     const int cap = pl->dtype == SU2_C128 ? fast_ring_slice_capacity<double>(N) : fast_ring_slice_capacity<float>(N);
     if (pl->fast && pl->rend[r] - pl->rbeg[r] > cap) return SU2_ERR_UNSUPPORTED;
   }
+  // one-pass N = 256 kernels (FP32): per gamma frequency q the bases from
+  // which the kernels compute every bin's pair and phase (FastRingParams::cols),
+  // checked here against the bin map; if the pair layout does not follow them,
+  // the plan keeps the two-pass kernels
+  std::vector<int> cols;
+  if (pl->sliced) {
+    cols.assign((size_t)4 * N, 0);
+    bool ok = true;
+    for (int q = 0; q < N && ok; q++) {
+      const int* bq = &bins[(size_t)q * N];
+      int* cq = &cols[(size_t)4 * q];
+      const bool valid = bq[0] >= 0;
+      if (valid) {
+        int hi_first = 192;
+        while (hi_first < N && bq[hi_first] < 0) hi_first++;
+        if (hi_first > 195 || bq[1] < 0) { ok = false; break; }
+        cq[0] = (bq[hi_first] >> 2) - (hi_first - 192);
+        cq[1] = bq[0] >> 2;
+        cq[2] = (bq[1] >> 2) - 1;
+        cq[3] = (bq[0] & 3) | ((hi_first - 192) << 2) | (1 << 4);
+      }
+      for (int pp = 0; pp < N && ok; pp++) {
+        const bool kept = valid && (pp < 64 || pp >= 192 + ((cq[3] >> 2) & 3));
+        if (!kept) { ok = bq[pp] < 0; continue; }
+        const int pidx = pp < 64 ? (pp == 0 ? cq[1] : cq[2] + pp) : cq[0] + (pp - 192);
+        const int ee = (3 * pp + (cq[3] & 3)) & 3;
+        ok = bq[pp] == ((pidx << 2) | ee);
+      }
+    }
+    if (!ok) {
+      cols.clear();
+      pl->sliced = false;
+    }
+  }
   // two-pass kernels: pair range of every block of gamma frequencies
   std::vector<int> qrange;
   if (pl->large) {
@@ -496,6 +530,11 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);
+  if (!cols.empty()) {
+    if ((e = pl->alloc((void**)&pl->d_cols, sizeof(int) * cols.size())) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpy(pl->d_cols, cols.data(), sizeof(int) * cols.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e);
+  }
   if (pl->real && !pl->real_io) {
     if ((e = pl->alloc((void**)&pl->d_bins_real, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
     if ((e = hipMemcpy(pl->d_bins_real, bins_real.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) !=
@@ -558,7 +597,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
       return hip_fail(e);
   }
   if ((e = pl->alloc(&pl->d_S, cb * (size_t)pl->P_pad * N * pl->batch)) != hipSuccess) return hip_fail(e);
-  if (pl->large) {
+  if (pl->large && !pl->sliced) {
     // intermediate of the two-pass ring kernels: a chunk of rings, at most 128 MB
     const size_t ring_bytes = cb * (size_t)N * N;
     pl->large_chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)pl->batch * N, (128u << 20) / ring_bytes));
@@ -590,7 +629,7 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
         e = launch_ring_forward_fast_real<T>(fast_params<T>(pl, 0), (const T*)in, (cpx<T>*)S, s);
       else if (pl->sliced) {
         if constexpr (std::is_same<T, float>::value)
-          e = launch_ring_forward_sliced(fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
+          e = launch_ring_sliced4(true, fast_params<T>(pl, 0), (const cpx<T>*)in, (cpx<T>*)S, s);
         else
           e = hipErrorInvalidValue;
       } else if (pl->large)
@@ -620,7 +659,13 @@ su2_status_t run_stage_t(su2_plan_s* pl, su2_stage_t stage, const void* in, void
       if (pl->real && !pl->real_io)
         e = launch_ring_inverse_fast_real<T>(fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
                                              (const cpx<T>*)S, (T*)out, s);
-      else if (pl->large)
+      else if (pl->sliced) {
+        if constexpr (std::is_same<T, float>::value)
+          e = launch_ring_sliced4(false, fast_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT), (const cpx<T>*)S,
+                                  (cpx<T>*)out, s);
+        else
+          e = hipErrorInvalidValue;
+      } else if (pl->large)
         e = launch_ring_inverse_large<T>(large_params<T>(pl, stage == SU2_STAGE_RING_ADJOINT),
                                          (const cpx<T>*)S, (cpx<T>*)out, s);
       else if (pl->fast)

@@ -124,6 +124,12 @@ struct FastRingParams {
   const int* bins_real;
   int so3;            // SO(3) plan: integer n only, no half-bin shift on any q
   int real_io;        // N = 256 kernels: real samples in (forward) or the real part out (inverse)
+  // N = 256 one-pass kernels: per gamma frequency q, 4 ints (the pair index of
+  // bin p = 192, of p = 0, of p = 1 minus 1; e0 | (first retained p >= 192,
+  // minus 192) << 2 | (column retained) << 4): bin (p, q) is retained for p in
+  // [0, 64) and [192 + ((w >> 2) & 3), 256) of a retained column, its pair
+  // index runs on from those bases and its phase exponent is (3 p + e0) mod 4
+  const int* cols;
 };
 
 // Sample access of the ring kernels.  Element idx of a signal buffer: complex,
@@ -131,14 +137,28 @@ struct FastRingParams {
 // complex value with zero imaginary part; stores keep only the real part.
 // Samples are read or written exactly once: non-temporal accesses keep them
 // from evicting the ring spectra and tables from the caches.
+// A zero the compiler cannot see: real samples enter the transforms with this
+// imaginary part, so that they are computed exactly as complex samples with a
+// zero imaginary part (a known zero would be folded away and change which
+// products become FMAs, and with them the rounding).
+template <class T>
+__device__ __forceinline__ T opaque_zero() {
+  T z = T(0);
+  asm volatile("" : "+v"(z));
+  return z;
+}
 template <class T>
 __device__ __forceinline__ cpx<T> ld_sample(const cpx<T>* base, size_t idx, int real_io) {
-  if (real_io) return {__builtin_nontemporal_load(reinterpret_cast<const T*>(base) + idx), T(0)};
+  if (real_io) return {__builtin_nontemporal_load(reinterpret_cast<const T*>(base) + idx), opaque_zero<T>()};
   return {__builtin_nontemporal_load(&base[idx].re), __builtin_nontemporal_load(&base[idx].im)};
 }
 template <class T>
 __device__ __forceinline__ void st_sample(cpx<T>* base, size_t idx, cpx<T> v, int real_io) {
   if (real_io) {
+    // the imaginary part is formed all the same, so that the compiler builds
+    // the real part exactly as in the complex case (a dead imaginary part
+    // changes which products it fuses into FMAs, and with them the rounding)
+    asm volatile("" ::"v"(v.im));
     __builtin_nontemporal_store(v.re, reinterpret_cast<T*>(base) + idx);
   } else {
     __builtin_nontemporal_store(v.re, &base[idx].re);
@@ -289,6 +309,10 @@ hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned
                                       cpx<float>* coeffs, hipStream_t s);
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s);
+// N = 256 rings in FP32 in one pass, four workgroups per ring, two per CU
+// (forward: samples -> S; inverse / adjoint: S -> samples)
+hipError_t launch_ring_sliced4(bool forward, const FastRingParams<float>& p, const cpx<float>* in, cpx<float>* out,
+                               hipStream_t s);
 hipError_t launch_interleave_bf16_table(int N, int ntiles, const PairInfo* pairs, const bf16x2_t* src, unsigned* dst,
                                         hipStream_t s);
 
@@ -325,10 +349,6 @@ hipError_t launch_ring_forward_fast_real(const FastRingParams<T>& p, const T* sa
 template <class T>
 hipError_t launch_ring_inverse_fast_real(const FastRingParams<T>& p, const cpx<T>* S, T* samples, hipStream_t s);
 
-// single-pass N = 256 forward ring in FP32: four workgroups per ring, each
-// holding a quarter of the transform in LDS (no intermediate buffer)
-hipError_t launch_ring_forward_sliced(const FastRingParams<float>& p, const cpx<float>* samples, cpx<float>* S,
-                                      hipStream_t s);
 bool large_ring_supported(int N);
 int large_ring_block();           // gamma frequencies per block (pair ranges are given per block)
 int large_ring_slice_capacity();  // pairs of one block the kernels can stage in LDS

@@ -30,6 +30,7 @@
 #include "su2fft_ring.hip"
 #include "su2fft_ring_fast.hip"
 #include "su2fft_ring_large.hip"
+#include "su2fft_ring_sliced.hip"
 #include "su2fft_beta.hip"
 #include "su2fft_beta_bf16.hip"
 #include "su2fft_beta_otf.hip"

@@ -55,7 +55,8 @@ struct su2_plan_s {
   double* d_rcoef = nullptr;
   double* d_nodes = nullptr;  // [3][N]: cos(beta_k), cos(beta_k / 2), sin(beta_k / 2)
   bool large = false;            // N = 256: two-pass ring kernels through an intermediate (d_G)
-  bool sliced = false;          // N = 256 in FP32: the forward ring runs in one pass, four workgroups per ring
+  bool sliced = false;          // N = 256 in FP32: both ring directions run in one pass, four workgroups per ring
+  int* d_cols = nullptr;        // N = 256 in FP32: per-column bin bases of the one-pass rings (null: not usable)
   bool allow_large = true;  // mixed-plan groups use the generic kernels instead
   int* d_qrange = nullptr;
   void* d_G = nullptr;
@@ -131,6 +132,7 @@ FastRingParams<T> fast_params(const su2_plan_s* pl, int adjoint) {
   r.bins_real = pl->d_bins_real;
   r.so3 = pl->so3 ? 1 : 0;
   r.real_io = pl->real_io ? 1 : 0;
+  r.cols = pl->d_cols;
   return r;
 }
 
