@@ -333,50 +333,72 @@ __device__ __forceinline__ void s4_rows_inverse(cpx<float>* row, int swr, int c,
   }
 }
 
+// Spectra of one column (q = 2 cq + odd) as this lane loads them: bins
+// p' = c + 8 m and 192 + c + 8 m, m < 8.  Their pair indices run on from
+// ci.z + c (lower run, p' >= 1; p' = 0 is pair ci.y) and ci.x + c (upper run),
+// so they step by one tile every two m.  Every lane loads a valid address;
+// bins that are not retained are zeroed when the column is transformed.
+struct S4Gather {
+  cpx<float> lo[8], hi[8];
+  int4 ci;
+};
+__device__ __forceinline__ void s4_gather(const cpx<float>* __restrict__ Sk, long long ts, const int* __restrict__ cols,
+                                          int q, int c, S4Gather& g) {
+  g.ci = reinterpret_cast<const int4*>(cols)[q];
+  const int4 ci = g.ci;
+  const bool valid = (ci.w >> 4) & 1;
+  const bool first_hi = c >= ((ci.w >> 2) & 3);  // upper bin p = 192 + c retained
+  const long long oL[2] = {s4_off(ci.z + c, ts), s4_off(ci.z + c + 8, ts)};
+  const long long oH[2] = {s4_off(ci.x + c, ts), s4_off(ci.x + c + 8, ts)};
+  const long long oL0 = c == 0 ? s4_off(ci.y, ts) : oL[0];
+#pragma unroll
+  for (int m = 0; m < 8; m++) {
+    const long long j = (long long)(m >> 1) * ts;
+    const bool ok3 = valid && (m != 0 || first_hi);
+    g.lo[m] = Sk[(m == 0 ? oL0 : oL[m & 1]) + j];
+    g.hi[m] = Sk[ok3 ? oH[m & 1] + j : 0];
+  }
+}
+
 // Column phase of inverse slice SL (rows j = 4 j' + SL; a compile-time
 // constant, so that the radix-4 step takes no branches): 8 lanes per column
 // q = 2 cq + odd for all 256 q, odd q first (kept in registers, godd), then
 // even q into the LDS block; a column's 64 LDS words serve as its exchange
-// slots.
+// slots.  The next column's spectra are requested before the current one is
+// transformed.
 template <int SL>
 __device__ __forceinline__ void s4_cols_inverse(const cpx<float>* __restrict__ Sk, size_t tile_stride,
                                                 const int* __restrict__ cols, float scale, int so3, cpx<float>* G,
                                                 const cpx<float>* tws, int t, cpx<float> (&godd)[2][8]) {
   typedef float T;
   constexpr int M = 2 * S4_N - 1;
+  const long long ts = (long long)tile_stride;
+  S4Gather gs[2];
+  s4_gather(Sk, ts, cols, 2 * (t >> 3) + 1, t & 7, gs[0]);
 #pragma unroll
   for (int r = 0; r < 4; r++) {
-    // a column's loads stay behind the previous column's transform (register budget)
-    __builtin_amdgcn_sched_barrier(0);
     const int odd = r < 2 ? 1 : 0;
     const int c = s4_opaque_lt<8>(t);  // addresses formed per column (register budget)
     const int cq = s4_opaque_lt<64>(t >> 3) + 64 * (r & 1);
-    const int q = 2 * cq + odd;
-    const int4 ci = reinterpret_cast<const int4*>(cols)[q];
+    if (r < 3) {
+      const int rn = r + 1;
+      s4_gather(Sk, ts, cols, 2 * (s4_opaque_lt<64>(t >> 3) + 64 * (rn & 1)) + (rn < 2 ? 1 : 0), c, gs[rn & 1]);
+    }
+    const S4Gather& g = gs[r & 1];
+    const int4 ci = g.ci;
     // the conjugate phase times the scale: the exponent (3 p + e0) mod 4 is
     // (3 c + e0) mod 4 for every bin p = c + 8 m (+ 192) of this lane
     const cpx<T> rho = s4_ipow((4 - ((3 * c + ci.w) & 3)) & 3, scale);
-    // bins p' = c + 8 m and 192 + c + 8 m; their pair indices run on from
-    // ci.z + c (lower, p' >= 1; p' = 0 is pair ci.y) and ci.x + c (upper),
-    // so they step by one tile every two m
     const bool valid = (ci.w >> 4) & 1;
-    const bool first_hi = c >= ((ci.w >> 2) & 3);  // upper bin p = 192 + c retained
-    const long long ts = (long long)tile_stride;
-    const long long oL[2] = {s4_off(ci.z + c, ts), s4_off(ci.z + c + 8, ts)};
-    const long long oH[2] = {s4_off(ci.x + c, ts), s4_off(ci.x + c + 8, ts)};
-    const long long oL0 = c == 0 ? (long long)s4_off(ci.y, ts) : oL[0];
+    const bool first_hi = c >= ((ci.w >> 2) & 3);
     const cpx<T> zero = {T(0), T(0)};
     cpx<T> x[8];  // p' = c + 8 m
 #pragma unroll
     for (int m = 0; m < 8; m++) {
       const int p0 = c + 8 * m;
-      const long long j = (long long)(m >> 1) * ts;
-      // every lane loads a valid address; bins not retained become zero
       const bool ok3 = valid && (m != 0 || first_hi);
-      const cpx<T> l0 = Sk[(m == 0 ? oL0 : oL[m & 1]) + j];
-      const cpx<T> l3 = Sk[ok3 ? oH[m & 1] + j : 0];
-      const cpx<T> v0 = valid ? cmul(l0, rho) : zero;
-      const cpx<T> v3 = ok3 ? cmul(l3, rho) : zero;
+      const cpx<T> v0 = valid ? cmul(g.lo[m], rho) : zero;
+      const cpx<T> v3 = ok3 ? cmul(g.hi[m], rho) : zero;
       // i^SL on the upper bins, then w256^{-p' SL}
       cpx<T> u;
       if constexpr (SL == 0) u = cadd(v0, v3);
