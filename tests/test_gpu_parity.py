@@ -199,9 +199,10 @@ def test_full_size_b64_batch32_sampled(dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_max_bandlimit_b128_sampled(dtype):
-    """B = 128 (largest supported; 256^3 grid, two-pass ring transforms over
-    several chunks of rings): round trip, sampled forward of non-bandlimited
-    samples, sampled inverse and adjoint points, all against the oracle."""
+    """B = 128 (largest supported; 256^3 grid: FP32 rings in one pass, four
+    workgroups per ring; FP64 rings in two passes over chunks of rings):
+    round trip, sampled forward of non-bandlimited samples, sampled inverse
+    and adjoint points, all against the oracle."""
     B, batch = 128, 2
     rng = np.random.default_rng(128)
     plan = su2.Plan(B, batch, dtype)
@@ -223,6 +224,36 @@ def test_max_bandlimit_b128_sampled(dtype):
     fu = _host(plan.forward(_dev(xu)))
     sel = rng.choice(oracle.num_coeffs(B), 12, replace=False)
     _check(fu[1][sel], oracle.forward(B, xu[1], sel), TOL[dtype], f"forward B=128 {dtype}")
+
+
+def test_b128_fp32_every_output_against_fp64():
+    """Every output of the FP32 B = 128 chain (one-pass ring kernels, four
+    workgroups per ring, two per CU) against the FP64 chain (two-pass ring
+    kernels: separate code), on a batch of 3 (the ring grid then ends in the
+    middle of an XCD's share): all forward coefficients of non-bandlimited
+    samples and all inverse and adjoint samples, at the c64 bar.  The FP64
+    chain's own B = 128 oracle checks are test_max_bandlimit_b128_sampled."""
+    B, batch = 128, 3
+    # FP32 inputs, upcast exactly for the FP64 chain
+    x32 = synth.samples_uniform(B, batch, seed=1280, dtype=np.complex64)
+    c32 = synth.coeffs(B, batch, seed=1281, dtype=np.complex64)
+    p64 = su2.Plan(B, batch, "c128")
+    ref_f = _host(p64.forward(_dev(x32.astype(np.complex128))))
+    ref_i = _host(p64.inverse(_dev(c32.astype(np.complex128))))
+    ref_a = _host(p64.adjoint(_dev(c32.astype(np.complex128))))
+    p64.close()
+    p32 = su2.Plan(B, batch, "c64")
+    got_f = _host(p32.forward(_dev(x32)))
+    for b in range(batch):
+        _check(got_f[b], ref_f[b], TOL["c64"], f"B=128 c64 vs c128 forward s{b}")
+    got_i = _host(p32.inverse(_dev(c32)))
+    for b in range(batch):
+        _check(got_i[b], ref_i[b], TOL["c64"], f"B=128 c64 vs c128 inverse s{b}")
+    del got_i, ref_i
+    got_a = _host(p32.adjoint(_dev(c32)))
+    for b in range(batch):
+        _check(got_a[b], ref_a[b], TOL["c64"], f"B=128 c64 vs c128 adjoint s{b}")
+    p32.close()
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
