@@ -2,7 +2,8 @@
  * su2fft -- separated Fourier transform on SU(2) for MI355X (gfx950).
  *
  * C ABI.  No C++ or framework types cross it: plain integers, plain host or
- * device pointers, and the HIP stream handle as an opaque pointer.
+ * device pointers, and the HIP stream handle (hipStream_t, itself an opaque
+ * pointer; the header includes HIP's C runtime API header for its type).
  *
  * The transform (Section 3, Definition 3.4 and the Peter-Weyl series; the
  * separation of Section 4, Proposition 4.2, with the contraction over beta of
@@ -49,6 +50,8 @@
 
 #include <stddef.h>
 #include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -159,17 +162,17 @@ su2_status_t su2_plan_destroy(su2_plan_t plan);
  * Proposition 4.2: a 2D FFT over (alpha, gamma) on every beta ring, then the
  * contraction over beta for every (m, n) pair.
  * d_samples: device, batch x N^3 complex; d_coeffs: device, batch x C(B) complex. */
-su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, hipStream_t stream);
 
 /* Inverse transform (synthesis), the Peter-Weyl series of Section 3 evaluated
  * as the transpose chain of the forward: contraction over l per (m, n), then an
  * inverse 2D FFT per ring.  d_coeffs: device input; d_samples: device output. */
-su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, hipStream_t stream);
 
 /* Adjoint (conjugate transpose) of su2_forward: the inverse chain with the
  * weight W_k in place of (2l+1).  This is the backward map of the forward
  * transform for gradient computation. */
-su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, hipStream_t stream);
 
 /* su2_forward for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.  Same
@@ -193,7 +196,7 @@ su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples,
  * needs clearing: a call reads only values it wrote itself.  The scratch keeps
  * the last call's ring spectra. */
 #define SU2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
-su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, hipStream_t stream);
 
 /* The kernels behind su2_forward / su2_inverse / su2_adjoint, one at a time,
  * for timing and profiling a single stage.  The intermediate ring spectra stay
@@ -214,7 +217,7 @@ typedef enum {
   SU2_STAGE_BETA_ADJOINT = 4,
   SU2_STAGE_RING_ADJOINT = 5
 } su2_stage_t;
-su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream);
+su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, hipStream_t stream);
 
 /* Sizes and indexing (pure host functions, no device needed).
  * su2_num_samples: points of the grid of Definition 4.1 (read with N = 2B
@@ -298,7 +301,7 @@ su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t*
  * stored products leave the FP32 range near the poles).  Single-B plans with
  * B <= 64 (SU2_ERR_UNSUPPORTED above); SU2_ERR_INVALID_VALUE for bad depth or
  * block, mixed plans or null pointers. */
-su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream);
+su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, hipStream_t stream);
 
 /* Diagnostic: copy to host the FP64 Wigner-d table a single-B plan generated
  * for the pair (m, n) (doubled indices): host_out[k * L + i] = d^{l0+i}_{nm}(beta_k),

@@ -127,30 +127,30 @@ using namespace su2;
 
 extern "C" {
 
-su2_status_t su2_calib_copy(const void* d_src, void* d_dst, int64_t bytes, void* stream) {
+su2_status_t su2_calib_copy(const void* d_src, void* d_dst, int64_t bytes, hipStream_t stream) {
   if (!d_src || !d_dst || bytes <= 0 || bytes % 16 || !aligned16(d_src) || !aligned16(d_dst))
     return SU2_ERR_INVALID_VALUE;
   const uintptr_t s = (uintptr_t)d_src, d = (uintptr_t)d_dst;
   if (s < d + (uintptr_t)bytes && d < s + (uintptr_t)bytes) return SU2_ERR_INVALID_VALUE;  // overlap
   const long long n = bytes / 16;
-  calib_copy_kernel<<<stream_blocks(n), CALIB_NT, 0, (hipStream_t)stream>>>(
+  calib_copy_kernel<<<stream_blocks(n), CALIB_NT, 0, stream>>>(
       static_cast<const calib_f32x4*>(d_src), static_cast<calib_f32x4*>(d_dst), n);
   return launch_status();
 }
 
-su2_status_t su2_calib_fill(void* d_dst, int64_t bytes, float value, void* stream) {
+su2_status_t su2_calib_fill(void* d_dst, int64_t bytes, float value, hipStream_t stream) {
   if (!d_dst || bytes <= 0 || bytes % 16 || !aligned16(d_dst)) return SU2_ERR_INVALID_VALUE;
   const long long n = bytes / 16;
-  calib_fill_kernel<<<stream_blocks(n), CALIB_NT, 0, (hipStream_t)stream>>>(static_cast<calib_f32x4*>(d_dst), n, value);
+  calib_fill_kernel<<<stream_blocks(n), CALIB_NT, 0, stream>>>(static_cast<calib_f32x4*>(d_dst), n, value);
   return launch_status();
 }
 
 su2_status_t su2_calib_mfma(int32_t kind, int32_t workgroups, int32_t iters, float* d_out, double* flops,
-                            void* stream) {
+                            hipStream_t stream) {
   if (kind < 0 || kind > 2 || workgroups < 1 || workgroups > (1 << 20) || iters < 1 || iters > (1 << 24) ||
       !d_out || !aligned16(d_out))
     return SU2_ERR_INVALID_VALUE;
-  const hipStream_t st = (hipStream_t)stream;
+  const hipStream_t st = stream;
   if (kind == 0) calib_mfma_kernel<0><<<workgroups, CALIB_NT, 0, st>>>(iters, d_out);
   else if (kind == 1) calib_mfma_kernel<1><<<workgroups, CALIB_NT, 0, st>>>(iters, d_out);
   else calib_mfma_kernel<2><<<workgroups, CALIB_NT, 0, st>>>(iters, d_out);

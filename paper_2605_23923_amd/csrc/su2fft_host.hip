@@ -863,25 +863,25 @@ su2_status_t su2_plan_info(su2_plan_t plan, int32_t* B, int32_t* batch, int32_t*
   return SU2_OK;
 }
 
-su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+su2_status_t su2_forward(su2_plan_t plan, const void* d_samples, void* d_coeffs, hipStream_t stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
-  if (plan->mixed) return run_mixed(plan, 0, d_samples, d_coeffs, (hipStream_t)stream);
-  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, (hipStream_t)stream);
+  if (plan->mixed) return run_mixed(plan, 0, d_samples, d_coeffs, stream);
+  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, stream);
 }
 
-su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+su2_status_t su2_inverse(su2_plan_t plan, const void* d_coeffs, void* d_samples, hipStream_t stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
-  if (plan->mixed) return run_mixed(plan, 1, d_coeffs, d_samples, (hipStream_t)stream);
-  return run_pair(plan, SU2_STAGE_BETA_INVERSE, SU2_STAGE_RING_INVERSE, d_coeffs, d_samples, (hipStream_t)stream);
+  if (plan->mixed) return run_mixed(plan, 1, d_coeffs, d_samples, stream);
+  return run_pair(plan, SU2_STAGE_BETA_INVERSE, SU2_STAGE_RING_INVERSE, d_coeffs, d_samples, stream);
 }
 
-su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+su2_status_t su2_adjoint(su2_plan_t plan, const void* d_coeffs, void* d_samples, hipStream_t stream) {
   if (!plan || !d_samples || !d_coeffs) return SU2_ERR_INVALID_VALUE;
-  if (plan->mixed) return run_mixed(plan, 2, d_coeffs, d_samples, (hipStream_t)stream);
-  return run_pair(plan, SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT, d_coeffs, d_samples, (hipStream_t)stream);
+  if (plan->mixed) return run_mixed(plan, 2, d_coeffs, d_samples, stream);
+  return run_pair(plan, SU2_STAGE_BETA_ADJOINT, SU2_STAGE_RING_ADJOINT, d_coeffs, d_samples, stream);
 }
 
-su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d_coeffs, hipStream_t stream) {
   if (!plan || !d_samples || !d_coeffs || plan->mixed) return SU2_ERR_INVALID_VALUE;
   // the two-pass forward ring (N = 256 in FP64) keeps a second plan-owned buffer
   if (plan->large && !plan->sliced) return SU2_ERR_UNSUPPORTED;
@@ -893,16 +893,16 @@ su2_status_t su2_forward_noalloc(su2_plan_t plan, const void* d_samples, void* d
   if (dev != plan->device) return SU2_ERR_INVALID_VALUE;
   void* S = nullptr;
   if ((e = scratch_address(dev, &S)) != hipSuccess) return hip_fail(e);
-  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, (hipStream_t)stream, S);
+  return run_pair(plan, SU2_STAGE_RING_FORWARD, SU2_STAGE_BETA_FORWARD, d_samples, d_coeffs, stream, S);
 }
 
-su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, void* stream) {
+su2_status_t su2_run_stage(su2_plan_t plan, su2_stage_t stage, const void* in, void* out, hipStream_t stream) {
   if (!plan || plan->mixed) return SU2_ERR_INVALID_VALUE;
   if ((int)stage < 0 || (int)stage > (int)SU2_STAGE_RING_ADJOINT) return SU2_ERR_INVALID_VALUE;
   const bool needs_in = stage == SU2_STAGE_RING_FORWARD || stage == SU2_STAGE_BETA_INVERSE ||
                         stage == SU2_STAGE_BETA_ADJOINT;
   if (needs_in ? !in : !out) return SU2_ERR_INVALID_VALUE;
-  return run_stage(plan, stage, in, out, (hipStream_t)stream);
+  return run_stage(plan, stage, in, out, stream);
 }
 
 su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, double* host_out, int32_t* L) {
@@ -926,7 +926,7 @@ su2_status_t su2_plan_dtable(su2_plan_t plan, int32_t two_m, int32_t two_n, doub
   return SU2_ERR_INVALID_VALUE;
 }
 
-su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, void* stream) {
+su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t block, void* d_coeffs, hipStream_t stream) {
   if (!plan || plan->mixed || plan->real || plan->so3 || !d_coeffs) return SU2_ERR_INVALID_VALUE;
   if (depth != 1 && depth != 2) return SU2_ERR_INVALID_VALUE;
   if (depth == 2 && block != 2 && block != 4 && block != 8 && block != 16) return SU2_ERR_INVALID_VALUE;
@@ -934,10 +934,10 @@ su2_status_t su2_beta_forward_shifted(su2_plan_t plan, int32_t depth, int32_t bl
   hipError_t e;
   if (plan->dtype == SU2_C128)
     e = launch_beta_forward_shifted<double>(otf_params<double>(plan, 0), (const cpx<double>*)plan->d_S,
-                                            (cpx<double>*)d_coeffs, depth, block, (hipStream_t)stream);
+                                            (cpx<double>*)d_coeffs, depth, block, stream);
   else
     e = launch_beta_forward_shifted<float>(otf_params<float>(plan, 0), (const cpx<float>*)plan->d_S,
-                                           (cpx<float>*)d_coeffs, depth, block, (hipStream_t)stream);
+                                           (cpx<float>*)d_coeffs, depth, block, stream);
   return e == hipSuccess ? SU2_OK : hip_fail(e);
 }
 
