@@ -122,6 +122,20 @@ def algorithmic_bytes(stage: str, B: int, batch: int, mode: str) -> int:
     return batch * (spec + coef) + table_bytes(B, mode)
 
 
+def step_bytes(counts: dict, mode: str) -> int:
+    """Algorithmic HBM bytes of one forward + inverse + adjoint step over a
+    batch given as {bandlimit: signals}: each direction is a ring stage and a
+    contraction stage per bandlimit (the table read once per stage and B)."""
+    per_dir = sum(algorithmic_bytes("ring_forward", B, n, mode) + algorithmic_bytes("beta_forward", B, n, mode)
+                  for B, n in counts.items())
+    return 3 * per_dir
+
+
+def step_hbm_frac(counts: dict, mode: str, ms_per_step: float) -> float:
+    """step_bytes over the step time, against the 8 TB/s peak."""
+    return round(step_bytes(counts, mode) / (ms_per_step * 1e-3) / HBM_PEAK, 4)
+
+
 def useful_flops(stage: str, B: int, batch: int, mode: str = "c64") -> float:
     """Useful real flops of a beta contraction: 4 per (l, m, n, k, signal)."""
     N = 2 * B
@@ -350,6 +364,9 @@ def secondary_configs(steps: int, warmup: int):
     c = torch.from_numpy(((rng.standard_normal(nc) + 1j * rng.standard_normal(nc)) / np.sqrt(2)).astype(np.complex64)).to("cuda")
     out["mixed_320_signals_c64"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup, len(Bs))
     out["mixed_320_signals_c64"]["signals"] = "256 x B=32 + 64 x B in {16,24,32,48,64} (seed 33)"
+    counts = {b: Bs.count(b) for b in sorted(set(Bs))}
+    out["mixed_320_signals_c64"]["step_hbm_frac"] = step_hbm_frac(counts, "c64",
+                                                                  out["mixed_320_signals_c64"]["ms_per_step"])
     # the same step with the autotuner off (default tile shapes, 2 workgroups per CU)
     prev = os.environ.get("SU2_AUTOTUNE")
     os.environ["SU2_AUTOTUNE"] = "0"
@@ -382,12 +399,15 @@ def secondary_configs(steps: int, warmup: int):
                                                          x, c, max(2, steps // 5), 1, batch)
     # the same shape with the plain FP32 contraction (stored table), beside the split-BF16 one
     out["b128_batch16_c64"] = run_whole(lambda: su2.Plan(B, batch, "c64"), x, c, max(2, steps // 5), 1, batch)
+    for key, m in (("b128_batch16_c64_bf16x3", "c64_bf16x3"), ("b128_batch16_c64", "c64")):
+        out[key]["step_hbm_frac"] = step_hbm_frac({B: batch}, m, out[key]["ms_per_step"])
     del x, c
     torch.cuda.empty_cache()
     # and in FP64 throughout
     x = torch.from_numpy(synth.samples_uniform(B, batch, seed=4, dtype=np.complex128)).to("cuda")
     c = torch.from_numpy(synth.coeffs(B, batch, seed=4, dtype=np.complex128)).to("cuda")
     out["b128_batch16_c128"] = run_whole(lambda: su2.Plan(B, batch, "c128"), x, c, max(2, steps // 5), 1, batch)
+    out["b128_batch16_c128"]["step_hbm_frac"] = step_hbm_frac({B: batch}, "c128", out["b128_batch16_c128"]["ms_per_step"])
     del x, c
     torch.cuda.empty_cache()
     return out

@@ -85,3 +85,16 @@ def test_shifted_depth1_flops():
     # per (coefficient, node, signal), twice the table form's count
     assert bench.shifted_depth1_flops(64, 1) == 2 * bench.useful_flops("beta_forward", 64, 1) == 8 * 128 * 89440
     assert bench.shifted_depth1_flops(64, 32) == 32 * bench.shifted_depth1_flops(64, 1)
+
+
+def test_step_bytes_adds_the_stages_of_every_bandlimit():
+    """A step is forward + inverse + adjoint: three ring stages and three
+    contraction stages per bandlimit, each at the bandlimit's own sizes."""
+    one = {64: 32}
+    per_dir = bench.algorithmic_bytes("ring_forward", 64, 32, "c64") + bench.algorithmic_bytes("beta_forward", 64, 32, "c64")
+    assert bench.step_bytes(one, "c64") == 3 * per_dir
+    mixed = {16: 3, 32: 5, 64: 2}
+    assert bench.step_bytes(mixed, "c64") == sum(bench.step_bytes({b: n}, "c64") for b, n in mixed.items())
+    # 1 ms per step at exactly the peak's bytes is a fraction of 1
+    ms = bench.step_bytes(one, "c64") / bench.HBM_PEAK * 1e3
+    assert abs(bench.step_hbm_frac(one, "c64", ms) - 1.0) < 1e-3
