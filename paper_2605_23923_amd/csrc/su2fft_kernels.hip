@@ -97,7 +97,7 @@ __global__ __launch_bounds__(FAST_NT, fast_waves_per_simd<T>()) void ring_fast_w
 }
 
 template <class T, bool FWD>
-__global__ __launch_bounds__(FFT_THREADS) void ring_generic_worklist_kernel(const WorkItem* __restrict__ items, int n,
+__global__ __launch_bounds__(GENERIC_NT) void ring_generic_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             const cpx<T>* __restrict__ in,
                                                                             cpx<T>* __restrict__ out, int dir) {
@@ -106,11 +106,11 @@ __global__ __launch_bounds__(FFT_THREADS) void ring_generic_worklist_kernel(cons
     const WorkItem w = items[it];
     const RingParams<T>& p = groups[w.g].rp[dir];
     if constexpr (FWD)
-      ring_forward_body<T>(in, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, groups[w.g].S, p, w.a, w.b,
-                           smem);
+      ring_forward_any<T>(in, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, groups[w.g].S, p, w.a, w.b,
+                          smem);
     else
-      ring_inverse_body<T>(groups[w.g].S, out, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b,
-                           smem);
+      ring_inverse_any<T>(groups[w.g].S, out, ring_offset(p.soff, w.a, p.N) + (size_t)w.b * p.N * p.N, p, w.a, w.b,
+                          smem);
     __syncthreads();
   }
 }
@@ -339,7 +339,7 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
       if (ms->n_ringg > 0) {
         args[0] = (void*)&ms->d_ringg;
         args[1] = (void*)&ms->n_ringg;
-        if ((e = hipLaunchKernel(ringg_kernel_ptr<T>(which == 0), grid_of(ms->n_ringg), dim3(FFT_THREADS), args,
+        if ((e = hipLaunchKernel(ringg_kernel_ptr<T>(which == 0), grid_of(ms->n_ringg), dim3(GENERIC_NT), args,
                                  ms->smem_ringg, sg)) != hipSuccess)
           return e;
       }

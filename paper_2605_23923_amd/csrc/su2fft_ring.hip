@@ -24,6 +24,9 @@
 
 namespace su2 {
 
+// threads per workgroup of the generic ring kernels (one ring per workgroup)
+constexpr int GENERIC_NT = 512;
+
 template <class T, int R, int SIGN>
 __device__ __forceinline__ void dft_small(cpx<T>* a) {
   if constexpr (R == 2) {
@@ -218,13 +221,169 @@ __device__ void ring_forward_body(const cpx<T>* __restrict__ xs, size_t x0, cpx<
   }
 }
 
+// ---- compile-time forms for the 3-smooth sizes N = 48 and N = 96 ----
+//
+// The same passes as run_dif / run_dit, and the same bodies for rings held
+// whole in LDS (split 1), with every size, radix, stride and index known to
+// the compiler: the per-butterfly divisions and remainders by run-time sizes
+// of the forms above become constants.  The radix sequence is radix_plan's
+// (8s, then 4 or 2, then 3s), which the host's bin positions assume.
+
+constexpr int ct_nrad(int L) {
+  int p2 = 0, p3 = 0;
+  while (L % 2 == 0) { L /= 2; p2++; }
+  while (L % 3 == 0) { L /= 3; p3++; }
+  return p2 / 3 + (p2 % 3 ? 1 : 0) + p3;
+}
+constexpr int ct_rad(int L, int s) {
+  int p2 = 0, p3 = 0;
+  while (L % 2 == 0) { L /= 2; p2++; }
+  while (L % 3 == 0) { L /= 3; p3++; }
+  const int n8 = p2 / 3, n42 = p2 % 3 ? 1 : 0;
+  if (s < n8) return 8;
+  if (s < n8 + n42) return p2 % 3 == 2 ? 4 : 2;
+  return 3;
+}
+// sub-transform length entering pass s
+constexpr int ct_ls(int L, int s) {
+  int Ls = L;
+  for (int t = 0; t < s; t++) Ls /= ct_rad(L, t);
+  return Ls;
+}
+
+template <class T, int R, int NLINES, int L, int LS, int ES, int LSTR, bool LINE_FAST, int TWON, bool DIF>
+__device__ __forceinline__ void pass_ct(cpx<T>* X, const cpx<T>* tw) {
+  constexpr int M = LS / R, PER_LINE = L / R, TOTAL = NLINES * PER_LINE, TSTEP = TWON / LS;
+  for (int bf = threadIdx.x; bf < TOTAL; bf += GENERIC_NT) {
+    int line, u;
+    if constexpr (LINE_FAST) {
+      line = bf % NLINES;
+      u = bf / NLINES;
+    } else {
+      line = bf / PER_LINE;
+      u = bf - line * PER_LINE;
+    }
+    const int block = u / M, off = u - block * M;
+    const int base = line * LSTR + (block * LS + off) * ES;
+    cpx<T> a[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) a[i] = X[base + i * M * ES];
+    if constexpr (DIF) {
+      dft_small<T, R, 1>(a);
+#pragma unroll
+      for (int i = 1; i < R; i++) a[i] = cmul(a[i], tw[(i * off * TSTEP) % TWON]);
+    } else {
+#pragma unroll
+      for (int i = 1; i < R; i++) a[i] = cmulc(a[i], tw[(i * off * TSTEP) % TWON]);
+      dft_small<T, R, -1>(a);
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++) X[base + i * M * ES] = a[i];
+  }
+}
+
+template <class T, int NLINES, int L, int ES, int LSTR, bool LINE_FAST, int TWON, int S = 0>
+__device__ __forceinline__ void run_dif_ct(cpx<T>* X, const cpx<T>* tw) {
+  if constexpr (S < ct_nrad(L)) {
+    pass_ct<T, ct_rad(L, S), NLINES, L, ct_ls(L, S), ES, LSTR, LINE_FAST, TWON, true>(X, tw);
+    __syncthreads();
+    run_dif_ct<T, NLINES, L, ES, LSTR, LINE_FAST, TWON, S + 1>(X, tw);
+  }
+}
+
+template <class T, int NLINES, int L, int ES, int LSTR, bool LINE_FAST, int TWON, int S = ct_nrad(L) - 1>
+__device__ __forceinline__ void run_dit_ct(cpx<T>* X, const cpx<T>* tw) {
+  if constexpr (S >= 0) {
+    pass_ct<T, ct_rad(L, S), NLINES, L, ct_ls(L, S), ES, LSTR, LINE_FAST, TWON, false>(X, tw);
+    __syncthreads();
+    run_dit_ct<T, NLINES, L, ES, LSTR, LINE_FAST, TWON, S - 1>(X, tw);
+  }
+}
+
+// ring_forward_body for N held whole in LDS (split 1); N a compile-time size
+template <class T, int N>
+__device__ void ring_forward_body_ct(const cpx<T>* __restrict__ xs, size_t x0, cpx<T>* __restrict__ S,
+                                     const RingParams<T>& p, int b, int k, unsigned char* smem_raw) {
+  constexpr int twoN = 2 * N;
+  cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = X + N * N;
+  for (int t = threadIdx.x; t < twoN; t += GENERIC_NT) tw[t] = p.tw[t];
+  const T Wk = p.W[k];
+  __syncthreads();
+  for (int e = threadIdx.x; e < N * N; e += GENERIC_NT) X[e] = ring_sample(xs, x0 + e, p.real_io);
+  __syncthreads();
+  run_dif_ct<T, N, N, 1, N, false, twoN>(X, tw);  // gamma: rows j
+  for (int e = threadIdx.x; e < N * N; e += GENERIC_NT) {
+    const int j = e / N, c = e - j * N;
+    const int q = p.colq[c];
+    if ((q & 1) && !p.so3) X[e] = cmul(X[e], tw[j]);
+  }
+  __syncthreads();
+  run_dif_ct<T, N, N, N, 1, true, twoN>(X, tw);  // alpha: columns
+  for (int pi = p.cls_begin[0] + threadIdx.x; pi < p.cls_end[0]; pi += GENERIC_NT) {
+    cpx<T> v = cscale(cmul(X[p.fftpos[pi]], p.rho[pi]), Wk);
+    const int tile = pi / PT;
+    S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)] = v;
+  }
+}
+
+// ring_inverse_body for N held whole in LDS (split 1); N a compile-time size
+template <class T, int N>
+__device__ void ring_inverse_body_ct(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xs, size_t x0,
+                                     const RingParams<T>& p, int b, int k, unsigned char* smem_raw) {
+  constexpr int twoN = 2 * N;
+  cpx<T>* X = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = X + N * N;
+  for (int t = threadIdx.x; t < twoN; t += GENERIC_NT) tw[t] = p.tw[t];
+  const T scale = p.adjoint ? p.W[k] : T(1);
+  __syncthreads();
+  for (int e = threadIdx.x; e < N * N; e += GENERIC_NT) X[e] = {T(0), T(0)};
+  __syncthreads();
+  for (int pi = p.cls_begin[0] + threadIdx.x; pi < p.cls_end[0]; pi += GENERIC_NT) {
+    const int tile = pi / PT;
+    cpx<T> v = S[(((size_t)tile * N + k) * p.batch + b) * PT + (pi - tile * PT)];
+    X[p.fftpos[pi]] = cscale(cmulc(v, p.rho[pi]), scale);
+  }
+  __syncthreads();
+  run_dit_ct<T, N, N, N, 1, true, twoN>(X, tw);  // alpha: columns
+  for (int e = threadIdx.x; e < N * N; e += GENERIC_NT) {
+    const int j = e / N, c = e - j * N;
+    const int q = p.colq[c];
+    if ((q & 1) && !p.so3) X[e] = cmulc(X[e], tw[j]);
+  }
+  __syncthreads();
+  run_dit_ct<T, N, N, 1, N, false, twoN>(X, tw);  // gamma: rows j
+  T* xr = reinterpret_cast<T*>(xs);
+  for (int e = threadIdx.x; e < N * N; e += GENERIC_NT) {
+    const size_t o = x0 + e;
+    if (p.real_io) xr[o] = X[e].re;
+    else xs[o] = X[e];
+  }
+}
+
+// the bodies above for the sizes they are built for, the run-time forms otherwise
 template <class T>
-__global__ __launch_bounds__(FFT_THREADS) void ring_forward_kernel(const cpx<T>* __restrict__ samples,
+__device__ __forceinline__ void ring_forward_any(const cpx<T>* __restrict__ xs, size_t x0, cpx<T>* __restrict__ S,
+                                                 const RingParams<T>& p, int b, int k, unsigned char* smem) {
+  if (p.split == 1 && p.N == 96) ring_forward_body_ct<T, 96>(xs, x0, S, p, b, k, smem);
+  else if (p.split == 1 && p.N == 48) ring_forward_body_ct<T, 48>(xs, x0, S, p, b, k, smem);
+  else ring_forward_body<T>(xs, x0, S, p, b, k, smem);
+}
+template <class T>
+__device__ __forceinline__ void ring_inverse_any(const cpx<T>* __restrict__ S, cpx<T>* __restrict__ xs, size_t x0,
+                                                 const RingParams<T>& p, int b, int k, unsigned char* smem) {
+  if (p.split == 1 && p.N == 96) ring_inverse_body_ct<T, 96>(S, xs, x0, p, b, k, smem);
+  else if (p.split == 1 && p.N == 48) ring_inverse_body_ct<T, 48>(S, xs, x0, p, b, k, smem);
+  else ring_inverse_body<T>(S, xs, x0, p, b, k, smem);
+}
+
+template <class T>
+__global__ __launch_bounds__(GENERIC_NT) void ring_forward_kernel(const cpx<T>* __restrict__ samples,
                                                                    cpx<T>* __restrict__ S, RingParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring = blockIdx.x;
   const int b = ring / p.N, k = ring - b * p.N;
-  ring_forward_body<T>(samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, S, p, b, k, smem_raw);
+  ring_forward_any<T>(samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, S, p, b, k, smem_raw);
 }
 
 // The ring's N x N output block starts at element x0 of the sample buffer xs
@@ -278,12 +437,12 @@ __device__ void ring_inverse_body(const cpx<T>* __restrict__ S, cpx<T>* __restri
 }
 
 template <class T>
-__global__ __launch_bounds__(FFT_THREADS) void ring_inverse_kernel(const cpx<T>* __restrict__ S,
+__global__ __launch_bounds__(GENERIC_NT) void ring_inverse_kernel(const cpx<T>* __restrict__ S,
                                                                    cpx<T>* __restrict__ samples, RingParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ring = blockIdx.x;
   const int b = ring / p.N, k = ring - b * p.N;
-  ring_inverse_body<T>(S, samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, p, b, k, smem_raw);
+  ring_inverse_any<T>(S, samples, ring_offset(p.soff, b, p.N) + (size_t)k * p.N * p.N, p, b, k, smem_raw);
 }
 
 template <class T>
@@ -297,7 +456,7 @@ hipError_t launch_ring_forward(const RingParams<T>& p, const cpx<T>* samples, cp
   hipError_t e = hipFuncSetAttribute((const void*)ring_forward_kernel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ring_forward_kernel<T>, dim3(p.batch * p.N), dim3(FFT_THREADS), smem, s, samples, S, p);
+  hipLaunchKernelGGL(ring_forward_kernel<T>, dim3(p.batch * p.N), dim3(GENERIC_NT), smem, s, samples, S, p);
   return hipGetLastError();
 }
 
@@ -307,7 +466,7 @@ hipError_t launch_ring_inverse(const RingParams<T>& p, const cpx<T>* S, cpx<T>* 
   hipError_t e = hipFuncSetAttribute((const void*)ring_inverse_kernel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ring_inverse_kernel<T>, dim3(p.batch * p.N), dim3(FFT_THREADS), smem, s, S, samples, p);
+  hipLaunchKernelGGL(ring_inverse_kernel<T>, dim3(p.batch * p.N), dim3(GENERIC_NT), smem, s, S, samples, p);
   return hipGetLastError();
 }
 
