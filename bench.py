@@ -32,8 +32,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"c128": 78.6e12, "c64": 157.3e12, "c64_bf16x3": 2.5e15}   # dense FP64 / FP32 / BF16
 DTYPE_NAME = {"c128": "f64", "c64": "f32", "c64_bf16x3": "f32+bf16x3"}
-# (B, batch) of the shapes bench.py can time stage by stage
-WORKLOADS = {"b64_batch32": (64, 32), "b128_batch16": (128, 16)}
+# (B, batch) of the shapes bench.py can time on their own: stage by stage, or
+# (mixed_320: 320 signals of mixed bandlimits) the whole step
+WORKLOADS = {"b64_batch32": (64, 32), "b128_batch16": (128, 16), "mixed_320": (None, 320)}
 STAGES = ["ring_forward", "beta_forward", "beta_inverse", "ring_inverse", "beta_adjoint", "ring_adjoint"]
 # a mode is a precision ("c128", "c64", "c64_bf16x3"), optionally with "_otf"
 # (Wigner-d values generated inside the contraction kernels instead of stored)
@@ -346,8 +347,10 @@ def shifted_forms(steps: int):
     return res
 
 
-def secondary_configs(steps: int, warmup: int):
-    """The other workload shapes, timed through the public calls."""
+def mixed_batch(steps: int, warmup: int, untuned: bool):
+    """The mixed-bandlimit step: 256 signals at B = 32 plus 64 with B from
+    {16, 24, 32, 48, 64}, FP32, one plan (autotuned; untuned: also with the
+    autotuner off)."""
     import numpy as np
     import torch
 
@@ -355,7 +358,6 @@ def secondary_configs(steps: int, warmup: int):
     import synth
 
     out = {}
-    # mixed bandlimits: 256 signals at B = 32 plus 64 with B from {16, 24, 32, 48, 64}, FP32, one plan
     Bs = [32] * 256 + synth.bandlimits_mixed(64, seed=33)
     ns = sum((2 * b) ** 3 for b in Bs)
     nc = sum(b * (b + 1) * (2 * b + 1) // 6 for b in Bs)
@@ -367,18 +369,32 @@ def secondary_configs(steps: int, warmup: int):
     counts = {b: Bs.count(b) for b in sorted(set(Bs))}
     out["mixed_320_signals_c64"]["step_hbm_frac"] = step_hbm_frac(counts, "c64",
                                                                   out["mixed_320_signals_c64"]["ms_per_step"])
-    # the same step with the autotuner off (default tile shapes, 2 workgroups per CU)
-    prev = os.environ.get("SU2_AUTOTUNE")
-    os.environ["SU2_AUTOTUNE"] = "0"
-    try:
-        out["mixed_320_signals_c64_untuned"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup, len(Bs))
-    finally:
-        if prev is None:
-            del os.environ["SU2_AUTOTUNE"]
-        else:
-            os.environ["SU2_AUTOTUNE"] = prev
+    if untuned:
+        # the same step with the autotuner off (default tile shapes, 2 workgroups per CU)
+        prev = os.environ.get("SU2_AUTOTUNE")
+        os.environ["SU2_AUTOTUNE"] = "0"
+        try:
+            out["mixed_320_signals_c64_untuned"] = run_whole(lambda: su2.MixedPlan(Bs, "c64"), x, c, steps, warmup,
+                                                             len(Bs))
+        finally:
+            if prev is None:
+                del os.environ["SU2_AUTOTUNE"]
+            else:
+                os.environ["SU2_AUTOTUNE"] = prev
     del x, c
     torch.cuda.empty_cache()
+    return out
+
+
+def secondary_configs(steps: int, warmup: int):
+    """The other workload shapes, timed through the public calls."""
+    import numpy as np
+    import torch
+
+    import paper_2605_23923_amd as su2
+    import synth
+
+    out = mixed_batch(steps, warmup, untuned=True)
     out["b64_batch32_beta_forward_shifted_c64"] = shifted_forms(steps)
     # one signal at B = 64 (the table, read once per launch, then outweighs the
     # ring spectra), forward and inverse timed separately, FP32 and FP64
@@ -530,7 +546,8 @@ def main():
     ap.add_argument("--workload", default="b64_batch32", choices=sorted(WORKLOADS),
                     help="b64_batch32 (default): the headline line.  b128_batch16: only the B=128 batch 16 shape "
                          "(256^3 grid), stage by stage for --mode and --other-modes, printed as one JSON object "
-                         "(for profiling; not the headline line)")
+                         "(for profiling; not the headline line).  mixed_320: only the mixed-bandlimit step "
+                         "(256 x B=32 + 64 x B in {16,24,32,48,64}, c64, autotuned), for profiling")
     ap.add_argument("--shifted-forms", action="store_true",
                     help="only time the forward contraction in its table and shifted-recurrence forms at B=64 "
                          "batch 32 (c64 plan), print that JSON object and exit")
@@ -565,6 +582,10 @@ def main():
     digest = source_digest()
     import paper_2605_23923_amd as su2
     su2.Plan(4, 1, "c64").close()   # loads the code objects, so that plan_ms is set-up alone
+    if args.workload == "mixed_320":
+        res = mixed_batch(args.steps, args.warmup, untuned=False)
+        print(json.dumps({"workload": args.workload, "steps": args.steps, **res, "source_digest": digest}), flush=True)
+        return
     if args.workload != "b64_batch32":
         modes = {}
         for m in [args.mode] + [m for m in args.other_modes.split(",") if m and m != args.mode]:

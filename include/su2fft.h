@@ -247,14 +247,16 @@ int64_t su2_so3_coeff_index(int32_t l, int32_t m, int32_t n);
  * or 2B not of the form 2^a 3^b). */
 su2_status_t su2_grid(int32_t B, double* alpha, double* beta, double* gamma, double* w_beta);
 
-/* Mixed plans: the persistent grid size, in workgroups per compute unit, that
- * the autotuner chose at plan creation for each of the four work-list kernels
+/* Mixed plans: the grid size, in workgroups per compute unit, that the
+ * autotuner chose at plan creation for each of the four work-list kernels
  * (ring forward, contraction forward, contraction inverse/adjoint, ring
- * inverse/adjoint), written to workgroups_per_cu[0..3].  The choice does not
- * change any result.  Setting the environment variable SU2_AUTOTUNE=0 before
- * plan creation skips the search (default 2 each); SU2_AUTOTUNE_CACHE names a
- * text file that caches choices across processes.  SU2_ERR_INVALID_VALUE for a
- * single-B plan. */
+ * inverse/adjoint), written to workgroups_per_cu[0..3]: one of 1, 2, 3, 4, 6,
+ * 8 (a persistent grid whose workgroups walk the task list in a static stride)
+ * or 0 (one workgroup per task).  The choice does not change any result.
+ * Environment, read at plan creation: SU2_AUTOTUNE=0 skips the search (default
+ * 2 each); SU2_AUTOTUNE_CACHE names a text file that caches choices across
+ * processes; SU2_GRID="a,b,c,d" pins the four values (each one of the above),
+ * over the search and the cache.  SU2_ERR_INVALID_VALUE for a single-B plan. */
 su2_status_t su2_plan_tuning(su2_plan_t plan, int32_t* workgroups_per_cu);
 
 /* Mixed plans: the contraction tile shapes the autotuner chose at plan

@@ -408,7 +408,8 @@ class MixedPlan(_PlanBase):
         self.coeff_shape = (self.total_coeffs,)
 
     def tuning(self):
-        """Workgroups per CU the autotuner chose for the four work-list kernels."""
+        """Workgroups per CU the autotuner chose for the four work-list kernels
+        (0: one workgroup per task)."""
         arr = (ctypes.c_int32 * 4)()
         _check(_load().su2_plan_tuning(self._handle, arr), "su2_plan_tuning")
         return list(arr)

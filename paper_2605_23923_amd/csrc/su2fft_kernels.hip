@@ -9,9 +9,10 @@
 // tile, signal tile) contraction task, each calling the same kernel bodies as
 // the single-B launches (so every signal's result is bit-identical to a
 // single-B plan's).  Tasks are ordered by decreasing cost and taken in a
-// static stride by a grid of `knob x CUs` workgroups; the knob of each kernel
-// is chosen by timing the candidates at plan creation (autotuner, cached per
-// device, mode and bandlimit mix, optionally on disk).  The two launches of a
+// static stride by a grid of `knob x CUs` workgroups, or (knob 0) one
+// workgroup per task; the knob of each kernel is chosen by timing the
+// candidates at plan creation (autotuner, cached per device, mode and
+// bandlimit mix, optionally on disk).  The two launches of a
 // call are captured once into a HIP graph per (direction, buffers, stream)
 // and replayed.
 #include <hip/hip_runtime.h>
@@ -244,7 +245,9 @@ struct MixedState {
   size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
   int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
   int num_cu = 0;
-  int knob[4] = {2, 2, 2, 2};       // workgroups per CU: ring forward, contraction forward, contraction inverse, ring inverse
+  // workgroups per CU (0: one per task): ring forward, contraction forward,
+  // contraction inverse, ring inverse
+  int knob[4] = {2, 2, 2, 2};
   // tile shapes (autotuned): nodes per forward chunk, and per group 16-signal
   // contraction tiles (1) or the widest (0) in the forward and the inverse
   int kc = 4;
@@ -319,7 +322,7 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
   MixedState* ms = pl->mixed;
   const GroupDev<T>* g = (const GroupDev<T>*)ms->d_groups;
   const bool bf = pl->dtype == SU2_C64_BF16X3;
-  auto grid_of = [&](int n) { return dim3((unsigned)std::max(1, std::min(n, knob * ms->num_cu))); };
+  auto grid_of = [&](int n) { return dim3((unsigned)std::max(1, knob > 0 ? std::min(n, knob * ms->num_cu) : n)); };
   switch (which) {
     case 0:
     case 3: {
@@ -564,6 +567,24 @@ std::map<std::string, std::vector<int>> g_tune_cache;
 std::string g_tune_file_loaded;   // cache file already read into g_tune_cache
 
 // shapes pinned through SU2_TILE_SHAPES ("kc,fwd,inv"); false if unset or malformed
+// the grid candidates of the autotuner, in workgroups per CU (0: one
+// workgroup per task, no task loop)
+constexpr int GRID_CANDS[] = {1, 2, 3, 4, 6, 8, 0};
+bool grid_candidate(int v) {
+  for (int c : GRID_CANDS)
+    if (v == c) return true;
+  return false;
+}
+
+// SU2_GRID="a,b,c,d": the four work-list grids pinned (each a candidate)
+bool pinned_grid(int (&k)[4]) {
+  const char* env = getenv("SU2_GRID");
+  if (!env || sscanf(env, "%d,%d,%d,%d", &k[0], &k[1], &k[2], &k[3]) != 4) return false;
+  for (int v : k)
+    if (!grid_candidate(v)) return false;
+  return true;
+}
+
 bool pinned_shapes(int* kc, int* fwd, int* inv) {
   const char* env = getenv("SU2_TILE_SHAPES");
   if (!env) return false;
@@ -643,7 +664,7 @@ su2_status_t autotune(su2_plan_s* pl) {
     auto valid = [&](const std::vector<int>& v) {
       if (v.size() != (size_t)(5 + 2 * ng)) return false;
       for (int i = 0; i < 4; i++)
-        if (v[i] < 1 || v[i] > 8) return false;
+        if (!grid_candidate(v[i])) return false;
       if (v[4] != 4 && v[4] != 8) return false;
       for (int g = 0; g < 2 * ng; g++)
         if (v[5 + g] != 0 && (v[5 + g] != 1 || dbl)) return false;
@@ -733,8 +754,7 @@ su2_status_t autotune(su2_plan_s* pl) {
   for (int which = 0; which < 4 && st == SU2_OK; which++) {
     float best = 1e30f;
     int best_k = ms->knob[which];
-    static const int cand[] = {1, 2, 3, 4, 6, 8};
-    for (int kn : cand) {
+    for (int kn : GRID_CANDS) {
       const float t = time_launch(which, kn);
       if (st != SU2_OK) break;
       if (t < best) { best = t; best_k = kn; }
@@ -840,6 +860,9 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, b
   if ((e = hipEventCreateWithFlags(&ms->join, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
   st = autotune(pl);
   if (st != SU2_OK) return st;
+  int pk[4];
+  if (pinned_grid(pk))  // overrides the search and the cache (not stored)
+    for (int i = 0; i < 4; i++) ms->knob[i] = pk[i];
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e);
   return SU2_OK;
 }

@@ -49,7 +49,7 @@ def test_mixed_bitwise_equals_single_plans(dtype):
     xs, cs = _mixed_inputs(Bs, dtype, 1)
     mp = su2.MixedPlan(Bs, dtype)
     k = mp.tuning()
-    assert len(k) == 4 and all(v in (1, 2, 3, 4, 6, 8) for v in k)
+    assert len(k) == 4 and all(v in (0, 1, 2, 3, 4, 6, 8) for v in k)
     x = _dev(np.concatenate(xs))
     c = _dev(np.concatenate(cs))
     f = _split(_host(mp.forward(x)), mp.coeff_offsets)
@@ -194,6 +194,30 @@ class _env:
 
 # groups of at most 16 signals and larger ones, every B class of the contraction
 SHAPE_BS = [8] * 3 + [24] * 20 + [32] * 5 + [48] * 17 + [64] * 2
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
+def test_pinned_grids_bitwise_equal_defaults(dtype):
+    """SU2_GRID pins the four work-list grids: one workgroup per task (0) and
+    the smallest persistent grid (1, every workgroup walking many tasks) give
+    the default grids' results bit for bit in all three directions, with the
+    register-resident and the generic ring lists and both contraction lists."""
+    Bs = [16, 48, 32, 24, 64, 8, 32, 48]
+    xs, cs = _mixed_inputs(Bs, dtype, 9)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    with _env(SU2_AUTOTUNE="0"):
+        ref = su2.MixedPlan(Bs, dtype)
+    want = [_host(ref.forward(x)), _host(ref.inverse(c)), _host(ref.adjoint(c))]
+    ref.close()
+    for grid in ("0,0,0,0", "1,1,1,1", "0,1,0,1"):
+        with _env(SU2_AUTOTUNE="0", SU2_GRID=grid):
+            mp = su2.MixedPlan(Bs, dtype)
+        assert mp.tuning() == [int(v) for v in grid.split(",")]
+        got = [_host(mp.forward(x)), _host(mp.inverse(c)), _host(mp.adjoint(c))]
+        mp.close()
+        for name, a, b in zip(("forward", "inverse", "adjoint"), got, want):
+            assert np.array_equal(a, b), (grid, name)
 
 
 def test_tile_shapes_defaults_reported():
