@@ -242,6 +242,14 @@ struct MixedState {
   su2::WorkItem* d_betaf = nullptr;
   su2::WorkItem* d_betai = nullptr;
   int n_ringf = 0, n_ringg = 0, n_betaf = 0, n_betai = 0;
+  // the contraction lists in runs of one shape class (forward: row tiles;
+  // inverse: degrees per group), largest class first: a run is one launch of
+  // the kernel built for exactly that class, so that the small bandlimits
+  // keep the registers, and the occupancy, of their single-B kernels
+  struct Run {
+    int cls, begin, n;
+  };
+  std::vector<Run> runs_f, runs_i;
   size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
   int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
   int num_cu = 0;
@@ -360,25 +368,41 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
       break;
     }
     case 1:
-      if (bf) {
-        void* k = betaf_bf16_kernel_ptr(ms->rtmax);
-        void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
-        return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(XB_THREADS), args, ms->smem_betaf, s);
-      } else {
-        void* k = betaf_kernel_ptr<T>(ms->rtmax, ms->kc);
-        void* args[] = {(void*)&ms->d_betaf, (void*)&ms->n_betaf, (void*)&g, (void*)&out};
-        return hipLaunchKernel(k, grid_of(ms->n_betaf), dim3(FWD_THREADS), args, ms->smem_betaf, s);
+    case 2: {
+      // the largest class on the call's stream, the others one after another
+      // on the second branch, so that the launches' tails overlap
+      const std::vector<MixedState::Run>& runs = which == 1 ? ms->runs_f : ms->runs_i;
+      const bool split = runs.size() > 1;
+      hipError_t e;
+      if (split) {
+        if ((e = hipEventRecord(ms->fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ms->side, ms->fork, 0)) != hipSuccess) return e;
       }
-    case 2:
-      if (bf) {
-        void* k = betai_bf16_kernel_ptr(ms->lq2);
-        void* args[] = {(void*)&ms->d_betai, (void*)&ms->n_betai, (void*)&g, (void*)&in, (void*)&dir};
-        return hipLaunchKernel(k, grid_of(ms->n_betai), dim3(XB_THREADS), args, ms->smem_betai, s);
-      } else {
-        void* k = betai_kernel_ptr<T>(ms->lq);
-        void* args[] = {(void*)&ms->d_betai, (void*)&ms->n_betai, (void*)&g, (void*)&in, (void*)&dir};
-        return hipLaunchKernel(k, grid_of(ms->n_betai), dim3(INV_THREADS), args, ms->smem_betai, s);
+      for (size_t ri = 0; ri < runs.size(); ri++) {
+        const MixedState::Run& r = runs[ri];
+        hipStream_t rs = ri == 0 ? s : ms->side;
+        if (which == 1) {
+          const WorkItem* items = ms->d_betaf + r.begin;
+          void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&out};
+          e = bf ? hipLaunchKernel(betaf_bf16_kernel_ptr(r.cls), grid_of(r.n), dim3(XB_THREADS), args, XBF_SMEM, rs)
+                 : hipLaunchKernel(betaf_kernel_ptr<T>(r.cls, ms->kc), grid_of(r.n), dim3(FWD_THREADS), args,
+                                   betaf_smem<T>(r.cls, ms->kc), rs);
+        } else {
+          const WorkItem* items = ms->d_betai + r.begin;
+          void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&in, (void*)&dir};
+          e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls), grid_of(r.n), dim3(XB_THREADS), args,
+                                   ms->smem_betai, rs)
+                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls), grid_of(r.n), dim3(INV_THREADS), args,
+                                   ms->smem_betai, rs);
+        }
+        if (e != hipSuccess) return e;
       }
+      if (split) {
+        if ((e = hipEventRecord(ms->join, ms->side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, ms->join, 0)) != hipSuccess) return e;
+      }
+      break;
+    }
   }
   return hipGetLastError();
 }
@@ -412,8 +436,14 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
   if (ms->smem_ringf > (size_t)max_lds || ms->smem_ringg > (size_t)max_lds || ms->smem_betaf > (size_t)max_lds ||
       ms->smem_betai > (size_t)max_lds)
     return hipErrorInvalidValue;
-  void* kf = bf ? betaf_bf16_kernel_ptr(ms->rtmax) : betaf_kernel_ptr<T>(ms->rtmax, ms->kc);
-  void* ki = bf ? betai_bf16_kernel_ptr(ms->lq2) : betai_kernel_ptr<T>(ms->lq);
+  for (const MixedState::Run& r : ms->runs_f)
+    if ((e = hipFuncSetAttribute(bf ? betaf_bf16_kernel_ptr(r.cls) : betaf_kernel_ptr<T>(r.cls, ms->kc),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+      return e;
+  for (const MixedState::Run& r : ms->runs_i)
+    if ((e = hipFuncSetAttribute(bf ? betai_bf16_kernel_ptr(r.cls) : betai_kernel_ptr<T>(r.cls),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+      return e;
   for (int fwd = 0; fwd < 2; fwd++) {
     if ((e = hipFuncSetAttribute(ringf_kernel_ptr<T>(fwd, pl->real), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  max_lds)) != hipSuccess)
@@ -422,8 +452,7 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
         hipSuccess)
       return e;
   }
-  if ((e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess) return e;
-  return hipFuncSetAttribute(ki, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  return hipSuccess;
 }
 
 // build the per-group device descriptors, work lists and LDS sizes from the
@@ -534,8 +563,28 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   };
   if ((e = upload(ringf, ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
   if ((e = upload(ringg, ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
-  if ((e = upload(betaf, ms->d_betaf, &ms->n_betaf)) != hipSuccess) return hip_fail(e);
-  if ((e = upload(betai, ms->d_betai, &ms->n_betai)) != hipSuccess) return hip_fail(e);
+  // contraction lists: by class (largest first), then by decreasing cost; one run per class
+  auto upload_runs = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem* dst, int* n,
+                         std::vector<MixedState::Run>& runs, bool fwd) -> hipError_t {
+    auto cls = [&](const WorkItem& w) { return fwd ? hg[w.g].rtmax : (bf ? hg[w.g].lq2 : hg[w.g].lq); };
+    std::stable_sort(lst.begin(), lst.end(), [&](const std::pair<double, WorkItem>& x,
+                                                 const std::pair<double, WorkItem>& y) {
+      const int cx = cls(x.second), cy = cls(y.second);
+      return cx != cy ? cx > cy : x.first > y.first;
+    });
+    runs.clear();
+    std::vector<WorkItem> v;
+    for (auto& x : lst) {
+      const int c = cls(x.second);
+      if (runs.empty() || runs.back().cls != c) runs.push_back({c, (int)v.size(), 0});
+      runs.back().n++;
+      v.push_back(x.second);
+    }
+    *n = (int)v.size();
+    return v.empty() ? hipSuccess : hipMemcpy(dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice);
+  };
+  if ((e = upload_runs(betaf, ms->d_betaf, &ms->n_betaf, ms->runs_f, true)) != hipSuccess) return hip_fail(e);
+  if ((e = upload_runs(betai, ms->d_betai, &ms->n_betai, ms->runs_i, false)) != hipSuccess) return hip_fail(e);
   if ((e = set_worklist_smem<T>(pl)) != hipSuccess) return hip_fail(e);
   return SU2_OK;
 }
@@ -552,8 +601,9 @@ su2_status_t rebuild_worklists(su2_plan_s* pl, int only_group = -1) {
 //      widest (32 in FP32) in the forward (FP32) and in the inverse (FP32 and
 //      split BF16), timing that group's contraction tasks alone;
 //   2. the nodes per forward chunk, 4 or 8 (FP32 and FP64);
-//   3. the persistent grid of each of the four work-list kernels, 1, 2, 3, 4,
-//      6 or 8 workgroups per CU.
+//   3. the grid of each of the four work-list kernels, 1, 2, 3, 4, 6 or 8
+//      workgroups per CU walking the list, or one workgroup per task.
+//      SU2_GRID="a,b,c,d" pins them (0 for one per task) over the search.
 // None of them changes a result (every signal's sums run in the same order).
 // Choices are cached per (device, mode, bandlimit mix) in the process and,
 // with SU2_AUTOTUNE_CACHE naming a text file, across processes.
@@ -566,7 +616,6 @@ std::mutex g_tune_mu;
 std::map<std::string, std::vector<int>> g_tune_cache;
 std::string g_tune_file_loaded;   // cache file already read into g_tune_cache
 
-// shapes pinned through SU2_TILE_SHAPES ("kc,fwd,inv"); false if unset or malformed
 // the grid candidates of the autotuner, in workgroups per CU (0: one
 // workgroup per task, no task loop)
 constexpr int GRID_CANDS[] = {1, 2, 3, 4, 6, 8, 0};
@@ -585,6 +634,7 @@ bool pinned_grid(int (&k)[4]) {
   return true;
 }
 
+// shapes pinned through SU2_TILE_SHAPES ("kc,fwd,inv"); false if unset or malformed
 bool pinned_shapes(int* kc, int* fwd, int* inv) {
   const char* env = getenv("SU2_TILE_SHAPES");
   if (!env) return false;
