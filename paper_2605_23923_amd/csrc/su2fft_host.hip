@@ -527,6 +527,23 @@ su2_status_t build_plan(su2_plan_s* pl) {
   if ((e = pl->alloc((void**)&pl->d_fftpos, sizeof(int) * pl->P_pad)) != hipSuccess) return hip_fail(e);
   if ((e = pl->alloc((void**)&pl->d_colq, sizeof(int) * pl->Nc)) != hipSuccess) return hip_fail(e);
   if ((e = pl->alloc((void**)&d_beta, sizeof(double) * N)) != hipSuccess) return hip_fail(e);
+  // the bin maps in the register-resident kernels' reading order: the
+  // entries of (q, p2) for the kept rows p1 of the alpha split, contiguous
+  int n1 = 0, n2 = 0;
+  auto thread_order = [&](std::vector<int>& b) {
+    if (!fast_ring_split(N, &n1, &n2)) return;
+    std::vector<int> v((size_t)N * N, -1);
+    const int h = n1 / 2;
+    for (int q = 0; q < N; q++)
+      for (int p2 = 0; p2 < n2; p2++)
+        for (int i = 0; i < h; i++) {
+          const int p1 = i < n1 / 4 ? i : i + n1 / 2;  // rows [0, N1/4) and [3 N1/4, N1)
+          v[((size_t)q * n2 + p2) * h + i] = b[(size_t)q * N + p2 + n2 * p1];
+        }
+    b.swap(v);
+  };
+  thread_order(bins);
+  if (pl->real && !pl->real_io) thread_order(bins_real);
   if ((e = pl->alloc((void**)&pl->d_bins, sizeof(int) * (size_t)N * N)) != hipSuccess) return hip_fail(e);
   if ((e = hipMemcpy(pl->d_bins, bins.data(), sizeof(int) * (size_t)N * N, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e);

@@ -115,12 +115,17 @@ struct FastRingParams {
   int N, batch;
   const cpx<T>* tw;   // e^{+i pi t / N}, t = 0..2N-1
   const T* W;         // beta weights W_k
-  const int* bins;    // [q * N + p]: (pair << 2) | e with rho = i^e, or -1 if the bin is not retained
+  // bin (p, q): (pair << 2) | e with rho = i^e, or -1 if the bin is not
+  // retained.  For the N of the register-resident kernels (split N = N1 N2,
+  // p = p2 + N2 p1) stored in the order they read it: entry
+  // ((q N2 + p2) (N1 / 2) + i) is the bin of row p1 = kept_row(i), so a
+  // thread's entries are contiguous; for N = 256, at q * N + p
+  const int* bins;
   int adjoint;        // inverse chain: 0 -> plain, 1 -> multiply by W_k
   int rbeg[FAST_ROUNDS], rend[FAST_ROUNDS];
   const long long* soff;  // per signal sample offsets, or null
-  // real signals (inverse): [q * N + p]: (source pair << 3) | (conjugate << 2) | e,
-  // the source being the bin's own pair (2m >= 0) or its mirror (-m, -n)
+  // real signals (inverse): (source pair << 3) | (conjugate << 2) | e, the
+  // source being the bin's own pair (2m >= 0) or its mirror (-m, -n); same order as bins
   const int* bins_real;
   int so3;            // SO(3) plan: integer n only, no half-bin shift on any q
   int real_io;        // N = 256 kernels: real samples in (forward) or the real part out (inverse)
@@ -336,6 +341,8 @@ bool fast_ring_supported(int N);
 template <class T>
 size_t fast_ring_smem(int N);
 int fast_rings_per_group(int N);
+// the register-resident kernels' split N = N1 N2 (false if N has none)
+bool fast_ring_split(int N, int* n1, int* n2);
 // pairs of one q slice that the kernels can stage in LDS
 template <class T>
 int fast_ring_slice_capacity(int N);

@@ -141,6 +141,24 @@ __device__ __forceinline__ cpx<T> ipow_scale(cpx<T> v, int e, T s) {
 template <int N1>
 __device__ __forceinline__ constexpr int kept_row(int i) { return i < N1 / 4 ? i : i + N1 / 2; }
 
+// the N1 / 2 bin entries of (q, p2), stored contiguously, in 16- or 8-byte loads
+template <int N1, int N2>
+__device__ __forceinline__ void load_entries(const int* __restrict__ bins, int q, int p2, int (&ent)[N1 / 2]) {
+  constexpr int H = N1 / 2;
+  const int* src = bins + (q * N2 + p2) * H;
+  if constexpr (H % 4 == 0) {
+#pragma unroll
+    for (int v = 0; v < H / 4; v++) {
+      const int4 w = reinterpret_cast<const int4*>(src)[v];
+      ent[4 * v] = w.x; ent[4 * v + 1] = w.y; ent[4 * v + 2] = w.z; ent[4 * v + 3] = w.w;
+    }
+  } else {
+    static_assert(H == 2, "entries per (q, p2)");
+    const int2 w = *reinterpret_cast<const int2*>(src);
+    ent[0] = w.x; ent[1] = w.y;
+  }
+}
+
 // FP32 rings: two workgroups per CU (64 KB LDS slices, at most 128 VGPRs);
 // FP64 rings: one workgroup per CU.
 template <class T>
@@ -302,8 +320,7 @@ __device__ __forceinline__ void ring_forward_fast_body(const void* __restrict__ 
     // this thread's bin entries for the round, fetched before the exchange so
     // that their latency hides behind it
     int ent[N1 / 2];
-#pragma unroll
-    for (int i = 0; i < N1 / 2; i++) ent[i] = p.bins[q * N + p2 + N2 * kept_row<N1>(i)];
+    load_entries<N1, N2>(p.bins, q, p2, ent);
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < G::I1 / ROUNDS; s++) {
@@ -353,13 +370,11 @@ template <class T, int N1, int N2, int NT, int ROUNDS, bool REAL>
 __device__ __forceinline__ void ring_inverse_fast_entries(const FastRingParams<T>& p,
                                                           int (&ent)[InvShape<N1, N2, NT, ROUNDS, REAL>::RA][N1 / 2],
                                                           int t) {
-  constexpr int N = N1 * N2;
   const int* bins = REAL ? p.bins_real : p.bins;
 #pragma unroll
   for (int r = 0; r < InvShape<N1, N2, NT, ROUNDS, REAL>::RA; r++) {
     const int q = t / N2 + (NT / N2) * r;
-#pragma unroll
-    for (int i = 0; i < N1 / 2; i++) ent[r][i] = bins[q * N + t % N2 + N2 * kept_row<N1>(i)];
+    load_entries<N1, N2>(bins, q, t % N2, ent[r]);
   }
 }
 
@@ -757,6 +772,16 @@ int fast_ring_slice_capacity(int N) {
     case 128: return FastRing<T, 128>::G::SLICE_CAP;
   }
   return 0;
+}
+
+bool fast_ring_split(int N, int* n1, int* n2) {
+  switch (N) {
+    case 16: *n1 = FastCfg<16>::N1; *n2 = FastCfg<16>::N2; return true;
+    case 32: *n1 = FastCfg<32>::N1; *n2 = FastCfg<32>::N2; return true;
+    case 64: *n1 = FastCfg<64>::N1; *n2 = FastCfg<64>::N2; return true;
+    case 128: *n1 = FastCfg<128>::N1; *n2 = FastCfg<128>::N2; return true;
+  }
+  return false;
 }
 
 int fast_rings_per_group(int N) {
