@@ -413,7 +413,10 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   // The next block's values are requested before this block's products, so
   // they have the whole block (products, staging, stores) to arrive; where
   // two register sets do not fit (FP64 with 64 degrees), after the products.
-  constexpr bool EARLY = sizeof(T) * LQ <= 64;
+  // FP32 with 64 degrees in 16-signal tiles (B = 128, batches of at most 16)
+  // also fetches late: without the second set the kernel fits 128 VGPRs and
+  // two workgroups share a CU (B = 128 batch 16: 0.502 -> 0.474 ms).
+  constexpr bool EARLY = sizeof(T) * LQ <= 64 && !(LQ == 16 && BT == 16);
   T av[2][LQ], avn[2][LQ];
   auto fetch_a = [&](T (&dst)[2][LQ], int kb) {
 #pragma unroll

@@ -306,6 +306,11 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
   // degrees of node k0 + lrow (rows past N read row N - 1 and are never
   // stored; degrees past L read the words that follow in the tile block, or
   // the zeroed table padding, and meet zero B operands)
+  // The next block's words are requested before this block's products,
+  // except with two 32-degree groups in 16-signal tiles (B = 128, batches of
+  // at most 16): there they are requested after the products, so that one
+  // register set suffices and two workgroups share a CU.
+  constexpr bool EARLY = !(LQ == 2 && BT == 16);
   unsigned aw[2][LQ][8], awn[2][LQ][8];
   auto fetch_a = [&](unsigned (&dst)[2][LQ][8], int k0) {
     const int k = k0 + lrow < N ? k0 + lrow : N - 1;
@@ -330,7 +335,8 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
       (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<float>)), BUFFER_RSRC_WORD3);
   fetch_a(aw, 0);
   for (int k0 = 0; k0 < N; k0 += 16) {
-    if (k0 + 16 < N) fetch_a(awn, k0 + 16);
+    if constexpr (EARLY)
+      if (k0 + 16 < N) fetch_a(awn, k0 + 16);
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const int L = pi[q].L;
@@ -359,6 +365,8 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
         for (int r = 0; r < 4; r++) stage[((4 * lg + r) * BT + bb) * PB + 2 * pp + reim] = acc[ct][r];
       }
     }
+    if constexpr (!EARLY)
+      if (k0 + 16 < N) fetch_a(aw, k0 + 16);  // in flight during the staging and the stores
     __syncthreads();
     // the thread index passes through an empty asm statement so that the
     // store addresses are formed here, not hoisted out of the node loop
@@ -381,12 +389,14 @@ __device__ __forceinline__ void beta_inverse_bf16x3_body(const cpx<float>* __res
       __builtin_amdgcn_raw_buffer_store_b128(w, srsrc, off, 0, 0);
     }
     __syncthreads();
+    if constexpr (EARLY) {
 #pragma unroll
-    for (int q = 0; q < 2; q++)
+      for (int q = 0; q < 2; q++)
 #pragma unroll
-      for (int s = 0; s < LQ; s++)
+        for (int s = 0; s < LQ; s++)
 #pragma unroll
-        for (int i = 0; i < 8; i++) aw[q][s][i] = awn[q][s][i];
+          for (int i = 0; i < 8; i++) aw[q][s][i] = awn[q][s][i];
+    }
   }
 }
 
