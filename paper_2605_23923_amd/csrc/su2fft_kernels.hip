@@ -251,7 +251,7 @@ struct MixedState {
   };
   std::vector<Run> runs_f, runs_i;
   size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
-  int rtmax = 1, lq = 2, lq2 = 1;   // largest contraction shapes present
+  int rtmax = 1;                    // largest forward row-tile count present (LDS check)
   int num_cu = 0;
   // workgroups per CU (0: one per task): ring forward, contraction forward,
   // contraction inverse, ring inverse
@@ -479,8 +479,6 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   std::vector<std::pair<double, WorkItem>> ringf, ringg, betaf, betai;
   int cap_f = 0, cap_i = 0;
   ms->rtmax = 1;
-  ms->lq = 2;
-  ms->lq2 = 1;
   for (int gi = 0; gi < ng; gi++) {
     su2_plan_s* gp = ms->groups[gi];
     GroupDev<T>& d = hg[gi];
@@ -501,8 +499,6 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
     d.tabi_bf = (const unsigned*)gp->d_tabbf;
     d.S = (cpx<T>*)gp->d_S;
     ms->rtmax = std::max(ms->rtmax, d.rtmax);
-    ms->lq = std::max(ms->lq, d.lq);
-    ms->lq2 = std::max(ms->lq2, d.lq2);
     const int N = gp->N;
     // ring LDS
     const double ring_cost = (double)N * N * (N > 1 ? std::log2((double)N) : 1.0);
