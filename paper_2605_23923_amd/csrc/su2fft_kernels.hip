@@ -8,7 +8,8 @@
 // walks every (group, signal, node) ring task, the other every (group, pair
 // tile, signal tile) contraction task, each calling the same kernel bodies as
 // the single-B launches (so every signal's result is bit-identical to a
-// single-B plan's).  Tasks are ordered by decreasing cost and taken in a
+// single-B plan's, except at B = 128, whose rings take the general ring
+// body where single-B plans have dedicated N = 256 kernels).  Tasks are ordered by decreasing cost and taken in a
 // static stride by a grid of `knob x CUs` workgroups, or (knob 0) one
 // workgroup per task; the knob of each kernel is chosen by timing the
 // candidates at plan creation (autotuner, cached per device, mode and
