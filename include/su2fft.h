@@ -140,12 +140,10 @@ su2_status_t su2_plan_create_ex(int32_t B, int32_t batch, su2_dtype_t dtype, uin
  * first time a (direction, input, output, stream) combination is used, and
  * the graph is replayed on later calls with the same buffers and stream (the
  * plan keeps up to 16 such graphs).  Results are bit-identical to single-B
- * plans of each signal, except for B = 128: its rings run the general ring
- * kernel, where a single-B plan runs the dedicated N = 256 kernels, and
- * agree with the single-B plan to rounding (normwise differences of about
- * 5e-16 in FP64, 3e-7 in FP32, 1e-6 with split BF16).  B_per_signal is a
- * host array, read only during the call.  su2_run_stage and su2_plan_dtable
- * do not accept mixed plans. */
+ * plans of each signal (B = 128 groups run the single-B plan's N = 256 ring
+ * kernels beside the work lists).  B_per_signal is a host array, read only
+ * during the call.  su2_run_stage and su2_plan_dtable do not accept mixed
+ * plans. */
 su2_status_t su2_plan_create_mixed(const int32_t* B_per_signal, int32_t batch, su2_dtype_t dtype,
                                    su2_plan_t* out);
 

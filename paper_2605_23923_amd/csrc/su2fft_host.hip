@@ -256,7 +256,7 @@ su2_status_t build_plan(su2_plan_s* pl) {
   // the register-resident ring kernels handle the whole ring themselves and
   // want the pairs ordered by 2m alone
   pl->fast = (pl->dtype == SU2_C128) ? fast_ring_supported<double>(N) : fast_ring_supported<float>(N);
-  const bool n256 = !pl->fast && pl->allow_large && large_ring_supported(N);
+  const bool n256 = !pl->fast && large_ring_supported(N);
   pl->sliced = n256 && pl->dtype != SU2_C128;
   pl->large = n256;
   // only the register-resident rings have a half-spectrum form for real signals

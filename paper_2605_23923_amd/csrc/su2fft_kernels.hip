@@ -8,8 +8,8 @@
 // walks every (group, signal, node) ring task, the other every (group, pair
 // tile, signal tile) contraction task, each calling the same kernel bodies as
 // the single-B launches (so every signal's result is bit-identical to a
-// single-B plan's, except at B = 128, whose rings take the general ring
-// body where single-B plans have dedicated N = 256 kernels).  Tasks are ordered by decreasing cost and taken in a
+// single-B plan's); the rings of N = 256 groups run the single-B plan's own
+// N = 256 kernels beside the work lists.  Tasks are ordered by decreasing cost and taken in a
 // static stride by a grid of `knob x CUs` workgroups, or (knob 0) one
 // workgroup per task; the knob of each kernel is chosen by timing the
 // candidates at plan creation (autotuner, cached per device, mode and
@@ -243,6 +243,9 @@ struct MixedState {
   su2::WorkItem* d_betaf = nullptr;
   su2::WorkItem* d_betai = nullptr;
   int n_ringf = 0, n_ringg = 0, n_betaf = 0, n_betai = 0;
+  // groups whose rings (N = 256) run the single-B plan's dedicated kernels
+  // (one-pass sliced in FP32, two-pass in FP64) instead of a work list
+  std::vector<int> dedicated;
   // the contraction lists in runs of one shape class (forward: row tiles;
   // inverse: degrees per group), largest class first: a run is one launch of
   // the kernel built for exactly that class, so that the small bandlimits
@@ -263,7 +266,7 @@ struct MixedState {
   std::vector<int> narrow_f, narrow_i;
   int max_betaf = 0, max_betai = 0;  // work-list capacities (every group in 16-signal tiles)
   hipStream_t cap = nullptr;          // capture stream
-  hipStream_t side = nullptr;         // second branch: generic ring tasks run beside the fast ones
+  hipStream_t side = nullptr;         // second branch: generic and N = 256 rings beside the fast ones
   hipEvent_t fork = nullptr, join = nullptr;
   std::vector<MixedGraph> graphs;
   std::vector<void*> allocs;
@@ -324,6 +327,21 @@ void* betai_bf16_kernel_ptr(int lq2) {
   return (void*)beta_inverse_bf16x3_worklist_kernel<2>;
 }
 
+// the rings of an N = 256 group with the single-B plan's kernels (d: 0
+// forward, 1 inverse, 2 adjoint); the ring spectra are the group's workspace
+template <class T>
+hipError_t launch_rings_256(su2_plan_s* gp, bool fwd, int d, const void* in, void* out, hipStream_t s) {
+  cpx<T>* S = (cpx<T>*)gp->d_S;
+  if (gp->sliced) {
+    if constexpr (std::is_same<T, float>::value)
+      return fwd ? launch_ring_sliced4(true, fast_params<T>(gp, 0), (const cpx<T>*)in, S, s)
+                 : launch_ring_sliced4(false, fast_params<T>(gp, d == 2), S, (cpx<T>*)out, s);
+    return hipErrorInvalidValue;
+  }
+  return fwd ? launch_ring_forward_large<T>(large_params<T>(gp, 0), (const cpx<T>*)in, S, s)
+             : launch_ring_inverse_large<T>(large_params<T>(gp, d == 2), S, (cpx<T>*)out, s);
+}
+
 // enqueue one work-list launch: which = 0 ring forward, 1 contraction forward,
 // 2 contraction inverse/adjoint, 3 ring inverse/adjoint
 template <class T>
@@ -335,9 +353,11 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
   switch (which) {
     case 0:
     case 3: {
-      // both ring lists present: the generic one runs on a second branch
-      // (fork/join through events, also inside a stream capture)
-      const bool both = ms->n_ringf > 0 && ms->n_ringg > 0;
+      // the generic list and the N = 256 groups run on a second branch beside
+      // the register-resident list (fork/join through events, also inside a
+      // stream capture)
+      const bool side_work = ms->n_ringg > 0 || !ms->dedicated.empty();
+      const bool both = ms->n_ringf > 0 && side_work;
       hipStream_t sg = both ? ms->side : s;
       hipError_t e;
       if (both) {
@@ -355,6 +375,8 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
                                  ms->smem_ringg, sg)) != hipSuccess)
           return e;
       }
+      for (int gi : ms->dedicated)
+        if ((e = launch_rings_256<T>(ms->groups[gi], which == 0, d, in, out, sg)) != hipSuccess) return e;
       if (ms->n_ringf > 0) {
         args[0] = (void*)&ms->d_ringf;
         args[1] = (void*)&ms->n_ringf;
@@ -480,6 +502,7 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   std::vector<std::pair<double, WorkItem>> ringf, ringg, betaf, betai;
   int cap_f = 0, cap_i = 0;
   ms->rtmax = 1;
+  ms->dedicated.clear();
   for (int gi = 0; gi < ng; gi++) {
     su2_plan_s* gp = ms->groups[gi];
     GroupDev<T>& d = hg[gi];
@@ -503,7 +526,9 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
     const int N = gp->N;
     // ring LDS
     const double ring_cost = (double)N * N * (N > 1 ? std::log2((double)N) : 1.0);
-    if (gp->fast) {
+    if (gp->large) {
+      ms->dedicated.push_back(gi);  // launched whole by launch_rings_256
+    } else if (gp->fast) {
       // one task per workgroup's worth of consecutive rings of a signal
       ms->smem_ringf = std::max(ms->smem_ringf, fast_ring_smem<T>(N));
       const int rpw = fast_rings_per_group(N);
@@ -883,7 +908,6 @@ su2_status_t create_mixed(const int32_t* Bs, int32_t batch, su2_dtype_t dtype, b
     gp->dtype = dtype;
     gp->real = real;
     gp->so3 = so3;
-    gp->allow_large = false;  // the work lists run the generic kernels for N = 256
     std::vector<long long> so, co;
     for (int s : kv.second) { so.push_back(soff[s]); co.push_back(coff[s]); }
     long long *dso = nullptr, *dco = nullptr;

@@ -57,7 +57,6 @@ struct su2_plan_s {
   bool large = false;            // N = 256: two-pass ring kernels through an intermediate (d_G)
   bool sliced = false;          // N = 256 in FP32: both ring directions run in one pass, four workgroups per ring
   int* d_cols = nullptr;        // N = 256 in FP32: per-column bin bases of the one-pass rings (null: not usable)
-  bool allow_large = true;  // mixed-plan groups use the generic kernels instead
   int* d_qrange = nullptr;
   void* d_G = nullptr;
   int large_chunk = 0;

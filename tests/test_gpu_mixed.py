@@ -3,9 +3,7 @@ autotuned grid sizes.
 
 Every signal of a mixed plan runs the same kernel bodies as a single-B plan,
 so its results must be bit-identical to a batch-1 single-B plan of that
-signal (B = 128 aside: its rings take the general ring body in mixed plans
-and agree with the single-B plan's N = 256 kernels to rounding); the oracle
-then pins one signal per distinct bandlimit.
+signal; the oracle then pins one signal per distinct bandlimit.
 """
 import os
 import subprocess
@@ -178,11 +176,10 @@ def test_mixed_real_and_so3_bitwise_equal_single_plans(kind, dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
 def test_mixed_with_b128_groups(dtype):
-    """B = 128 groups in a mixed plan run the generic ring body (the gamma
-    axis split so that a slice of the ring fits in LDS) where single-B plans
-    run the one-pass sliced (FP32) or two-pass (FP64) N = 256 rings: equal to
-    the single-B plan to rounding, and to sampled oracle coefficients and
-    points; the B = 16 signal beside them stays bit for bit."""
+    """B = 128 groups in a mixed plan run the single-B plan's N = 256 ring
+    kernels (one pass in FP32, two passes in FP64) beside the work lists:
+    every signal bit for bit equal to its single-B plan, and the B = 128
+    signals to sampled oracle coefficients and points."""
     Bs = [128, 16, 128]
     xs, cs = _mixed_inputs(Bs, dtype, 12)
     with _env(SU2_AUTOTUNE="0"):
@@ -191,22 +188,13 @@ def test_mixed_with_b128_groups(dtype):
     i = _split(_host(mp.inverse(_dev(np.concatenate(cs)))), mp.sample_offsets)
     a = _split(_host(mp.adjoint(_dev(np.concatenate(cs)))), mp.sample_offsets)
     mp.close()
-    near = {"c128": 1e-13, "c64": 2e-6, "c64_bf16x3": 2e-6}[dtype]  # two FFT orderings of one rounding
     for s, B in enumerate(Bs):
         N = 2 * B
         p = su2.Plan(B, 1, dtype)
-        want = [_host(p.forward(_dev(xs[s].reshape(1, N, N, N))))[0],
-                _host(p.inverse(_dev(cs[s].reshape(1, -1)))).reshape(-1),
-                _host(p.adjoint(_dev(cs[s].reshape(1, -1)))).reshape(-1)]
+        assert np.array_equal(f[s], _host(p.forward(_dev(xs[s].reshape(1, N, N, N))))[0]), (s, B, "forward")
+        assert np.array_equal(i[s], _host(p.inverse(_dev(cs[s].reshape(1, -1)))).reshape(-1)), (s, B, "inverse")
+        assert np.array_equal(a[s], _host(p.adjoint(_dev(cs[s].reshape(1, -1)))).reshape(-1)), (s, B, "adjoint")
         p.close()
-        for name, got, ref in zip(("forward", "inverse", "adjoint"), (f[s], i[s], a[s]), want):
-            if B != 128:
-                assert np.array_equal(got, ref), (s, B, name)
-                continue
-            rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            record(f"mixed B=128 vs single-B {name} {dtype}", rel, np.max(np.abs(got - ref)) / np.max(np.abs(ref)),
-                   tol=near)
-            assert rel <= near, (s, name, rel)
     rng = np.random.default_rng(5)
     sel = rng.choice(oracle.num_coeffs(128), 6, replace=False)
     ref = oracle.forward(128, xs[2].astype(np.complex128), sel)
@@ -216,6 +204,28 @@ def test_mixed_with_b128_groups(dtype):
     ref = oracle.inverse(128, cs[2].astype(np.complex128), pts)
     rel = np.linalg.norm(i[2][pts] - ref) / np.linalg.norm(ref)
     assert rel <= TOL[dtype], ("inverse", rel)
+
+
+def test_mixed_real_with_b128_group():
+    """Real signals at B = 128 in a mixed plan (the N = 256 kernels with real
+    samples in and the real part out) equal batch-1 real single-B plans bit
+    for bit, beside a half-spectrum B = 16 signal."""
+    Bs = [16, 128]
+    rng = np.random.default_rng(17)
+    xs = [synth.samples_uniform(B, 1, seed=int(rng.integers(1 << 30))).real.astype(np.float32).reshape(-1)
+          for B in Bs]
+    cs = [synth.coeffs(B, 1, seed=int(rng.integers(1 << 30)), dtype=np.complex64)[0] for B in Bs]
+    with _env(SU2_AUTOTUNE="0"):
+        mp = su2.MixedPlan(Bs, "c64", real=True)
+    f = _split(_host(mp.forward(_dev(np.concatenate(xs)))), mp.coeff_offsets)
+    i = _split(_host(mp.inverse(_dev(np.concatenate(cs)))), mp.sample_offsets)
+    mp.close()
+    for s, B in enumerate(Bs):
+        p = su2.Plan(B, 1, "c64", real=True)
+        N = 2 * B
+        assert np.array_equal(f[s], _host(p.forward(_dev(xs[s].reshape(1, N, N, N))))[0]), (B, "forward")
+        assert np.array_equal(i[s], _host(p.inverse(_dev(cs[s].reshape(1, -1)))).reshape(-1)), (B, "inverse")
+        p.close()
 
 
 class _env:
