@@ -15,7 +15,8 @@ is bracketed by HIP events on the stream it runs on; `roofline` reports the
 kernel with the largest share of the step against the HBM peak, with its
 algorithmic bytes per launch.  `cpu_baseline` times the CPU oracle (direct
 quadrature sum) on a bounded sample of the same forward workload, and
-`cpu_fft_baseline` a plain CPU FFT-based separated transform (float64) beside it.
+`cpu_fft_baseline` a plain CPU FFT-based separated transform (float64) beside it
+(`cpu_fft_baselines`: float64 and float32, forward and inverse).
 """
 from __future__ import annotations
 
@@ -503,24 +504,35 @@ def cpu_baseline(B: int, budget_s: float):
                       f"{(2 * B) ** 3} terms each), {dt:.1f} s; scaled by {C}/{count}"}
 
 
-def cpu_fft_baseline(B: int):
+def cpu_fft_baselines(B: int):
     """A plain CPU FFT-based separated transform (scipy.fft + numpy matmul,
-    float64, all host cores): forward transforms of a batch of 4 signals,
-    best of 3 after a warm-up; tables built once, before timing."""
+    all host cores), in float64 and in float32: forward and inverse
+    transforms of a batch of 4 signals, best of 3 after a warm-up; tables
+    built once per precision, before timing.  Returns the entries, the
+    float64 forward first."""
+    import numpy as np
+
     import oracle.cpu_fft as cf
     import synth
 
-    plan = cf.CpuFFTPlan(B)
     x = synth.samples_uniform(B, 4, seed=5)
-    plan.forward(x)
-    best = 1e30
-    for _ in range(3):
-        t0 = time.perf_counter()
-        plan.forward(x)
-        best = min(best, time.perf_counter() - t0)
-    return {"value": round(4 / best, 3), "unit": "transforms/s", "cores": plan.workers, "kind": "cpu_fft",
-            "sample": f"forward, B={B}, batch 4, scipy.fft (workers={plan.workers}) + numpy matmul in float64, "
-                      f"best of 3: {best:.2f} s; table build excluded"}
+    c = synth.coeffs(B, 4, seed=6)
+    out = []
+    for dt, name in ((np.complex128, "float64"), (np.complex64, "float32")):
+        plan = cf.CpuFFTPlan(B, dtype=dt)
+        xd, cd = x.astype(dt), c.astype(dt)
+        for direction, fn, arg in (("forward", plan.forward, xd), ("inverse", plan.inverse, cd)):
+            fn(arg)
+            best = 1e30
+            for _ in range(3):
+                t0 = time.perf_counter()
+                fn(arg)
+                best = min(best, time.perf_counter() - t0)
+            out.append({"value": round(4 / best, 3), "unit": "transforms/s", "cores": plan.workers,
+                        "kind": "cpu_fft",
+                        "sample": f"{direction}, B={B}, batch 4, scipy.fft (workers={plan.workers}) + numpy matmul "
+                                  f"in {name}, best of 3: {best:.2f} s; table build excluded"})
+    return out
 
 
 def main():
@@ -634,7 +646,9 @@ def main():
         line["other_workloads"] = secondary_configs(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(B, args.cpu_budget)
-        line["cpu_fft_baseline"] = cpu_fft_baseline(B)
+        fft = cpu_fft_baselines(B)
+        line["cpu_fft_baseline"] = fft[0]
+        line["cpu_fft_baselines"] = fft
     print(json.dumps(line), flush=True)
 
 

@@ -7,7 +7,9 @@ It evaluates the regrouped quadrature sum of Section 4 (the core equation
 that turns the inner sums over alpha and gamma into a 2D DFT on every beta
 ring and leaves one projection over the beta nodes per (m, n)), with library
 FFTs (``scipy.fft``) and matrix products (``numpy.matmul``) in double
-precision, on the grid and basis of the direct-sum oracle:
+precision (or, as a second CPU baseline, in single precision: the tables
+rounded to float32 and every array complex64), on the grid and basis of the
+direct-sum oracle:
 
   forward:  G_k[j, q] = sum_l f[k, j, l] e^{+2 pi i q l / N},            q = 2m mod N
             H_k[p, q] = sum_j G_k[j, q] e^{i pi j / N} e^{+2 pi i p j / N}  (half-integer n; no
@@ -32,13 +34,15 @@ from . import coeff_index, grid, num_coeffs, wigner_d_many
 
 
 class CpuFFTPlan:
-    def __init__(self, B: int, workers: int | None = None):
+    def __init__(self, B: int, workers: int | None = None, dtype=np.complex128):
         self.B, self.N = B, 2 * B
         self.workers = workers or os.cpu_count() or 1
+        self.cdt = np.dtype(dtype)
+        self.rdt = np.float32 if self.cdt == np.complex64 else np.float64
         N = self.N
         _, beta, _, W = grid(B)
-        self.W = W
-        self.twist = np.exp(1j * np.pi * np.arange(N) / N)
+        self.W = W.astype(self.rdt)
+        self.twist = np.exp(1j * np.pi * np.arange(N) / N).astype(self.cdt)
         # retained pairs, grouped by their number of degrees L for batched products
         groups = {}
         for tm in range(-(B - 1), B):
@@ -65,18 +69,19 @@ class CpuFFTPlan:
             p = np.where(odd, np.mod((tn - 1) // 2, N), np.mod(tn // 2, N))
             ring_phase = (-1.0) ** tm * np.exp(-1j * np.pi * tn / 2)            # (-1)^{2m} e^{-i pi n}
             beta_phase = 1j ** np.mod((tn - tm) // 2, 4)                        # i^{n-m}
-            self.groups.append(dict(L=L, d=d, cidx=cidx, q=q, p=p, odd=odd, tls=tls,
-                                    ring_phase=ring_phase, beta_phase=beta_phase))
+            self.groups.append(dict(L=L, d=d.astype(self.rdt), cidx=cidx, q=q, p=p, odd=odd,
+                                    scale=(tls + 1).astype(self.rdt), ring_phase=ring_phase.astype(self.cdt),
+                                    beta_phase=beta_phase.astype(self.cdt)))
 
     # ---- forward ----
     def forward(self, f: np.ndarray) -> np.ndarray:
         """f: (batch, N, N, N) samples [b][k][j][l] -> (batch, C) coefficients."""
         N, w = self.N, self.workers
-        f = np.asarray(f, dtype=np.complex128).reshape(-1, N, N, N)
+        f = np.asarray(f, dtype=self.cdt).reshape(-1, N, N, N)
         G = sfft.ifft(f, axis=3, workers=w) * N                       # sum_l e^{+2 pi i q l / N}
         A0 = sfft.ifft(G, axis=2, workers=w) * N                      # integer n
         A1 = sfft.ifft(G * self.twist[None, None, :, None], axis=2, workers=w) * N   # half-integer n
-        out = np.zeros((f.shape[0], num_coeffs(self.B)), dtype=np.complex128)
+        out = np.zeros((f.shape[0], num_coeffs(self.B)), dtype=self.cdt)
         for g in self.groups:
             H = np.where(g["odd"][None, None, :], A1[:, :, g["p"], g["q"]], A0[:, :, g["p"], g["q"]])  # (b, k, G)
             S = H * self.W[None, :, None] * g["ring_phase"][None, None, :]
@@ -89,14 +94,14 @@ class CpuFFTPlan:
     # ---- inverse / adjoint ----
     def _synth(self, c: np.ndarray, adjoint: bool) -> np.ndarray:
         N, w = self.N, self.workers
-        c = np.asarray(c, dtype=np.complex128).reshape(-1, num_coeffs(self.B))
+        c = np.asarray(c, dtype=self.cdt).reshape(-1, num_coeffs(self.B))
         nb = c.shape[0]
-        H0 = np.zeros((nb, N, N, N), dtype=np.complex128)   # [b][k][p][q], integer n
+        H0 = np.zeros((nb, N, N, N), dtype=self.cdt)        # [b][k][p][q], integer n
         H1 = np.zeros_like(H0)                               # half-integer n
         for g in self.groups:
             cc = c[:, g["cidx"]]                                         # (b, G, L)
             if not adjoint:
-                cc = cc * (g["tls"] + 1)[None, :, :]
+                cc = cc * g["scale"][None, :, :]
             cc = cc * np.conj(g["beta_phase"])[None, :, None]
             S = np.matmul(np.transpose(g["d"], (0, 2, 1)), np.transpose(cc, (1, 2, 0)))  # (G, N, b)
             S = np.transpose(S, (2, 1, 0)) * np.conj(g["ring_phase"])[None, None, :]       # (b, k, G)

@@ -33,3 +33,18 @@ def test_cpu_fft_round_trip(B):
     pl = CpuFFTPlan(B, workers=2)
     c = synth.coeffs(B, 2, seed=60 + B)
     assert _rel(pl.forward(pl.inverse(c)), c) < 1e-12
+
+
+@pytest.mark.parametrize("B", [4, 12])
+def test_cpu_fft_single_precision_baseline(B):
+    """The single-precision variant (the second CPU baseline) computes the
+    same sums in float32 / complex64: within single-precision rounding of the
+    double-precision plan, in every direction, and in complex64."""
+    x = synth.samples_uniform(B, 2, seed=60 + B)
+    c = synth.coeffs(B, 2, seed=70 + B)
+    p64 = CpuFFTPlan(B, workers=2)
+    p32 = CpuFFTPlan(B, workers=2, dtype=np.complex64)
+    for got, ref in ((p32.forward(x), p64.forward(x)), (p32.inverse(c), p64.inverse(c)),
+                     (p32.adjoint(c), p64.adjoint(c))):
+        assert got.dtype == np.complex64
+        assert _rel(got, ref) < 1e-5
