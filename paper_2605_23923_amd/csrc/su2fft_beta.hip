@@ -63,6 +63,19 @@ struct BetaCfg<double> {
   static constexpr int BT = 16;  // 32 real columns
 };
 
+// compute units of the current device (read once per process)
+inline int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+              ? n
+              : 256;
+  }
+  return cus;
+}
+
 // ---- coefficients through LDS ----
 //
 // A wave's matrix-core operands (inverse) or results (forward) belong to two
@@ -554,24 +567,28 @@ static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx
   if constexpr (sizeof(T) == 4) {
     // two resident workgroups per CU pay off once most CUs get two (grids
     // of at least 1.5 workgroups per CU)
-    static int cus = 0;
-    if (cus == 0) {
-      int dev = 0;
-      if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                   hipSuccess || cus < 1)
-        cus = 256;
-    }
-    if (2LL * grid.x >= 3LL * cus) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
+    if (2LL * grid.x >= 3LL * device_cus()) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
   }
   return launch_forward_shape<T, RTMAX, 8, BT>(p, grid, S, coeffs, s);
+}
+
+// 16-signal tiles instead of the widest (FP32): for batches of at most 16,
+// and where the widest tiles would leave fewer than 1.5 workgroups per CU
+// (real-signal and SO(3) plans at B = 64 batch 32 contract about 250 pair
+// tiles), so that most CUs hold two workgroups
+template <class T>
+bool narrow_tiles(const BetaParams<T>& p, int units) {
+  constexpr int BTW = BetaCfg<T>::BT;
+  if (BTW <= 16) return false;
+  return p.batch <= 16 || 2LL * units * ((p.batch + BTW - 1) / BTW) < 3LL * device_cus();
 }
 
 template <class T>
 hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* coeffs, hipStream_t s) {
   constexpr int BTW = BetaCfg<T>::BT;      // widest signal tile
-  constexpr int BTN = BTW > 16 ? 16 : BTW;  // for batches of at most 16
+  constexpr int BTN = BTW > 16 ? 16 : BTW;  // narrow tiles (narrow_tiles)
   const int rt = beta_rtmax(p.B);
-  if (BTN != BTW && p.batch <= BTN) {
+  if (BTN != BTW && narrow_tiles(p, p.ntiles - p.tile0)) {
     const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + BTN - 1) / BTN, p.paired));
     if (rt == 1) return launch_forward_rt<T, 1, BTN>(p, grid, S, coeffs, s);
     if (rt == 2) return launch_forward_rt<T, 2, BTN>(p, grid, S, coeffs, s);
@@ -586,8 +603,8 @@ hipError_t launch_beta_forward(const BetaParams<T>& p, const cpx<T>* S, cpx<T>* 
 template <class T>
 hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx<T>* S, hipStream_t s) {
   constexpr int BTW = BetaCfg<T>::BT;                             // widest signal tile
-  constexpr int BTN = BTW > 16 ? 16 : BTW;                         // for batches of at most 16
-  const int bt = p.batch <= BTN ? BTN : BTW;
+  constexpr int BTN = BTW > 16 ? 16 : BTW;                         // narrow tiles (narrow_tiles)
+  const int bt = narrow_tiles(p, p.ntiles - p.tile0) ? BTN : BTW;
   const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt));
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);

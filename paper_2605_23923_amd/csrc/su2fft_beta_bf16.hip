@@ -456,7 +456,10 @@ hipError_t launch_beta_forward_bf16x3(const BetaParams<float>& p, const unsigned
 
 hipError_t launch_beta_inverse_bf16x3(const BetaParams<float>& p, const unsigned* tabi, const cpx<float>* coeffs,
                                       cpx<float>* S, hipStream_t s) {
-  const bool narrow = p.batch <= 16;  // 16-signal tiles
+  // 16-signal tiles for batches of at most 16, and where the widest would
+  // leave fewer than 1.5 workgroups per CU (as for the FP32 contractions)
+  const bool narrow =
+      p.batch <= 16 || 2LL * (p.ntiles - p.tile0) * ((p.batch + XB_BT - 1) / XB_BT) < 3LL * device_cus();
   const int bt = narrow ? 16 : XB_BT;
   const dim3 grid(contraction_grid(p.ntiles - p.tile0, (p.batch + bt - 1) / bt));
   const int lq2 = beta_bf16_lq(p.B);
