@@ -182,11 +182,12 @@ struct CoefRound {
 // while the matrix cores work on chunk c.
 constexpr int FWD_THREADS = 512;
 
-// KC: beta nodes per streamed chunk.  4 in FP32 when the grid has at least
-// 1.5 workgroups per CU (fewer prefetch registers, two resident workgroups:
-// measured 14 % faster than 8 at B = 64 batch 32), otherwise 8 (more bytes
-// in flight per workgroup: measured better for grids of one workgroup per
-// CU); 8 in FP64 (measured 8 % faster than 4).
+// KC: beta nodes per streamed chunk.  4 when the grid has at least 1.5
+// workgroups per CU (fewer prefetch registers, two resident workgroups: FP32
+// measured 14 % faster than 8 at B = 64 batch 32, FP64 19 % once its pair
+// descriptors sit in scalar registers: 114 instead of 144 VGPRs), otherwise
+// 8 (more bytes in flight per workgroup: measured better for grids of one
+// workgroup per CU).  fwd_kc_default is the mixed plans' default.
 template <class T>
 constexpr int fwd_kc_default() { return sizeof(T) == 4 ? 4 : 8; }
 
@@ -229,7 +230,8 @@ __device__ __forceinline__ void beta_forward_body(const cpx<T>* __restrict__ S, 
 
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform: the pairs' descriptors load into scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
   const PairInfo p0 = p.pairs[tile * PT];
@@ -564,11 +566,9 @@ static hipError_t launch_forward_shape(const BetaParams<T>& p, dim3 grid, const 
 template <class T, int RTMAX, int BT>
 static hipError_t launch_forward_rt(const BetaParams<T>& p, dim3 grid, const cpx<T>* S, cpx<T>* coeffs,
                                     hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-    // two resident workgroups per CU pay off once most CUs get two (grids
-    // of at least 1.5 workgroups per CU)
-    if (2LL * grid.x >= 3LL * device_cus()) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
-  }
+  // two resident workgroups per CU pay off once most CUs get two (grids of
+  // at least 1.5 workgroups per CU)
+  if (2LL * grid.x >= 3LL * device_cus()) return launch_forward_shape<T, RTMAX, 4, BT>(p, grid, S, coeffs, s);
   return launch_forward_shape<T, RTMAX, 8, BT>(p, grid, S, coeffs, s);
 }
 

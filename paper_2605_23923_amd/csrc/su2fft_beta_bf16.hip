@@ -85,7 +85,8 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
 
   const int b0 = bt * BT;
   const int nb = min(BT, p.batch - b0);
-  const int wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform: the pairs' descriptors load into scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lrow = lane & 15, lg = lane >> 4;
   const int N = p.N;
   const int NB8 = (N + 7) / 8;
@@ -110,37 +111,48 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
 #pragma unroll
       for (int ct = 0; ct < CT; ct++) acc[i][rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  float4 sreg[SPT];
-  auto fetch = [&](int k0) {
+  // HALF: the next chunk's first half is requested before the current
+  // chunk's products and its second half after them, so that the prefetch
+  // holds half the registers
+  constexpr bool HALF = RTMAX == 2 && !EARLY;
+  constexpr int SH = HALF ? SPT / 2 : SPT;
+  float4 sreg[SH];
+  auto fetch = [&](int k0, int h) {
 #pragma unroll
-    for (int i = 0; i < SPT; i++) {
+    for (int ii = 0; ii < SH; ii++) {
+      const int i = h * SH + ii;
       const int v = tid + XB_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       const int k = k0 + kk;
       if (k < N && bb < nb)
-        sreg[i] = *reinterpret_cast<const float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
+        sreg[ii] = *reinterpret_cast<const float4*>(S + (((size_t)tile * N + k) * p.batch + b0 + bb) * PT + pv * VC);
       else
-        sreg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sreg[ii] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  auto commit = [&]() {
+  auto commit = [&](int h) {
 #pragma unroll
-    for (int i = 0; i < SPT; i++) {
+    for (int ii = 0; ii < SH; ii++) {
+      const int i = h * SH + ii;
       const int v = tid + XB_THREADS * i;
       const int kk = v / (BT * PT / VC), rem = v - kk * (BT * PT / VC);
       const int bb = rem / (PT / VC), pv = rem - bb * (PT / VC);
       float* d = sS + kk * PK + bb * PB + 2 * pv * VC;
-      d[0] = sreg[i].x; d[1] = sreg[i].y; d[2] = sreg[i].z; d[3] = sreg[i].w;
+      d[0] = sreg[ii].x; d[1] = sreg[ii].y; d[2] = sreg[ii].z; d[3] = sreg[ii].w;
     }
   };
 
   const int nchunk = (N + KC - 1) / KC;
-  fetch(0);
-  commit();
+  fetch(0, 0);
+  commit(0);
+  if constexpr (HALF) {
+    fetch(0, 1);
+    commit(1);
+  }
   for (int c = 0; c < nchunk; c++) {
     __syncthreads();
-    if (c + 1 < nchunk) fetch((c + 1) * KC);
+    if (c + 1 < nchunk) fetch((c + 1) * KC, 0);
     const int kb = c * (KC / 8) + lg;  // this lane's group of 8 nodes
     // the chunk's table operands of both pairs, requested together before
     // any of them is used (an index out of range reads the table's first
@@ -203,7 +215,13 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
       }
     }
     __syncthreads();
-    if (c + 1 < nchunk) commit();
+    if (c + 1 < nchunk) {
+      commit(0);
+      if constexpr (HALF) {
+        fetch((c + 1) * KC, 1);
+        commit(1);
+      }
+    }
   }
 
   // epilogue: the coefficients leave through LDS (CoefRound), 8 degrees of
@@ -233,7 +251,7 @@ __device__ __forceinline__ void beta_forward_bf16x3_body(const cpx<float>* __res
 }
 
 template <int RTMAX>
-__global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_kernel(const cpx<float>* __restrict__ S,
+__global__ __launch_bounds__(XB_THREADS, RTMAX == 2 ? 4 : 1) void beta_forward_bf16x3_kernel(const cpx<float>* __restrict__ S,
                                                                          cpx<float>* __restrict__ coeffs,
                                                                          BetaParams<float> p,
                                                                          const unsigned* __restrict__ tabf) {
