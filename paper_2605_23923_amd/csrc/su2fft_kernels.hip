@@ -4,18 +4,18 @@
 // A mixed plan groups its signals by bandlimit B.  Each group has the tables
 // and the ring-spectrum workspace of a single-B plan; its signals stay where
 // the caller put them (concatenated in order), reached through per-signal
-// offset tables.  A transform runs as two persistent work-list kernels: one
-// walks every (group, signal, node) ring task, the other every (group, pair
-// tile, signal tile) contraction task, each calling the same kernel bodies as
-// the single-B launches (so every signal's result is bit-identical to a
-// single-B plan's); the rings of N = 256 groups run the single-B plan's own
-// N = 256 kernels beside the work lists.  Tasks are ordered by decreasing cost and taken in a
-// static stride by a grid of `knob x CUs` workgroups, or (knob 0) one
-// workgroup per task; the knob of each kernel is chosen by timing the
-// candidates at plan creation (autotuner, cached per device, mode and
-// bandlimit mix, optionally on disk).  The two launches of a
-// call are captured once into a HIP graph per (direction, buffers, stream)
-// and replayed.
+// offset tables.  A transform runs as work lists: one of (group, signal,
+// node) ring tasks per ring kernel family, and the (group, pair tile, signal
+// tile) contraction tasks split by contraction shape class, each launch
+// calling the same kernel bodies as the single-B launches (so every signal's
+// result is bit-identical to a single-B plan's); the rings of N = 256 groups
+// run the single-B plan's own N = 256 kernels beside the work lists.  Tasks
+// are ordered by decreasing cost and taken in a static stride by a grid of
+// `knob x CUs` workgroups, or (knob 0) one workgroup per task; the knob of
+// each kernel is chosen by timing the candidates at plan creation
+// (autotuner, cached per device, mode and bandlimit mix, optionally on
+// disk).  The launches of a call are captured once into a HIP graph per
+// (direction, buffers, stream) and replayed.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -61,8 +61,10 @@ struct GroupDev {
 
 // ---- work-list kernels ----
 
-// Ring tasks come in two lists, one per ring kernel family, so that each
-// work-list kernel keeps the register budget of its single-B counterpart.
+// Ring tasks come in two lists, one per ring kernel family, and every
+// contraction launch carries one shape class (row tiles RTC, degree groups
+// LQC / LQ2C) and holds only that class's bodies, so that each work-list
+// kernel keeps the register budget of its single-B counterpart.
 // dir 0: forward (in = samples -> workspaces); 1: inverse, 2: adjoint (workspaces -> out = samples)
 // REAL: real-signal plans (the half-spectrum form of the register-resident rings)
 template <class T, bool FWD, bool REAL>
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(GENERIC_NT) void ring_generic_worklist_kernel(const
   }
 }
 
-template <class T, int RTMAX_MAX, int KC>
+template <class T, int RTC, int KC>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             cpx<T>* __restrict__ coeffs) {
@@ -129,24 +131,26 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
     const GroupDev<T>& g = groups[w.g];
     if (g.narrow_f) {
       if constexpr (BetaCfg<T>::BT > 16) {
-        if (g.rtmax == 1) beta_forward_body<T, 1, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-        if constexpr (RTMAX_MAX >= 2)
+        if constexpr (RTC == 1)
+          if (g.rtmax == 1) beta_forward_body<T, 1, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+        if constexpr (RTC == 2)
           if (g.rtmax == 2) beta_forward_body<T, 2, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-        if constexpr (RTMAX_MAX >= 4)
+        if constexpr (RTC == 4)
           if (g.rtmax == 4) beta_forward_body<T, 4, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
       }
     } else {
-      if (g.rtmax == 1) beta_forward_body<T, 1, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-      if constexpr (RTMAX_MAX >= 2)
+      if constexpr (RTC == 1)
+        if (g.rtmax == 1) beta_forward_body<T, 1, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      if constexpr (RTC == 2)
         if (g.rtmax == 2) beta_forward_body<T, 2, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-      if constexpr (RTMAX_MAX >= 4)
+      if constexpr (RTC == 4)
         if (g.rtmax == 4) beta_forward_body<T, 4, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
 }
 
-template <class T, int LQ_MAX>
+template <class T, int LQC>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             const cpx<T>* __restrict__ coeffs, int dir) {
@@ -159,28 +163,30 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     const BetaParams<T>& p = g.bp[dir];
     if (g.narrow_i) {
       if constexpr (BetaCfg<T>::BT > 16) {
-        if (g.lq == 2) beta_inverse_body<T, 2, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQ_MAX >= 4)
+        if constexpr (LQC == 2)
+          if (g.lq == 2) beta_inverse_body<T, 2, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+        if constexpr (LQC == 4)
           if (g.lq == 4) beta_inverse_body<T, 4, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQ_MAX >= 8)
+        if constexpr (LQC == 8)
           if (g.lq == 8) beta_inverse_body<T, 8, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQ_MAX >= 16)
+        if constexpr (LQC == 16)
           if (g.lq == 16) beta_inverse_body<T, 16, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
       }
     } else {
-      if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQ_MAX >= 4)
+      if constexpr (LQC == 2)
+        if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
+      if constexpr (LQC == 4)
         if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQ_MAX >= 8)
+      if constexpr (LQC == 8)
         if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQ_MAX >= 16)
+      if constexpr (LQC == 16)
         if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
     }
     __syncthreads();
   }
 }
 
-template <int RTMAX_MAX>
+template <int RTC>
 __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups, cpx<float>* __restrict__ coeffs) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -189,16 +195,17 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kerne
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.rtmax == 1) beta_forward_bf16x3_body<1>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
-    if constexpr (RTMAX_MAX >= 2)
+    if constexpr (RTC == 1)
+      if (g.rtmax == 1) beta_forward_bf16x3_body<1>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
+    if constexpr (RTC == 2)
       if (g.rtmax == 2) beta_forward_bf16x3_body<2>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
-    if constexpr (RTMAX_MAX >= 4)
+    if constexpr (RTC == 4)
       if (g.rtmax == 4) beta_forward_bf16x3_body<4, false>(g.S, coeffs, g.bp[0], g.tabf_bf, w.a, w.b, smem, t);
     __syncthreads();
   }
 }
 
-template <int LQ2_MAX>
+template <int LQ2C>
 __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups,
     const cpx<float>* __restrict__ coeffs, int dir) {
@@ -209,12 +216,14 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
     if (g.narrow_i) {
-      if (g.lq2 == 1) beta_inverse_bf16x3_body<1, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-      if constexpr (LQ2_MAX >= 2)
+      if constexpr (LQ2C == 1)
+        if (g.lq2 == 1) beta_inverse_bf16x3_body<1, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      if constexpr (LQ2C == 2)
         if (g.lq2 == 2) beta_inverse_bf16x3_body<2, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     } else {
-      if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-      if constexpr (LQ2_MAX >= 2)
+      if constexpr (LQ2C == 1)
+        if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      if constexpr (LQ2C == 2)
         if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     }
     __syncthreads();
