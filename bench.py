@@ -14,7 +14,8 @@ around the K timed steps (bracketed by device synchronisation).  Every kernel
 is bracketed by HIP events on the stream it runs on; `roofline` reports the
 kernel with the largest share of the step against the HBM peak, with its
 algorithmic bytes per launch.  `cpu_baseline` times the CPU oracle (direct
-quadrature sum) on a bounded sample of the same forward workload, and
+quadrature sum) on a bounded sample of the same forward workload on all host
+cores (`cpu_baseline_1core`: on one), and
 `cpu_fft_baseline` a plain CPU FFT-based separated transform (float64) beside it
 (`cpu_fft_baselines`: float64 and float32, forward and inverse).
 """
@@ -477,14 +478,23 @@ def measured_peaks():
                       "16x16x4 FP64/FP32 and 16x16x32 BF16 at %d workgroups x 256 threads; best of 5" % wg}
 
 
-def cpu_baseline(B: int, budget_s: float):
+def cpu_baseline(B: int, budget_s: float, threads: int = 0):
     """The oracle's direct sum on a bounded sample: the forward transform of one
     signal restricted to a subset of its coefficients (a few of every 2l), timed
-    on the host; scaled to whole-signal transforms per second."""
+    on the host (all cores, or `threads` of them); scaled to whole-signal
+    transforms per second."""
     import numpy as np
 
     import oracle
     import synth
+
+    if threads:
+        all_threads = oracle.num_threads()
+        oracle.set_num_threads(threads)
+        try:
+            return cpu_baseline(B, budget_s)
+        finally:
+            oracle.set_num_threads(all_threads)
 
     C = B * (B + 1) * (2 * B + 1) // 6
     x = synth.samples_uniform(B, 1, seed=5)[0]
@@ -646,6 +656,7 @@ def main():
         line["other_workloads"] = secondary_configs(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(B, args.cpu_budget)
+        line["cpu_baseline_1core"] = cpu_baseline(B, args.cpu_budget / 3, threads=1)
         fft = cpu_fft_baselines(B)
         line["cpu_fft_baseline"] = fft[0]
         line["cpu_fft_baselines"] = fft

@@ -66,6 +66,8 @@ def _load():
     lib.orc_synth.argtypes = [ctypes.c_int, dp, ctypes.c_int, i64, lp, dp]
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -80,6 +82,11 @@ def _lptr(a):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def num_coeffs(B: int) -> int:

@@ -298,3 +298,14 @@ int orc_num_threads(void) {
   return 0;
 #endif
 }
+
+/* Set the number of OpenMP threads of later calls (n >= 1; ignored without
+ * OpenMP).  Timing only: results do not depend on it. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
