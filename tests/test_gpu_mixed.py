@@ -174,6 +174,16 @@ def test_mixed_real_and_so3_bitwise_equal_single_plans(kind, dtype):
         p.close()
 
 
+def test_pinned_grid_rejects_values_the_search_cannot_choose():
+    """SU2_GRID must name four candidates (0, 1, 2, 3, 4, 6, 8): anything else
+    is ignored and the plan keeps its defaults."""
+    for bad in ("5,5,5,5", "1,2,3", "-1,0,0,0", "x"):
+        with _env(SU2_AUTOTUNE="0", SU2_GRID=bad):
+            mp = su2.MixedPlan([16, 24], "c64")
+        assert mp.tuning() == [2, 2, 2, 2], bad
+        mp.close()
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64", "c64_bf16x3"])
 def test_mixed_with_b128_groups(dtype):
     """B = 128 groups in a mixed plan run the single-B plan's N = 256 ring

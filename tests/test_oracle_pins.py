@@ -363,3 +363,23 @@ def test_coefficient_layout_is_a_bijection():
         assert seen == list(range(oracle.num_coeffs(B)))
         assert oracle.num_coeffs(B) == B * (B + 1) * (2 * B + 1) // 6
     assert oracle.coeff_index(2, 1, 0) == -1 and oracle.coeff_index(1, 3, 1) == -1
+
+
+def test_thread_count_does_not_change_results():
+    """The CPU baselines time the oracle on one core and on all of them; its
+    sums are per-coefficient and per-sample, so the thread count changes no
+    bit of a result."""
+    B = 4
+    rng = np.random.default_rng(81)
+    N = 2 * B
+    x = rng.standard_normal(N ** 3) + 1j * rng.standard_normal(N ** 3)
+    C = oracle.num_coeffs(B)
+    c = rng.standard_normal(C) + 1j * rng.standard_normal(C)
+    full = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        f1, i1 = oracle.forward(B, x), oracle.inverse(B, c)
+    finally:
+        oracle.set_num_threads(max(full, 1))
+    assert np.array_equal(f1, oracle.forward(B, x))
+    assert np.array_equal(i1, oracle.inverse(B, c))
