@@ -401,9 +401,16 @@ constexpr size_t inverse_smem() { return (size_t)16 * InvStage<T>::NRS * sizeof(
 
 // BT signals per workgroup: BetaCfg<T>::BT, or 16 for FP32 batches of at
 // most 16, which would leave half of a 32-signal tile's columns empty.
-template <class T, int LQ, int BT = BetaCfg<T>::BT>
+// WPP pairs per wave: 2 (8 waves, INV_THREADS threads) or 1 (16 waves):
+// one pair per wave halves the coefficient operands each lane holds, which
+// lets FP64 with 17-32 degrees keep 16 waves per CU instead of 8.
+template <int WPP>
+constexpr int inverse_threads() { return 64 * PT / WPP; }
+
+template <class T, int LQ, int BT = BetaCfg<T>::BT, int WPP = 2>
 __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
                                                   const BetaParams<T>& p, int tile, int bt, unsigned char* smem, int tid) {
+  constexpr int NTH = inverse_threads<WPP>(), PW = PT / WPP;  // threads; pair stride between a wave's pairs
   typedef typename acc4<T>::type accT;
   constexpr int CT = 2 * BT / 16;
   static_assert(BT <= BetaCfg<T>::BT && BT % 8 == 0, "signal tile");
@@ -415,10 +422,10 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   const int lrow = lane & 15, lk = lane >> 4;
   const int N = p.N;
 
-  PairInfo pi[2];
+  PairInfo pi[WPP];
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
-    pi[q] = p.pairs[tile * PT + wave + 8 * q];
+  for (int q = 0; q < WPP; q++) {
+    pi[q] = p.pairs[tile * PT + wave + PW * q];
     if (p.real && mirrored_pair(pi[q].tm, pi[q].tn)) pi[q].L = 0;
   }
 
@@ -432,10 +439,10 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   // also fetches late: without the second set the kernel fits 128 VGPRs and
   // two workgroups share a CU (B = 128 batch 16: 0.502 -> 0.474 ms).
   constexpr bool EARLY = sizeof(T) * LQ <= 64 && !(LQ == 16 && BT == 16);
-  T av[2][LQ], avn[2][LQ];
-  auto fetch_a = [&](T (&dst)[2][LQ], int kb) {
+  T av[WPP][LQ], avn[WPP][LQ];
+  auto fetch_a = [&](T (&dst)[WPP][LQ], int kb) {
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < WPP; q++) {
       const T* src = p.tabi + pi[q].itab + (long long)kb * ((pi[q].L + 3) / 4) * 64 + lane;
 #pragma unroll
       for (int s = 0; s < LQ; s++) {
@@ -449,19 +456,19 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   // B operands: the scaled coefficients of the wave's two pairs, gathered
   // through LDS (CoefRound) in rounds of 8 degrees of all 16 pairs
   constexpr int J = 4 * LQ;  // degrees held per pair
-  typedef CoefRound<T, BT, INV_THREADS> CR;
+  typedef CoefRound<T, BT, NTH> CR;
   static_assert(CR::ELEMS <= (size_t)16 * NRS && J % CR::JC == 0, "coefficient rounds fit in the stage buffer");
-  T bop[2][LQ][CT];
+  T bop[WPP][LQ][CT];
 #pragma unroll
   for (int j0 = 0; j0 < J; j0 += CR::JC) {
     CR::gather(coeffs, p, tile, j0, b0, nb, stage, tid);
 #pragma unroll
-    for (int h = 0; h < 2; h++)
+    for (int h = 0; h < WPP; h++)
 #pragma unroll
       for (int s = j0 / 4; s < (j0 + CR::JC) / 4; s++)
 #pragma unroll
         for (int ct = 0; ct < CT; ct++)
-          bop[h][s][ct] = stage[(wave + 8 * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
+          bop[h][s][ct] = stage[(wave + PW * h) * CR::PS + (4 * s - j0 + lk) * CR::CWP + ct * 16 + lrow];
     __syncthreads();
   }
 
@@ -470,7 +477,7 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   // check drops them; every lane issues the same unconditional stores
   constexpr int VC = 16 / (int)sizeof(cpx<T>);
   constexpr int NV = 16 * BT * (PT / VC);  // 16-byte stores per block of 16 nodes
-  static_assert(NV % INV_THREADS == 0, "store split");
+  static_assert(NV % NTH == 0, "store split");
   const long long slab = (long long)N * p.batch * PT;
   const __amdgpu_buffer_rsrc_t srsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(S + (size_t)tile * slab), (short)0, (int)(slab * (long long)sizeof(cpx<T>)), BUFFER_RSRC_WORD3);
@@ -478,9 +485,9 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
     if constexpr (EARLY)
       if (k0 + 16 < N) fetch_a(avn, k0 / 16 + 1);
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < WPP; q++) {
       const int L = pi[q].L;
-      const int pp = wave + 8 * q;
+      const int pp = wave + PW * q;
       accT acc[CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ct++)
@@ -511,8 +518,8 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
     int tq = tid;
     asm volatile("" : "+v"(tq));
 #pragma unroll
-    for (int i = 0; i < NV / INV_THREADS; i++) {
-      const int v = tq + INV_THREADS * i;
+    for (int i = 0; i < NV / NTH; i++) {
+      const int v = tq + NTH * i;
       const int row = v / (PT / VC), pv = v - row * (PT / VC);
       const int kk = row / BT, bb = row - kk * BT;
       const int k = k0 + kk;
@@ -529,22 +536,22 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
     __syncthreads();
     if constexpr (EARLY) {
 #pragma unroll
-      for (int q = 0; q < 2; q++)
+      for (int q = 0; q < WPP; q++)
 #pragma unroll
         for (int s = 0; s < LQ; s++) av[q][s] = avn[q][s];
     }
   }
 }
 
-template <class T, int LQ, int BT>
-__global__ __launch_bounds__(INV_THREADS) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
-                                                                   cpx<T>* __restrict__ S, BetaParams<T> p) {
+template <class T, int LQ, int BT, int WPP>
+__global__ __launch_bounds__(inverse_threads<WPP>()) void beta_inverse_kernel(const cpx<T>* __restrict__ coeffs,
+                                                                              cpx<T>* __restrict__ S, BetaParams<T> p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the inverse keeps the natural order (tiles with a shared block far apart
   // in time): measured 2-3 % faster than pairing them, unlike the forward
   const TileSlot sl = contraction_slot(blockIdx.x, p.ntiles - p.tile0, (p.batch + BT - 1) / BT);
   if (!sl.valid) return;
-  beta_inverse_body<T, LQ, BT>(coeffs, S, p, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
+  beta_inverse_body<T, LQ, BT, WPP>(coeffs, S, p, p.tile0 + sl.tile, sl.bt, smem_raw, threadIdx.x);
 }
 
 // allow the kernel `smem` bytes of dynamic LDS (beyond the 64 KB default)
@@ -609,11 +616,16 @@ hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);
   hipError_t e;
-#define SU2_INV_CASE(Q, BTC)                                                                            \
-  if (lq == Q && bt == BTC) {                                                                           \
-    if ((e = set_smem(beta_inverse_kernel<T, Q, BTC>, smem)) != hipSuccess) return e;                   \
-    hipLaunchKernelGGL((beta_inverse_kernel<T, Q, BTC>), grid, dim3(INV_THREADS), smem, s, coeffs, S, p); \
-    return hipGetLastError();                                                                           \
+  // one pair per wave for FP64 with 17-32 degrees (B = 33-64): 110 instead of
+  // 176 VGPRs, 16 waves per CU instead of 8 (B = 64 batch 32: 0.187 -> 0.167
+  // ms; with fewer degrees the 8-wave form is as fast or faster)
+#define SU2_INV_CASE(Q, BTC)                                                                             \
+  if (lq == Q && bt == BTC) {                                                                            \
+    constexpr int W = (sizeof(T) == 8 && Q == 8) ? 1 : 2;                                                \
+    if ((e = set_smem(beta_inverse_kernel<T, Q, BTC, W>, smem)) != hipSuccess) return e;                 \
+    hipLaunchKernelGGL((beta_inverse_kernel<T, Q, BTC, W>), grid, dim3(inverse_threads<W>()), smem, s, coeffs, \
+                       S, p);                                                                            \
+    return hipGetLastError();                                                                            \
   }
   SU2_INV_CASE(2, BTW)
   SU2_INV_CASE(4, BTW)

@@ -24,7 +24,7 @@ def _report():
 def test_report_covers_the_transform_kernels():
     names = " ".join(_report())
     for k in ("ring_forward_fast<float, 64, false>", "ring_inverse_fast<double, 128, false>",
-              "beta_forward_kernel<float, 2, 4, 32>", "beta_inverse_kernel<double, 16, 16>", "beta_forward_bf16x3_kernel<4>",
+              "beta_forward_kernel<float, 2, 4, 32>", "beta_inverse_kernel<double, 16, 16, 2>", "beta_inverse_kernel<double, 8, 16, 1>", "beta_forward_bf16x3_kernel<4>",
               "ring_cols_forward_large<float>", "beta_forward_otf_kernel<float, 2, 32>"):
         assert k in names, k
 
