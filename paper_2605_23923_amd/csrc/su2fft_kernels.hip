@@ -150,7 +150,11 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
   }
 }
 
-template <class T, int LQC>
+// inverse work lists: one launch per (degree class, tile width), so that a
+// launch holds the one body its tasks run (the 32-signal body of 8 degree
+// groups alone would raise the 16-signal tasks to 130 VGPRs, one workgroup
+// per CU)
+template <class T, int LQC, bool NAR>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             const cpx<T>* __restrict__ coeffs, int dir) {
@@ -160,27 +164,11 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    const BetaParams<T>& p = g.bp[dir];
-    if (g.narrow_i) {
-      if constexpr (BetaCfg<T>::BT > 16) {
-        if constexpr (LQC == 2)
-          if (g.lq == 2) beta_inverse_body<T, 2, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQC == 4)
-          if (g.lq == 4) beta_inverse_body<T, 4, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQC == 8)
-          if (g.lq == 8) beta_inverse_body<T, 8, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-        if constexpr (LQC == 16)
-          if (g.lq == 16) beta_inverse_body<T, 16, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
-      }
-    } else {
-      if constexpr (LQC == 2)
-        if (g.lq == 2) beta_inverse_body<T, 2>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQC == 4)
-        if (g.lq == 4) beta_inverse_body<T, 4>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQC == 8)
-        if (g.lq == 8) beta_inverse_body<T, 8>(coeffs, g.S, p, w.a, w.b, smem, t);
-      if constexpr (LQC == 16)
-        if (g.lq == 16) beta_inverse_body<T, 16>(coeffs, g.S, p, w.a, w.b, smem, t);
+    if (g.lq == LQC && (g.narrow_i != 0) == NAR) {
+      if constexpr (NAR)
+        beta_inverse_body<T, LQC, 16>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
+      else
+        beta_inverse_body<T, LQC>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -205,7 +193,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kerne
   }
 }
 
-template <int LQ2C>
+template <int LQ2C, bool NAR>
 __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups,
     const cpx<float>* __restrict__ coeffs, int dir) {
@@ -215,16 +203,11 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.narrow_i) {
-      if constexpr (LQ2C == 1)
-        if (g.lq2 == 1) beta_inverse_bf16x3_body<1, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-      if constexpr (LQ2C == 2)
-        if (g.lq2 == 2) beta_inverse_bf16x3_body<2, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-    } else {
-      if constexpr (LQ2C == 1)
-        if (g.lq2 == 1) beta_inverse_bf16x3_body<1>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-      if constexpr (LQ2C == 2)
-        if (g.lq2 == 2) beta_inverse_bf16x3_body<2>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+    if (g.lq2 == LQ2C && (g.narrow_i != 0) == NAR) {
+      if constexpr (NAR)
+        beta_inverse_bf16x3_body<LQ2C, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      else
+        beta_inverse_bf16x3_body<LQ2C>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -256,11 +239,12 @@ struct MixedState {
   // (one-pass sliced in FP32, two-pass in FP64) instead of a work list
   std::vector<int> dedicated;
   // the contraction lists in runs of one shape class (forward: row tiles;
-  // inverse: degrees per group), largest class first: a run is one launch of
-  // the kernel built for exactly that class, so that the small bandlimits
-  // keep the registers, and the occupancy, of their single-B kernels
+  // inverse: degrees per group and tile width), largest class first: a run
+  // is one launch of the kernel built for exactly that class, so that the
+  // small bandlimits keep the registers, and the occupancy, of their
+  // single-B kernels
   struct Run {
-    int cls, begin, n;
+    int cls, nar, begin, n;  // nar: 16-signal tiles (inverse runs only)
   };
   std::vector<Run> runs_f, runs_i;
   size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
@@ -319,21 +303,26 @@ size_t betaf_smem(int rtmax, int kc) {
     return rtmax <= 1 ? FwdGeom<T, 1, 8>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 8>::SMEM : FwdGeom<T, 4, 8>::SMEM);
   return rtmax <= 1 ? FwdGeom<T, 1, 4>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 4>::SMEM : FwdGeom<T, 4, 4>::SMEM);
 }
+template <class T, bool NAR>
+void* betai_kernel_ptr_w(int lq) {
+  if (lq <= 2) return (void*)beta_inverse_worklist_kernel<T, 2, NAR>;
+  if (lq <= 4) return (void*)beta_inverse_worklist_kernel<T, 4, NAR>;
+  if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8, NAR>;
+  return (void*)beta_inverse_worklist_kernel<T, 16, NAR>;
+}
 template <class T>
-void* betai_kernel_ptr(int lq) {
-  if (lq <= 2) return (void*)beta_inverse_worklist_kernel<T, 2>;
-  if (lq <= 4) return (void*)beta_inverse_worklist_kernel<T, 4>;
-  if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8>;
-  return (void*)beta_inverse_worklist_kernel<T, 16>;
+void* betai_kernel_ptr(int lq, int nar) {
+  return nar ? betai_kernel_ptr_w<T, true>(lq) : betai_kernel_ptr_w<T, false>(lq);
 }
 void* betaf_bf16_kernel_ptr(int rtmax) {
   if (rtmax <= 1) return (void*)beta_forward_bf16x3_worklist_kernel<1>;
   if (rtmax <= 2) return (void*)beta_forward_bf16x3_worklist_kernel<2>;
   return (void*)beta_forward_bf16x3_worklist_kernel<4>;
 }
-void* betai_bf16_kernel_ptr(int lq2) {
-  if (lq2 <= 1) return (void*)beta_inverse_bf16x3_worklist_kernel<1>;
-  return (void*)beta_inverse_bf16x3_worklist_kernel<2>;
+void* betai_bf16_kernel_ptr(int lq2, int nar) {
+  if (lq2 <= 1)
+    return nar ? (void*)beta_inverse_bf16x3_worklist_kernel<1, true> : (void*)beta_inverse_bf16x3_worklist_kernel<1, false>;
+  return nar ? (void*)beta_inverse_bf16x3_worklist_kernel<2, true> : (void*)beta_inverse_bf16x3_worklist_kernel<2, false>;
 }
 
 // the rings of an N = 256 group with the single-B plan's kernels (d: 0
@@ -422,9 +411,9 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
         } else {
           const WorkItem* items = ms->d_betai + r.begin;
           void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&in, (void*)&dir};
-          e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls), grid_of(r.n), dim3(XB_THREADS), args,
+          e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls, r.nar), grid_of(r.n), dim3(XB_THREADS), args,
                                    ms->smem_betai, rs)
-                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls), grid_of(r.n), dim3(INV_THREADS), args,
+                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls, r.nar), grid_of(r.n), dim3(INV_THREADS), args,
                                    ms->smem_betai, rs);
         }
         if (e != hipSuccess) return e;
@@ -473,7 +462,7 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
       return e;
   for (const MixedState::Run& r : ms->runs_i)
-    if ((e = hipFuncSetAttribute(bf ? betai_bf16_kernel_ptr(r.cls) : betai_kernel_ptr<T>(r.cls),
+    if ((e = hipFuncSetAttribute(bf ? betai_bf16_kernel_ptr(r.cls, r.nar) : betai_kernel_ptr<T>(r.cls, r.nar),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
       return e;
   for (int fwd = 0; fwd < 2; fwd++) {
@@ -594,20 +583,24 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   };
   if ((e = upload(ringf, ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
   if ((e = upload(ringg, ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
-  // contraction lists: by class (largest first), then by decreasing cost; one run per class
+  // contraction lists: by class (largest first; wide inverse tiles before
+  // 16-signal ones), then by decreasing cost; one run per class
   auto upload_runs = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem* dst, int* n,
                          std::vector<MixedState::Run>& runs, bool fwd) -> hipError_t {
     auto cls = [&](const WorkItem& w) { return fwd ? hg[w.g].rtmax : (bf ? hg[w.g].lq2 : hg[w.g].lq); };
+    auto nar = [&](const WorkItem& w) { return fwd ? 0 : hg[w.g].narrow_i; };
     std::stable_sort(lst.begin(), lst.end(), [&](const std::pair<double, WorkItem>& x,
                                                  const std::pair<double, WorkItem>& y) {
       const int cx = cls(x.second), cy = cls(y.second);
-      return cx != cy ? cx > cy : x.first > y.first;
+      if (cx != cy) return cx > cy;
+      const int nx = nar(x.second), ny = nar(y.second);
+      return nx != ny ? nx < ny : x.first > y.first;
     });
     runs.clear();
     std::vector<WorkItem> v;
     for (auto& x : lst) {
-      const int c = cls(x.second);
-      if (runs.empty() || runs.back().cls != c) runs.push_back({c, (int)v.size(), 0});
+      const int c = cls(x.second), a = nar(x.second);
+      if (runs.empty() || runs.back().cls != c || runs.back().nar != a) runs.push_back({c, a, (int)v.size(), 0});
       runs.back().n++;
       v.push_back(x.second);
     }
