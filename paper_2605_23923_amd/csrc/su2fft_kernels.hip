@@ -6,7 +6,7 @@
 // the caller put them (concatenated in order), reached through per-signal
 // offset tables.  A transform runs as work lists: one of (group, signal,
 // node) ring tasks per ring kernel family, and the (group, pair tile, signal
-// tile) contraction tasks split by contraction shape class, each launch
+// tile) contraction tasks split by contraction shape class and tile width, each launch
 // calling the same kernel bodies as the single-B launches (so every signal's
 // result is bit-identical to a single-B plan's); the rings of N = 256 groups
 // run the single-B plan's own N = 256 kernels beside the work lists.  Tasks
@@ -64,7 +64,9 @@ struct GroupDev {
 // Ring tasks come in two lists, one per ring kernel family, and every
 // contraction launch carries one shape class (row tiles RTC, degree groups
 // LQC / LQ2C) and holds only that class's bodies, so that each work-list
-// kernel keeps the register budget of its single-B counterpart.
+// kernel keeps the register budget of its single-B counterpart.  W is the
+// set of signal-tile widths a launch holds: 1 the 16-signal body, 2 the
+// widest, 3 both (each task takes its group's width).
 // dir 0: forward (in = samples -> workspaces); 1: inverse, 2: adjoint (workspaces -> out = samples)
 // REAL: real-signal plans (the half-spectrum form of the register-resident rings)
 template <class T, bool FWD, bool REAL>
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(GENERIC_NT) void ring_generic_worklist_kernel(const
   }
 }
 
-template <class T, int RTC, int KC>
+template <class T, int RTC, int KC, int W>
 __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             cpx<T>* __restrict__ coeffs) {
@@ -129,32 +131,17 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    if (g.narrow_f) {
-      if constexpr (BetaCfg<T>::BT > 16) {
-        if constexpr (RTC == 1)
-          if (g.rtmax == 1) beta_forward_body<T, 1, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-        if constexpr (RTC == 2)
-          if (g.rtmax == 2) beta_forward_body<T, 2, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-        if constexpr (RTC == 4)
-          if (g.rtmax == 4) beta_forward_body<T, 4, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-      }
-    } else {
-      if constexpr (RTC == 1)
-        if (g.rtmax == 1) beta_forward_body<T, 1, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-      if constexpr (RTC == 2)
-        if (g.rtmax == 2) beta_forward_body<T, 2, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
-      if constexpr (RTC == 4)
-        if (g.rtmax == 4) beta_forward_body<T, 4, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+    if (g.rtmax == RTC) {
+      if constexpr ((W & 1) != 0)
+        if (g.narrow_f) beta_forward_body<T, RTC, KC, 16>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
+      if constexpr ((W & 2) != 0)
+        if (!g.narrow_f) beta_forward_body<T, RTC, KC>(g.S, coeffs, g.bp[0], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
 }
 
-// inverse work lists: one launch per (degree class, tile width), so that a
-// launch holds the one body its tasks run (the 32-signal body of 8 degree
-// groups alone would raise the 16-signal tasks to 130 VGPRs, one workgroup
-// per CU)
-template <class T, int LQC, bool NAR>
+template <class T, int LQC, int W>
 __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(const WorkItem* __restrict__ items, int n,
                                                                             const GroupDev<T>* __restrict__ groups,
                                                                             const cpx<T>* __restrict__ coeffs, int dir) {
@@ -164,11 +151,11 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
-    if (g.lq == LQC && (g.narrow_i != 0) == NAR) {
-      if constexpr (NAR)
-        beta_inverse_body<T, LQC, 16>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
-      else
-        beta_inverse_body<T, LQC>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
+    if (g.lq == LQC) {
+      if constexpr ((W & 1) != 0)
+        if (g.narrow_i) beta_inverse_body<T, LQC, 16>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
+      if constexpr ((W & 2) != 0)
+        if (!g.narrow_i) beta_inverse_body<T, LQC>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -193,7 +180,7 @@ __global__ __launch_bounds__(XB_THREADS) void beta_forward_bf16x3_worklist_kerne
   }
 }
 
-template <int LQ2C, bool NAR>
+template <int LQ2C, int W>
 __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kernel(
     const WorkItem* __restrict__ items, int n, const GroupDev<float>* __restrict__ groups,
     const cpx<float>* __restrict__ coeffs, int dir) {
@@ -203,11 +190,11 @@ __global__ __launch_bounds__(XB_THREADS) void beta_inverse_bf16x3_worklist_kerne
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<float>& g = groups[w.g];
-    if (g.lq2 == LQ2C && (g.narrow_i != 0) == NAR) {
-      if constexpr (NAR)
-        beta_inverse_bf16x3_body<LQ2C, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
-      else
-        beta_inverse_bf16x3_body<LQ2C>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+    if (g.lq2 == LQ2C) {
+      if constexpr ((W & 1) != 0)
+        if (g.narrow_i) beta_inverse_bf16x3_body<LQ2C, 16>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
+      if constexpr ((W & 2) != 0)
+        if (!g.narrow_i) beta_inverse_bf16x3_body<LQ2C>(coeffs, g.S, g.bp[dir], g.tabi_bf, w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -239,12 +226,16 @@ struct MixedState {
   // (one-pass sliced in FP32, two-pass in FP64) instead of a work list
   std::vector<int> dedicated;
   // the contraction lists in runs of one shape class (forward: row tiles;
-  // inverse: degrees per group and tile width), largest class first: a run
-  // is one launch of the kernel built for exactly that class, so that the
-  // small bandlimits keep the registers, and the occupancy, of their
-  // single-B kernels
+  // inverse: degrees per group), largest class first: a run is one launch of
+  // the kernel built for exactly that class, so that the small bandlimits
+  // keep the registers, and the occupancy, of their single-B kernels.  A
+  // class whose groups use both signal-tile widths runs as one launch
+  // holding both bodies, unless that kernel fits fewer than two workgroups
+  // per CU and the 16-signal body alone fits more: then the two widths are
+  // two runs (the 32-signal body takes 195 VGPRs in the FP32 forward of
+  // 65-128 degrees, the 16-signal one 119)
   struct Run {
-    int cls, nar, begin, n;  // nar: 16-signal tiles (inverse runs only)
+    int cls, w, begin, n;  // w: tile widths held (1: 16 signals, 2: widest, 3: both)
   };
   std::vector<Run> runs_f, runs_i;
   size_t smem_ringf = 0, smem_ringg = 0, smem_betaf = 0, smem_betai = 0;
@@ -286,16 +277,22 @@ void* ringg_kernel_ptr(bool fwd) {
   return fwd ? (void*)ring_generic_worklist_kernel<T, true> : (void*)ring_generic_worklist_kernel<T, false>;
 }
 
+template <class T, int KC, int W>
+void* betaf_kernel_ptr_w(int rtmax) {
+  if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1, KC, W>;
+  if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2, KC, W>;
+  return (void*)beta_forward_worklist_kernel<T, 4, KC, W>;
+}
+template <class T, int KC>
+void* betaf_kernel_ptr_k(int rtmax, int w) {
+  if constexpr (BetaCfg<T>::BT == 16) return betaf_kernel_ptr_w<T, KC, 2>(rtmax);  // one width
+  else
+    return w == 1 ? betaf_kernel_ptr_w<T, KC, 1>(rtmax)
+                  : (w == 2 ? betaf_kernel_ptr_w<T, KC, 2>(rtmax) : betaf_kernel_ptr_w<T, KC, 3>(rtmax));
+}
 template <class T>
-void* betaf_kernel_ptr(int rtmax, int kc) {
-  if (kc == 8) {
-    if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1, 8>;
-    if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2, 8>;
-    return (void*)beta_forward_worklist_kernel<T, 4, 8>;
-  }
-  if (rtmax <= 1) return (void*)beta_forward_worklist_kernel<T, 1, 4>;
-  if (rtmax <= 2) return (void*)beta_forward_worklist_kernel<T, 2, 4>;
-  return (void*)beta_forward_worklist_kernel<T, 4, 4>;
+void* betaf_kernel_ptr(int rtmax, int kc, int w) {
+  return kc == 8 ? betaf_kernel_ptr_k<T, 8>(rtmax, w) : betaf_kernel_ptr_k<T, 4>(rtmax, w);
 }
 template <class T>
 size_t betaf_smem(int rtmax, int kc) {
@@ -303,26 +300,43 @@ size_t betaf_smem(int rtmax, int kc) {
     return rtmax <= 1 ? FwdGeom<T, 1, 8>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 8>::SMEM : FwdGeom<T, 4, 8>::SMEM);
   return rtmax <= 1 ? FwdGeom<T, 1, 4>::SMEM : (rtmax <= 2 ? FwdGeom<T, 2, 4>::SMEM : FwdGeom<T, 4, 4>::SMEM);
 }
-template <class T, bool NAR>
+template <class T, int W>
 void* betai_kernel_ptr_w(int lq) {
-  if (lq <= 2) return (void*)beta_inverse_worklist_kernel<T, 2, NAR>;
-  if (lq <= 4) return (void*)beta_inverse_worklist_kernel<T, 4, NAR>;
-  if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8, NAR>;
-  return (void*)beta_inverse_worklist_kernel<T, 16, NAR>;
+  if (lq <= 2) return (void*)beta_inverse_worklist_kernel<T, 2, W>;
+  if (lq <= 4) return (void*)beta_inverse_worklist_kernel<T, 4, W>;
+  if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8, W>;
+  return (void*)beta_inverse_worklist_kernel<T, 16, W>;
 }
 template <class T>
-void* betai_kernel_ptr(int lq, int nar) {
-  return nar ? betai_kernel_ptr_w<T, true>(lq) : betai_kernel_ptr_w<T, false>(lq);
+void* betai_kernel_ptr(int lq, int w) {
+  if constexpr (BetaCfg<T>::BT == 16) return betai_kernel_ptr_w<T, 2>(lq);  // one width
+  else
+    return w == 1 ? betai_kernel_ptr_w<T, 1>(lq) : (w == 2 ? betai_kernel_ptr_w<T, 2>(lq) : betai_kernel_ptr_w<T, 3>(lq));
 }
 void* betaf_bf16_kernel_ptr(int rtmax) {
   if (rtmax <= 1) return (void*)beta_forward_bf16x3_worklist_kernel<1>;
   if (rtmax <= 2) return (void*)beta_forward_bf16x3_worklist_kernel<2>;
   return (void*)beta_forward_bf16x3_worklist_kernel<4>;
 }
-void* betai_bf16_kernel_ptr(int lq2, int nar) {
-  if (lq2 <= 1)
-    return nar ? (void*)beta_inverse_bf16x3_worklist_kernel<1, true> : (void*)beta_inverse_bf16x3_worklist_kernel<1, false>;
-  return nar ? (void*)beta_inverse_bf16x3_worklist_kernel<2, true> : (void*)beta_inverse_bf16x3_worklist_kernel<2, false>;
+template <int W>
+void* betai_bf16_kernel_ptr_w(int lq2) {
+  return lq2 <= 1 ? (void*)beta_inverse_bf16x3_worklist_kernel<1, W> : (void*)beta_inverse_bf16x3_worklist_kernel<2, W>;
+}
+void* betai_bf16_kernel_ptr(int lq2, int w) {
+  return w == 1 ? betai_bf16_kernel_ptr_w<1>(lq2) : (w == 2 ? betai_bf16_kernel_ptr_w<2>(lq2) : betai_bf16_kernel_ptr_w<3>(lq2));
+}
+
+// workgroups of `threads` threads with `smem` bytes of LDS that one CU holds
+// of kernel f (0 if the runtime cannot tell)
+int wgs_per_cu(const void* f, int threads, size_t smem, int device) {
+  int max_lds = 0, n = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, smem) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
 }
 
 // the rings of an N = 256 group with the single-B plan's kernels (d: 0
@@ -406,14 +420,14 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
           const WorkItem* items = ms->d_betaf + r.begin;
           void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&out};
           e = bf ? hipLaunchKernel(betaf_bf16_kernel_ptr(r.cls), grid_of(r.n), dim3(XB_THREADS), args, XBF_SMEM, rs)
-                 : hipLaunchKernel(betaf_kernel_ptr<T>(r.cls, ms->kc), grid_of(r.n), dim3(FWD_THREADS), args,
+                 : hipLaunchKernel(betaf_kernel_ptr<T>(r.cls, ms->kc, r.w), grid_of(r.n), dim3(FWD_THREADS), args,
                                    betaf_smem<T>(r.cls, ms->kc), rs);
         } else {
           const WorkItem* items = ms->d_betai + r.begin;
           void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&in, (void*)&dir};
-          e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls, r.nar), grid_of(r.n), dim3(XB_THREADS), args,
+          e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls, r.w), grid_of(r.n), dim3(XB_THREADS), args,
                                    ms->smem_betai, rs)
-                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls, r.nar), grid_of(r.n), dim3(INV_THREADS), args,
+                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls, r.w), grid_of(r.n), dim3(INV_THREADS), args,
                                    ms->smem_betai, rs);
         }
         if (e != hipSuccess) return e;
@@ -458,11 +472,11 @@ hipError_t set_worklist_smem(su2_plan_s* pl) {
       ms->smem_betai > (size_t)max_lds)
     return hipErrorInvalidValue;
   for (const MixedState::Run& r : ms->runs_f)
-    if ((e = hipFuncSetAttribute(bf ? betaf_bf16_kernel_ptr(r.cls) : betaf_kernel_ptr<T>(r.cls, ms->kc),
+    if ((e = hipFuncSetAttribute(bf ? betaf_bf16_kernel_ptr(r.cls) : betaf_kernel_ptr<T>(r.cls, ms->kc, r.w),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
       return e;
   for (const MixedState::Run& r : ms->runs_i)
-    if ((e = hipFuncSetAttribute(bf ? betai_bf16_kernel_ptr(r.cls, r.nar) : betai_kernel_ptr<T>(r.cls, r.nar),
+    if ((e = hipFuncSetAttribute(bf ? betai_bf16_kernel_ptr(r.cls, r.w) : betai_kernel_ptr<T>(r.cls, r.w),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
       return e;
   for (int fwd = 0; fwd < 2; fwd++) {
@@ -583,24 +597,41 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
   };
   if ((e = upload(ringf, ms->d_ringf, &ms->n_ringf)) != hipSuccess) return hip_fail(e);
   if ((e = upload(ringg, ms->d_ringg, &ms->n_ringg)) != hipSuccess) return hip_fail(e);
-  // contraction lists: by class (largest first; wide inverse tiles before
-  // 16-signal ones), then by decreasing cost; one run per class
+  // contraction lists: by class (largest first), then by tile width where a
+  // class is split (widest first), then by decreasing cost; one run per class
+  // and width set
   auto upload_runs = [&](std::vector<std::pair<double, WorkItem>>& lst, WorkItem* dst, int* n,
                          std::vector<MixedState::Run>& runs, bool fwd) -> hipError_t {
     auto cls = [&](const WorkItem& w) { return fwd ? hg[w.g].rtmax : (bf ? hg[w.g].lq2 : hg[w.g].lq); };
-    auto nar = [&](const WorkItem& w) { return fwd ? 0 : hg[w.g].narrow_i; };
+    auto narrow = [&](const WorkItem& w) { return fwd ? (!bf && hg[w.g].narrow_f) : hg[w.g].narrow_i != 0; };
+    int present[17] = {0};  // per class: 1 = 16-signal tasks, 2 = widest
+    for (auto& x : lst) present[cls(x.second)] |= narrow(x.second) ? 1 : 2;
+    bool split[17] = {false};
+    for (int c = 1; c <= 16; c++) {
+      if (present[c] != 3) continue;
+      const void* both = fwd ? betaf_kernel_ptr<T>(c, ms->kc, 3) : (bf ? betai_bf16_kernel_ptr(c, 3) : betai_kernel_ptr<T>(c, 3));
+      const void* one = fwd ? betaf_kernel_ptr<T>(c, ms->kc, 1) : (bf ? betai_bf16_kernel_ptr(c, 1) : betai_kernel_ptr<T>(c, 1));
+      const int threads = fwd ? FWD_THREADS : (bf ? XB_THREADS : INV_THREADS);
+      const size_t smem = fwd ? betaf_smem<T>(c, ms->kc) : (bf ? XBI_SMEM : inverse_smem<T>());
+      const int nb = wgs_per_cu(both, threads, smem, pl->device), n1 = wgs_per_cu(one, threads, smem, pl->device);
+      split[c] = nb < 2 && n1 > nb;
+    }
+    auto wset = [&](const WorkItem& w) {
+      const int c = cls(w);
+      return present[c] == 3 && !split[c] ? 3 : (narrow(w) ? 1 : 2);
+    };
     std::stable_sort(lst.begin(), lst.end(), [&](const std::pair<double, WorkItem>& x,
                                                  const std::pair<double, WorkItem>& y) {
       const int cx = cls(x.second), cy = cls(y.second);
       if (cx != cy) return cx > cy;
-      const int nx = nar(x.second), ny = nar(y.second);
-      return nx != ny ? nx < ny : x.first > y.first;
+      const int wx = wset(x.second), wy = wset(y.second);
+      return wx != wy ? wx > wy : x.first > y.first;
     });
     runs.clear();
     std::vector<WorkItem> v;
     for (auto& x : lst) {
-      const int c = cls(x.second), a = nar(x.second);
-      if (runs.empty() || runs.back().cls != c || runs.back().nar != a) runs.push_back({c, a, (int)v.size(), 0});
+      const int c = cls(x.second), a = wset(x.second);
+      if (runs.empty() || runs.back().cls != c || runs.back().w != a) runs.push_back({c, a, (int)v.size(), 0});
       runs.back().n++;
       v.push_back(x.second);
     }
