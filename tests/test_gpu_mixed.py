@@ -324,6 +324,34 @@ def test_pinned_tile_shapes_bitwise_equal_default(dtype, shapes):
         assert np.array_equal(_host(a), _host(b)), fn
 
 
+# 65-128 degrees in both tile widths: 17 signals of B = 72 (32-signal tiles)
+# and 2 of B = 96 (16-signal tiles).  Both bodies in one kernel would take 195
+# VGPRs in the FP32 forward, so each width is a launch of its own there (and
+# in the inverse), the class being split in two runs.
+SPLIT_BS = [72] * 17 + [96] * 2
+
+
+def test_split_width_runs_bitwise_equal_single_width():
+    """The default tile shapes of SPLIT_BS (one run per width in the classes
+    of 65-128 degrees) give the bits of every group in one width, 16 or 32
+    signals, in all three directions."""
+    xs, cs = _mixed_inputs(SPLIT_BS, "c64", 11)
+    x = _dev(np.concatenate(xs))
+    c = _dev(np.concatenate(cs))
+    with _env(SU2_AUTOTUNE="0"):
+        ref = su2.MixedPlan(SPLIT_BS, "c64")
+    assert [tuple(s) for s in ref.tile_shapes()] == [(72, 32, 32, 4), (96, 16, 16, 4)]
+    want = [_host(ref.forward(x)), _host(ref.inverse(c)), _host(ref.adjoint(c))]
+    ref.close()
+    for shapes in ("4,16,16", "4,32,32"):
+        with _env(SU2_AUTOTUNE="0", SU2_TILE_SHAPES=shapes):
+            mp = su2.MixedPlan(SPLIT_BS, "c64")
+        got = [_host(mp.forward(x)), _host(mp.inverse(c)), _host(mp.adjoint(c))]
+        mp.close()
+        for name, a, b in zip(("forward", "inverse", "adjoint"), got, want):
+            assert np.array_equal(a, b), (shapes, name)
+
+
 def test_autotuned_tile_shapes_valid_and_cached(tmp_path):
     """The search picks a valid shape per group and changes no result; a fresh
     process reads the choice back from the disk cache instead of searching."""
