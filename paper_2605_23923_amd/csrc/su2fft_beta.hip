@@ -453,7 +453,7 @@ __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coe
   };
   fetch_a(av, 0);  // in flight while the coefficients are gathered
 
-  // B operands: the scaled coefficients of the wave's two pairs, gathered
+  // B operands: the scaled coefficients of the wave's WPP pairs, gathered
   // through LDS (CoefRound) in rounds of 8 degrees of all 16 pairs
   constexpr int J = 4 * LQ;  // degrees held per pair
   typedef CoefRound<T, BT, NTH> CR;
