@@ -187,7 +187,9 @@ __global__ __launch_bounds__(S4_NT, 4) void ring_forward_sliced4(const cpx<float
   const TileSlot sl = contraction_slot(blockIdx.x, p.batch * N, S4_SLC);
   if (!sl.valid) return;
   const int ring = sl.tile, s = sl.bt;
-  const int b = ring / N, k = ring - b * N;
+  // rings node-major over the signals (as the N <= 128 forward rings): the
+  // rings in flight together write whole rows of each spectra tile
+  const int k = ring / p.batch, b = ring - k * p.batch;
   const size_t x0 = ring_offset(p.soff, b, N) + (size_t)k * N * N;
   for (int i = t; i < 2 * N; i += S4_NT) tws[i] = p.tw[i];
   __syncthreads();
