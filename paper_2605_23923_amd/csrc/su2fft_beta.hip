@@ -406,6 +406,12 @@ constexpr size_t inverse_smem() { return (size_t)16 * InvStage<T>::NRS * sizeof(
 // lets FP64 with 17-32 degrees keep 16 waves per CU instead of 8.
 template <int WPP>
 constexpr int inverse_threads() { return 64 * PT / WPP; }
+// pairs per wave of the inverse for a type and degree-group count: one for
+// FP64 with 17-32 degrees (B = 33-64: 110 instead of 176 VGPRs, 16 waves per
+// CU instead of 8, B = 64 batch 32 0.187 -> 0.167 ms; with fewer degrees the
+// 8-wave form is as fast or faster), else two
+template <class T>
+constexpr int inverse_wpp(int lq) { return sizeof(T) == 8 && lq == 8 ? 1 : 2; }
 
 template <class T, int LQ, int BT = BetaCfg<T>::BT, int WPP = 2>
 __device__ __forceinline__ void beta_inverse_body(const cpx<T>* __restrict__ coeffs, cpx<T>* __restrict__ S,
@@ -616,12 +622,9 @@ hipError_t launch_beta_inverse(const BetaParams<T>& p, const cpx<T>* coeffs, cpx
   const size_t smem = inverse_smem<T>();
   const int lq = beta_lq(p.B);
   hipError_t e;
-  // one pair per wave for FP64 with 17-32 degrees (B = 33-64): 110 instead of
-  // 176 VGPRs, 16 waves per CU instead of 8 (B = 64 batch 32: 0.187 -> 0.167
-  // ms; with fewer degrees the 8-wave form is as fast or faster)
 #define SU2_INV_CASE(Q, BTC)                                                                             \
   if (lq == Q && bt == BTC) {                                                                            \
-    constexpr int W = (sizeof(T) == 8 && Q == 8) ? 1 : 2;                                                \
+    constexpr int W = inverse_wpp<T>(Q);                                                                 \
     if ((e = set_smem(beta_inverse_kernel<T, Q, BTC, W>, smem)) != hipSuccess) return e;                 \
     hipLaunchKernelGGL((beta_inverse_kernel<T, Q, BTC, W>), grid, dim3(inverse_threads<W>()), smem, s, coeffs, \
                        S, p);                                                                            \

@@ -142,9 +142,9 @@ __global__ __launch_bounds__(FWD_THREADS) void beta_forward_worklist_kernel(cons
 }
 
 template <class T, int LQC, int W>
-__global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(const WorkItem* __restrict__ items, int n,
-                                                                            const GroupDev<T>* __restrict__ groups,
-                                                                            const cpx<T>* __restrict__ coeffs, int dir) {
+__global__ __launch_bounds__(inverse_threads<inverse_wpp<T>(LQC)>()) void beta_inverse_worklist_kernel(
+    const WorkItem* __restrict__ items, int n, const GroupDev<T>* __restrict__ groups, const cpx<T>* __restrict__ coeffs,
+    int dir) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const WorkItem w = items[it];
@@ -152,10 +152,11 @@ __global__ __launch_bounds__(INV_THREADS) void beta_inverse_worklist_kernel(cons
     asm volatile("" : "+v"(t));   // keep per-thread set-up inside the loop (see the ring work list)
     const GroupDev<T>& g = groups[w.g];
     if (g.lq == LQC) {
+      constexpr int WPP = inverse_wpp<T>(LQC);
       if constexpr ((W & 1) != 0)
-        if (g.narrow_i) beta_inverse_body<T, LQC, 16>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
+        if (g.narrow_i) beta_inverse_body<T, LQC, 16, WPP>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
       if constexpr ((W & 2) != 0)
-        if (!g.narrow_i) beta_inverse_body<T, LQC>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
+        if (!g.narrow_i) beta_inverse_body<T, LQC, BetaCfg<T>::BT, WPP>(coeffs, g.S, g.bp[dir], w.a, w.b, smem, t);
     }
     __syncthreads();
   }
@@ -307,6 +308,12 @@ void* betai_kernel_ptr_w(int lq) {
   if (lq <= 8) return (void*)beta_inverse_worklist_kernel<T, 8, W>;
   return (void*)beta_inverse_worklist_kernel<T, 16, W>;
 }
+// threads of the inverse work-list kernel of degree class lq (the class's
+// kernel is built for exactly that class, lq in {2, 4, 8, 16})
+template <class T>
+int betai_threads(int lq) {
+  return inverse_wpp<T>(lq) == 1 ? inverse_threads<1>() : inverse_threads<2>();
+}
 template <class T>
 void* betai_kernel_ptr(int lq, int w) {
   if constexpr (BetaCfg<T>::BT == 16) return betai_kernel_ptr_w<T, 2>(lq);  // one width
@@ -427,7 +434,7 @@ hipError_t enqueue(su2_plan_s* pl, int which, int dir, const void* in, void* out
           void* args[] = {(void*)&items, (void*)&r.n, (void*)&g, (void*)&in, (void*)&dir};
           e = bf ? hipLaunchKernel(betai_bf16_kernel_ptr(r.cls, r.w), grid_of(r.n), dim3(XB_THREADS), args,
                                    ms->smem_betai, rs)
-                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls, r.w), grid_of(r.n), dim3(INV_THREADS), args,
+                 : hipLaunchKernel(betai_kernel_ptr<T>(r.cls, r.w), grid_of(r.n), dim3(betai_threads<T>(r.cls)), args,
                                    ms->smem_betai, rs);
         }
         if (e != hipSuccess) return e;
@@ -611,7 +618,7 @@ su2_status_t build_worklists(su2_plan_s* pl, int only_group = -1) {
       if (present[c] != 3) continue;
       const void* both = fwd ? betaf_kernel_ptr<T>(c, ms->kc, 3) : (bf ? betai_bf16_kernel_ptr(c, 3) : betai_kernel_ptr<T>(c, 3));
       const void* one = fwd ? betaf_kernel_ptr<T>(c, ms->kc, 1) : (bf ? betai_bf16_kernel_ptr(c, 1) : betai_kernel_ptr<T>(c, 1));
-      const int threads = fwd ? FWD_THREADS : (bf ? XB_THREADS : INV_THREADS);
+      const int threads = fwd ? FWD_THREADS : (bf ? XB_THREADS : betai_threads<T>(c));
       const size_t smem = fwd ? betaf_smem<T>(c, ms->kc) : (bf ? XBI_SMEM : inverse_smem<T>());
       const int nb = wgs_per_cu(both, threads, smem, pl->device), n1 = wgs_per_cu(one, threads, smem, pl->device);
       split[c] = nb < 2 && n1 > nb;
